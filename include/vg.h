@@ -1,0 +1,167 @@
+/*
+ * vg.h -- C ABI of the MI355X (gfx950) voxel-grid library: one dense depth
+ * frame -> a robot-centred uint8 grid of occupied / free / unknown voxels.
+ *
+ * Method: Toumieh & Lambert, "GPU Accelerated Voxel Grid Generation for fast
+ * MAV Exploration" (arXiv 2112.13169), Sec. IV:
+ *   step 1 voxel grid setup (Sec. IV-A)        -> vg_create_grid
+ *   steps 2-4 populate occupied (Alg. 1), ray-trace to free (Alg. 2) and
+ *   update the local grid (Alg. 3)             -> vg_integrate_frame
+ *   step 5 shift the local grid (Sec. IV-E)    -> vg_shift_grid
+ * Argument names follow the paper's nomenclature (Table I).
+ *
+ * Conventions for every entry point:
+ *  - Ownership: the caller owns every device buffer (the local grid, its spare
+ *    copy, the scratch workspace, depth images).  The library never allocates
+ *    or frees device memory; a vg_grid handle owns host metadata only.
+ *  - Asynchrony: device work is enqueued on `stream` (a hipStream_t; NULL is
+ *    the default stream) and nothing blocks the host, except where stated.
+ *    One handle must not be used from two streams at once; distinct handles
+ *    are independent.
+ *  - Errors: argument errors are detected before any device work is enqueued,
+ *    return VG_ERR_ARG and leave the grid unchanged.  HIP launch / copy errors
+ *    return VG_ERR_HIP.  Nothing throws across the ABI.
+ *  - Layout: grids are uint8[grid_size_z][grid_size_y][grid_size_x] with the
+ *    paper's linear index idx = x + y*grid_size_x + z*grid_size_x*grid_size_y
+ *    (Sec. IV-D); grid axes are aligned with the world (ENU) frame.
+ *  - Voxel values: VG_UNKNOWN 0, VG_FREE 1, VG_OCCUPIED 2.  Other byte values
+ *    written by vg_write_grid are kept until a frame overwrites them.
+ */
+#ifndef VG_H
+#define VG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct vg_grid vg_grid;
+typedef int32_t vg_status;
+
+#define VG_OK 0
+#define VG_ERR_ARG (-1)    /* invalid argument; nothing was enqueued          */
+#define VG_ERR_HIP (-2)    /* a HIP runtime call failed                       */
+#define VG_ERR_BUDGET (-3) /* the scratch workspace is too small              */
+#define VG_ERR_STATE (-4)  /* handle used on a different device than created  */
+
+#define VG_UNKNOWN 0
+#define VG_FREE 1
+#define VG_OCCUPIED 2
+
+#define VG_PINHOLE 0  /* z-depth image (depth along the optical axis)      */
+#define VG_SPINNING 1 /* range image of a spinning sensor, 360 deg azimuth */
+
+/* T^w_c: camera -> world.  R row-major (columns are the camera axes in the
+ * world frame), t = camera centre in metres.  Pinhole camera frame: z along
+ * the optical axis, x right (across fov_x), y down (across fov_y).  Spinning
+ * sensor frame: z up.  All 12 entries must be finite. */
+typedef struct vg_pose {
+    float R[9];
+    float t[3];
+} vg_pose;
+
+/* Sensor model.
+ * VG_PINHOLE: pixel (u, v) looks along ((u - cx) / fx, (v - cy) / fy, 1); the
+ *   image holds z-depth in metres.  fov_x / fov_y (radians, in (0, pi)) set
+ *   the ray fan of Sec. IV-C.
+ * VG_SPINNING: column u has azimuth cos/sin col_tab[2u], col_tab[2u+1]; row v
+ *   has elevation cos/sin row_tab[2v], row_tab[2v+1] (device pointers,
+ *   float32); the image holds range in metres; fov_y is the full vertical
+ *   field of view (radians) that bounds the ray fan; fov_x, fx..cy unused.
+ * Image sizes are at most 65535 x 65535.
+ * A pixel is a measurement iff depth_min <= value <= depth (NaN is not).
+ * `depth` is also the range the fan clears: vox_depth = round(depth/vox_size). */
+typedef struct vg_sensor {
+    int32_t kind;
+    int32_t width, height;
+    int32_t reserved;
+    double fx, fy, cx, cy;
+    double fov_x, fov_y;
+    float depth_min, depth;
+    const float *col_tab;
+    const float *row_tab;
+} vg_sensor;
+
+/* Ray-fan sizes of Sec. IV-C for a sensor on a grid of voxel size vox_size:
+ * out[0] = vox_depth, out[1] = half width, out[2] = half height (pinhole; the
+ * fan is (2*out[1]+1) x (2*out[2]+1) rays), out[3] = number of rays.
+ * Host-only; returns VG_ERR_ARG when the sizes are out of range
+ * (vox_depth > 16384, half sizes > 16384). */
+vg_status vg_fan_sizes(const vg_sensor *sensor, float vox_size, int64_t out[4]);
+
+/* Bytes of device scratch a grid of this size needs to integrate frames from
+ * sensors with up to `max_rays` rays (vg_fan_sizes out[3]).  Host-only. */
+size_t vg_scratch_bytes(int32_t grid_size_x, int32_t grid_size_y, int32_t grid_size_z,
+                        int64_t max_rays);
+
+/* Step 1 (Sec. IV-A): bind caller buffers to a new grid and set every voxel
+ * of loc_grid to unknown (enqueued on `stream`).
+ *   loc_grid, loc_spare: device, grid_size_x*y*z bytes each, distinct.  The
+ *     spare buffer receives shifted grids (vg_shift_grid swaps the two).
+ *   scratch: device, scratch_bytes >= vg_scratch_bytes(..., max_rays), 256-byte
+ *     aligned; it is cleared here and owned by the grid until destroyed.
+ *   origin_w: world position (m) of the grid corner (voxel (0,0,0)'s minimum
+ *     corner); vox_size > 0 m; vox_inf in [0, 64] voxels of inflation.
+ *   Dimensions in [1, 65535] with grid_size_x*y*z < 2^31.
+ * On success *out receives the handle. */
+vg_status vg_create_grid(int32_t grid_size_x, int32_t grid_size_y, int32_t grid_size_z,
+                         float vox_size, const float origin_w[3], int32_t vox_inf,
+                         uint8_t *loc_grid, uint8_t *loc_spare, void *scratch,
+                         size_t scratch_bytes, void *stream, vg_grid **out);
+
+/* Steps 2-4 (Alg. 1, 2, 3) for one frame, enqueued on `stream`:
+ *   depth: device, sensor->height rows of sensor->width float32, rows
+ *     row_pitch_bytes apart (>= 4*width, multiple of 4).
+ *   T_w_c: camera pose for this frame (host struct, read before returning).
+ * The frame's occupied voxels (vox_inf cubes around the measured points,
+ * clipped to the grid) become VG_OCCUPIED; voxels the ray fan crosses before
+ * its first occupied voxel become VG_FREE unless some ray crosses them after
+ * a hit, in which case they become VG_UNKNOWN; every other voxel keeps its
+ * value.  Returns VG_ERR_BUDGET if the fan needs more rays than the scratch
+ * workspace was sized for. */
+vg_status vg_integrate_frame(vg_grid *g, const float *depth, int64_t row_pitch_bytes,
+                             const vg_sensor *sensor, const vg_pose *T_w_c, void *stream);
+
+/* Same as vg_integrate_frame for a dense point cloud (the paper's stereo input
+ * form, Sec. IV): `points` is device float32[n_points][3] in the camera frame;
+ * an entry is a measurement iff all three coordinates are finite.  The ray fan
+ * is the pinhole fan of sensor->fov_x, fov_y and depth (kind must be
+ * VG_PINHOLE; width, height, fx..cy are ignored). */
+vg_status vg_integrate_points(vg_grid *g, const float *points, int64_t n_points,
+                              const vg_sensor *sensor, const vg_pose *T_w_c, void *stream);
+
+/* Step 5 (Sec. IV-E): shift the grid content by an integer voxel offset:
+ * new[x,y,z] = old[x+dx, y+dy, z+dz] where that lies inside, else unknown; the
+ * grid origin moves by (dx,dy,dz)*vox_size (kept as an integer count so it
+ * never drifts).  Enqueued on `stream`; (0,0,0) does nothing. */
+vg_status vg_shift_grid(vg_grid *g, int32_t dx, int32_t dy, int32_t dz, void *stream);
+
+/* Offset that re-centres the grid on a camera at t_w_c (metres):
+ * delta = floor((t_w_c - origin_w) / vox_size) - grid_size / 2.  Host-only. */
+vg_status vg_center_offset(const vg_grid *g, const float t_w_c[3], int32_t delta_out[3]);
+
+/* Current grid origin in the world frame (host-only). */
+vg_status vg_grid_origin(const vg_grid *g, float origin_w_out[3]);
+
+/* Copy the local grid (linear layout) to dst: device memory if dst_is_device,
+ * else host memory; enqueued on `stream` -- synchronise the stream before
+ * reading a host destination. */
+vg_status vg_read_grid(const vg_grid *g, uint8_t *dst, int32_t dst_is_device, void *stream);
+
+/* Overwrite the local grid (restore a checkpoint) from src (linear layout). */
+vg_status vg_write_grid(vg_grid *g, const uint8_t *src, int32_t src_is_device, void *stream);
+
+/* Release the handle (host metadata only; caller buffers are untouched).
+ * The caller must make sure no work using the handle is still queued if it
+ * frees the buffers afterwards. */
+vg_status vg_destroy_grid(vg_grid *g);
+
+/* Static description of a status code. */
+const char *vg_status_str(vg_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

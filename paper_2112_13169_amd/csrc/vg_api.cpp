@@ -1,0 +1,504 @@
+// vg_api.cpp -- host side of the C ABI declared in include/vg.h:
+// argument validation, the host-computed per-frame constants (T^v_c, the ray
+// fan sizes of Sec. IV-C, the camera voxel), scratch layout and launches.
+#include "../../include/vg.h"
+#include "vg_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#pragma clang fp contract(off)
+
+using namespace vg;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int32_t kMaxFan = 16384;
+constexpr size_t kHzBytes = (size_t)8 * kMaxFan * sizeof(int32_t);
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Scratch layout (all offsets 256-aligned):
+//   [0, 256)               parked-ray counter
+//   [256, 256+N')          occupancy stamps, one byte per voxel
+//   [.., + kHzBytes)       spinning fan: half height per ring column
+//   [.., end)              parked rays, 32 bytes each
+struct Layout {
+    size_t counter, occ, hz, parked, fixed;
+};
+
+Layout layout_for(int64_t voxels)
+{
+    Layout l;
+    l.counter = 0;
+    l.occ = kAlign;
+    l.hz = l.occ + align_up((size_t)voxels);
+    l.parked = l.hz + kHzBytes;
+    l.fixed = l.parked;
+    return l;
+}
+
+double round_half_away(double v) { return v < 0.0 ? -std::floor(-v + 0.5) : std::floor(v + 0.5); }
+
+struct Fan {
+    int32_t vd = 0, hw = 0, hh = 0;   // hh: largest half height for spinning fans
+    int64_t rays = 0;
+    std::vector<int32_t> hz;          // spinning only
+};
+
+// Sec. IV-C: vox_depth = depth / vox_size rounded; the half width / height of
+// the fan is tan(fov/2) * vox_depth rounded, so the full sizes are odd.  A
+// spinning fan (no pinhole fov) uses every lattice column on the square ring
+// of half side vox_depth, each as high as tan(vfov/2) times its distance.
+bool fan_for(const vg_sensor &s, float vox_size, Fan &f)
+{
+    double vd = round_half_away((double)s.depth / (double)vox_size);
+    if (!(vd >= 1.0 && vd <= kMaxFan))
+        return false;
+    f.vd = (int32_t)vd;
+    if (s.kind == VG_SPINNING) {
+        if (!(s.fov_y > 0.0 && s.fov_y < 3.14159))
+            return false;
+        const double thv = std::tan(s.fov_y / 2.0);
+        f.hz.resize((size_t)8 * f.vd);
+        f.rays = 0;
+        f.hh = 0;
+        f.hw = 0;
+        for (int32_t c = 0; c < 8 * f.vd; ++c) {
+            int32_t side = c / (2 * f.vd), k = c % (2 * f.vd), x, y;
+            if (side == 0) {
+                x = f.vd;
+                y = -f.vd + 1 + k;
+            } else if (side == 1) {
+                x = f.vd - 1 - k;
+                y = f.vd;
+            } else if (side == 2) {
+                x = -f.vd;
+                y = f.vd - 1 - k;
+            } else {
+                x = -f.vd + 1 + k;
+                y = -f.vd;
+            }
+            double h = round_half_away(thv * std::sqrt((double)x * x + (double)y * y));
+            if (!(h >= 0.0 && h <= kMaxFan))
+                return false;
+            f.hz[c] = (int32_t)h;
+            if (f.hz[c] > f.hh)
+                f.hh = f.hz[c];
+            f.rays += 2 * (int64_t)f.hz[c] + 1;
+        }
+        return true;
+    }
+    if (!(s.fov_x > 0.0 && s.fov_x < 3.14159 && s.fov_y > 0.0 && s.fov_y < 3.14159))
+        return false;
+    double hw = round_half_away(std::tan(s.fov_x / 2.0) * vd);
+    double hh = round_half_away(std::tan(s.fov_y / 2.0) * vd);
+    if (!(hw >= 0.0 && hw <= kMaxFan && hh >= 0.0 && hh <= kMaxFan))
+        return false;
+    f.hw = (int32_t)hw;
+    f.hh = (int32_t)hh;
+    f.rays = (2 * (int64_t)f.hw + 1) * (2 * (int64_t)f.hh + 1);
+    return true;
+}
+
+bool finite_pose(const vg_pose *T)
+{
+    for (float v : T->R)
+        if (!std::isfinite(v))
+            return false;
+    for (float v : T->t)
+        if (!std::isfinite(v))
+            return false;
+    return true;
+}
+
+}  // namespace
+
+struct vg_grid {
+    int32_t n[3];
+    float s;
+    float base[3];
+    int32_t shift[3];
+    int32_t r;
+    uint8_t *loc, *spare;
+    uint8_t *scratch;
+    size_t scratch_bytes;
+    Layout lay;
+    uint32_t epoch;          // stamp of the last frame, 0 = none yet
+    int device;
+    // spinning fan table currently in scratch
+    int32_t hz_vd = 0;
+    double hz_fov = -1.0;
+    std::vector<int32_t> hz_host;   // kept alive for the asynchronous upload
+};
+
+namespace {
+
+vg_status hip_status(hipError_t e) { return e == hipSuccess ? VG_OK : VG_ERR_HIP; }
+
+bool same_device(const vg_grid *g)
+{
+    int d = -1;
+    return hipGetDevice(&d) == hipSuccess && d == g->device;
+}
+
+// Origin after integer shifts: base + (float)shift * vox_size (no drift).
+void current_origin(const vg_grid *g, float o[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        float off = (float)g->shift[a] * g->s;
+        o[a] = g->base[a] + off;
+    }
+}
+
+bool valid_sensor(const vg_sensor *s)
+{
+    if (!s)
+        return false;
+    if (s->kind != VG_PINHOLE && s->kind != VG_SPINNING)
+        return false;
+    if (s->width < 0 || s->height < 0 || s->width > 65535 || s->height > 65535)
+        return false;
+    if (!std::isfinite(s->depth) || !(s->depth > 0.0f) || std::isnan(s->depth_min))
+        return false;
+    if (s->kind == VG_PINHOLE) {
+        if (!(std::isfinite(s->fx) && std::isfinite(s->fy) && s->fx != 0.0 && s->fy != 0.0 &&
+              std::isfinite(s->cx) && std::isfinite(s->cy)))
+            return false;
+    } else if (s->width > 0 && s->height > 0 && (!s->col_tab || !s->row_tab)) {
+        return false;
+    }
+    return true;
+}
+
+// Common part of steps 2-4: per-frame constants, stamp, launches.
+vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_floats, int32_t W,
+                    int32_t H, const vg_sensor *sensor, const vg_pose *T, hipStream_t st)
+{
+    Fan fan;
+    if (!fan_for(*sensor, g->s, fan))
+        return VG_ERR_ARG;
+    if ((W > 0 && H > 0) && !data)
+        return VG_ERR_ARG;
+
+    // T^v_c = T^v_w T^w_c: the grid frame is the world frame translated by
+    // -origin (axes aligned), so R is unchanged and t^v = t^w_c - origin.
+    float origin[3], tv[3], o[3];
+    int32_t v0[3];
+    current_origin(g, origin);
+    for (int a = 0; a < 3; ++a) {
+        tv[a] = T->t[a] - origin[a];
+        o[a] = tv[a] / g->s;   // camera position in voxel units
+        if (!(std::fabs(o[a]) < 16777216.0f))
+            return VG_ERR_ARG;
+        v0[a] = (int32_t)std::floor(o[a]);
+    }
+
+    size_t cap = (g->scratch_bytes - g->lay.fixed) / sizeof(ParkedRay);
+    if ((int64_t)cap < fan.rays)
+        return VG_ERR_BUDGET;
+    if (!same_device(g))
+        return VG_ERR_STATE;
+
+    // Per-frame occupancy stamp 1..255; the plane is cleared when it wraps.
+    hipError_t e = hipSuccess;
+    if (g->epoch == 255) {
+        e = launch_fill(g->scratch + g->lay.occ, 0, (size_t)g->n[0] * g->n[1] * g->n[2], st);
+        if (e != hipSuccess)
+            return VG_ERR_HIP;
+        g->epoch = 0;
+    }
+    const uint32_t epoch = g->epoch + 1;
+
+    if (kind == kSpinning && (g->hz_vd != fan.vd || g->hz_fov != sensor->fov_y)) {
+        g->hz_host = fan.hz;
+        e = hipMemcpyAsync(g->scratch + g->lay.hz, g->hz_host.data(),
+                           g->hz_host.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
+        // The table changes only with the sensor; wait so the host copy can
+        // be replaced safely next time.
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(st);
+        if (e != hipSuccess)
+            return VG_ERR_HIP;
+        g->hz_vd = fan.vd;
+        g->hz_fov = sensor->fov_y;
+    }
+
+    uint32_t *counter = reinterpret_cast<uint32_t *>(g->scratch + g->lay.counter);
+    OccParams op;
+    std::memcpy(op.R, T->R, sizeof op.R);
+    std::memcpy(op.tv, tv, sizeof op.tv);
+    op.s = g->s;
+    std::memcpy(op.n, g->n, sizeof op.n);
+    op.r = g->r;
+    op.kind = kind;
+    op.W = W;
+    op.H = H;
+    op.pitch = pitch_floats;
+    op.fx = sensor->fx;
+    op.fy = sensor->fy;
+    op.cx = sensor->cx;
+    op.cy = sensor->cy;
+    op.dmin = sensor->depth_min;
+    op.dmax = sensor->depth;
+    op.img = data;
+    op.col_tab = sensor->col_tab;
+    op.row_tab = sensor->row_tab;
+    op.loc = g->loc;
+    op.occ = g->scratch + g->lay.occ;
+    op.parked_count = counter;
+    op.epoch = epoch;
+    e = launch_occupied(op, st);
+    if (e != hipSuccess)
+        return VG_ERR_HIP;
+
+    RayParams rp;
+    std::memcpy(rp.R, T->R, sizeof rp.R);
+    std::memcpy(rp.o, o, sizeof rp.o);
+    std::memcpy(rp.v0, v0, sizeof rp.v0);
+    std::memcpy(rp.n, g->n, sizeof rp.n);
+    rp.kind = kind == kSpinning ? kSpinning : kPinhole;
+    rp.vd = fan.vd;
+    rp.hw = fan.hw;
+    rp.hh = fan.hh;
+    if (kind == kSpinning) {
+        rp.na = 8 * fan.vd;
+        rp.nb = 2 * fan.hh + 1;
+    } else {
+        rp.na = 2 * fan.hw + 1;
+        rp.nb = 2 * fan.hh + 1;
+    }
+    rp.tiles_a = (rp.na + 7) / 8;
+    int64_t tiles = (int64_t)rp.tiles_a * ((rp.nb + 7) / 8);
+    if (tiles * 64 > (int64_t)0x7fffffff)
+        return VG_ERR_ARG;
+    rp.tiles = (int32_t)tiles;
+    rp.hz = reinterpret_cast<const int32_t *>(g->scratch + g->lay.hz);
+    rp.loc = g->loc;
+    rp.occ = g->scratch + g->lay.occ;
+    rp.parked = reinterpret_cast<ParkedRay *>(g->scratch + g->lay.parked);
+    rp.parked_count = counter;
+    rp.parked_cap = (uint32_t)std::min<size_t>(cap, 0xffffffffu);
+    rp.epoch = epoch;
+    e = launch_rays(rp, st);
+    if (e != hipSuccess)
+        return VG_ERR_HIP;
+    g->epoch = epoch;
+    return VG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+vg_status vg_fan_sizes(const vg_sensor *sensor, float vox_size, int64_t out[4])
+{
+    if (!valid_sensor(sensor) || !out || !(vox_size > 0.0f) || !std::isfinite(vox_size))
+        return VG_ERR_ARG;
+    Fan f;
+    if (!fan_for(*sensor, vox_size, f))
+        return VG_ERR_ARG;
+    out[0] = f.vd;
+    out[1] = f.hw;
+    out[2] = f.hh;
+    out[3] = f.rays;
+    return VG_OK;
+}
+
+size_t vg_scratch_bytes(int32_t gx, int32_t gy, int32_t gz, int64_t max_rays)
+{
+    if (gx < 1 || gy < 1 || gz < 1 || max_rays < 0)
+        return 0;
+    int64_t n = (int64_t)gx * gy * gz;
+    if (n >= ((int64_t)1 << 31))
+        return 0;
+    return layout_for(n).fixed + align_up((size_t)max_rays * sizeof(ParkedRay));
+}
+
+vg_status vg_create_grid(int32_t gx, int32_t gy, int32_t gz, float vox_size,
+                         const float origin_w[3], int32_t vox_inf, uint8_t *loc_grid,
+                         uint8_t *loc_spare, void *scratch, size_t scratch_bytes, void *stream,
+                         vg_grid **out)
+{
+    if (!out)
+        return VG_ERR_ARG;
+    *out = nullptr;
+    if (gx < 1 || gy < 1 || gz < 1 || gx > 65535 || gy > 65535 || gz > 65535 ||
+        (int64_t)gx * gy * gz >= ((int64_t)1 << 31))
+        return VG_ERR_ARG;
+    if (!(vox_size > 0.0f) || !std::isfinite(vox_size) || vox_inf < 0 || vox_inf > 64)
+        return VG_ERR_ARG;
+    if (!origin_w || !std::isfinite(origin_w[0]) || !std::isfinite(origin_w[1]) ||
+        !std::isfinite(origin_w[2]))
+        return VG_ERR_ARG;
+    if (!loc_grid || !loc_spare || loc_grid == loc_spare || !scratch ||
+        ((uintptr_t)scratch % kAlign) != 0)
+        return VG_ERR_ARG;
+    const int64_t n = (int64_t)gx * gy * gz;
+    Layout lay = layout_for(n);
+    if (scratch_bytes < lay.fixed)
+        return VG_ERR_BUDGET;
+
+    vg_grid *g = new (std::nothrow) vg_grid;
+    if (!g)
+        return VG_ERR_ARG;
+    g->n[0] = gx;
+    g->n[1] = gy;
+    g->n[2] = gz;
+    g->s = vox_size;
+    for (int a = 0; a < 3; ++a) {
+        g->base[a] = origin_w[a];
+        g->shift[a] = 0;
+    }
+    g->r = vox_inf;
+    g->loc = loc_grid;
+    g->spare = loc_spare;
+    g->scratch = static_cast<uint8_t *>(scratch);
+    g->scratch_bytes = scratch_bytes;
+    g->lay = lay;
+    g->epoch = 0;
+    if (hipGetDevice(&g->device) != hipSuccess) {
+        delete g;
+        return VG_ERR_HIP;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    // Step 1: every voxel of the local grid starts unknown; stamps start clear.
+    if (launch_fill(loc_grid, VG_UNKNOWN, (size_t)n, st) != hipSuccess ||
+        launch_fill(scratch, 0, lay.fixed, st) != hipSuccess) {
+        delete g;
+        return VG_ERR_HIP;
+    }
+    *out = g;
+    return VG_OK;
+}
+
+vg_status vg_integrate_frame(vg_grid *g, const float *depth, int64_t row_pitch_bytes,
+                             const vg_sensor *sensor, const vg_pose *T_w_c, void *stream)
+{
+    if (!g || !valid_sensor(sensor) || !T_w_c || !finite_pose(T_w_c))
+        return VG_ERR_ARG;
+    if (row_pitch_bytes % 4 != 0 || row_pitch_bytes < 4 * (int64_t)sensor->width)
+        return VG_ERR_ARG;
+    int kind = sensor->kind == VG_SPINNING ? kSpinning : kPinhole;
+    return integrate(g, kind, depth, row_pitch_bytes / 4, sensor->width, sensor->height, sensor,
+                     T_w_c, static_cast<hipStream_t>(stream));
+}
+
+vg_status vg_integrate_points(vg_grid *g, const float *points, int64_t n_points,
+                              const vg_sensor *sensor, const vg_pose *T_w_c, void *stream)
+{
+    if (!g || !valid_sensor(sensor) || sensor->kind != VG_PINHOLE || !T_w_c ||
+        !finite_pose(T_w_c) || n_points < 0 || n_points > 0x7fffffff)
+        return VG_ERR_ARG;
+    return integrate(g, kPoints, points, 0, (int32_t)n_points, 1, sensor, T_w_c,
+                     static_cast<hipStream_t>(stream));
+}
+
+vg_status vg_shift_grid(vg_grid *g, int32_t dx, int32_t dy, int32_t dz, void *stream)
+{
+    if (!g)
+        return VG_ERR_ARG;
+    const int32_t d[3] = {dx, dy, dz};
+    for (int a = 0; a < 3; ++a) {
+        int64_t s = (int64_t)g->shift[a] + d[a];
+        if (s > (1 << 24) || s < -(1 << 24))
+            return VG_ERR_ARG;
+    }
+    if (dx == 0 && dy == 0 && dz == 0)
+        return VG_OK;
+    if (!same_device(g))
+        return VG_ERR_STATE;
+    hipError_t e = launch_shift(g->loc, g->spare, g->n, d, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return VG_ERR_HIP;
+    uint8_t *t = g->loc;
+    g->loc = g->spare;
+    g->spare = t;
+    for (int a = 0; a < 3; ++a)
+        g->shift[a] += d[a];
+    return VG_OK;
+}
+
+vg_status vg_center_offset(const vg_grid *g, const float t_w_c[3], int32_t delta_out[3])
+{
+    if (!g || !t_w_c || !delta_out)
+        return VG_ERR_ARG;
+    float origin[3];
+    current_origin(g, origin);
+    int32_t d[3];
+    for (int a = 0; a < 3; ++a) {
+        if (!std::isfinite(t_w_c[a]))
+            return VG_ERR_ARG;
+        float rel = t_w_c[a] - origin[a];
+        float c = std::floor(rel / g->s);
+        if (!(std::fabs(c) < 16777216.0f))
+            return VG_ERR_ARG;
+        d[a] = (int32_t)c - g->n[a] / 2;
+    }
+    for (int a = 0; a < 3; ++a)
+        delta_out[a] = d[a];
+    return VG_OK;
+}
+
+vg_status vg_grid_origin(const vg_grid *g, float origin_w_out[3])
+{
+    if (!g || !origin_w_out)
+        return VG_ERR_ARG;
+    current_origin(g, origin_w_out);
+    return VG_OK;
+}
+
+vg_status vg_read_grid(const vg_grid *g, uint8_t *dst, int32_t dst_is_device, void *stream)
+{
+    if (!g || !dst)
+        return VG_ERR_ARG;
+    size_t n = (size_t)g->n[0] * g->n[1] * g->n[2];
+    return hip_status(hipMemcpyAsync(dst, g->loc, n,
+                                     dst_is_device ? hipMemcpyDeviceToDevice
+                                                   : hipMemcpyDeviceToHost,
+                                     static_cast<hipStream_t>(stream)));
+}
+
+vg_status vg_write_grid(vg_grid *g, const uint8_t *src, int32_t src_is_device, void *stream)
+{
+    if (!g || !src)
+        return VG_ERR_ARG;
+    size_t n = (size_t)g->n[0] * g->n[1] * g->n[2];
+    return hip_status(hipMemcpyAsync(g->loc, src, n,
+                                     src_is_device ? hipMemcpyDeviceToDevice
+                                                   : hipMemcpyHostToDevice,
+                                     static_cast<hipStream_t>(stream)));
+}
+
+vg_status vg_destroy_grid(vg_grid *g)
+{
+    if (!g)
+        return VG_ERR_ARG;
+    delete g;
+    return VG_OK;
+}
+
+const char *vg_status_str(vg_status s)
+{
+    switch (s) {
+    case VG_OK:
+        return "ok";
+    case VG_ERR_ARG:
+        return "invalid argument";
+    case VG_ERR_HIP:
+        return "HIP runtime error";
+    case VG_ERR_BUDGET:
+        return "scratch workspace too small";
+    case VG_ERR_STATE:
+        return "handle used on another device";
+    default:
+        return "unknown status";
+    }
+}
+
+}  // extern "C"

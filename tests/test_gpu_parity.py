@@ -1,0 +1,298 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, voxel
+by voxel, bit-exact (the grid is integer data; every fp32 decision is taken
+in the same precision and operation order on both sides)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2112_13169_amd import scenes
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2112_13169_amd import vg
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+class GpuGrid:
+    """One grid on the GPU plus an oracle twin fed the same frames."""
+
+    def __init__(self, dims, vox_size, origin, vox_inf, max_rays, init=None):
+        self.dims = tuple(dims)
+        gx, gy, gz = dims
+        self.buf = vg.GridBuffers(dims, max_rays)
+        self.h = vg.vg_create_grid(dims, vox_size, origin, vox_inf, self.buf.loc, self.buf.spare,
+                                   self.buf.scratch)
+        self.vox_size = np.float32(vox_size)
+        self.vox_inf = vox_inf
+        self.base = np.asarray(origin, np.float32)
+        self.shift_total = np.zeros(3, np.int32)
+        self.ref = np.zeros((gz, gy, gx), np.uint8)
+        if init is not None:
+            self.write(init)
+
+    def origin(self):
+        return oracle.origin(self.base, self.shift_total, self.vox_size)
+
+    def write(self, arr):
+        arr = np.ascontiguousarray(arr, np.uint8)
+        src = torch.from_numpy(arr.reshape(-1)).cuda()
+        vg.vg_write_grid(self.h, src)
+        torch.cuda.synchronize()
+        self.ref = arr.reshape(self.ref.shape).copy()
+
+    def read(self):
+        out = torch.empty(self.ref.size, dtype=torch.uint8, device="cuda")
+        vg.vg_read_grid(self.h, out)
+        torch.cuda.synchronize()
+        return out.cpu().numpy().reshape(self.ref.shape)
+
+    def integrate(self, fr, pitch_pad=0):
+        H, W = fr.depth.shape
+        host = np.full((H, W + pitch_pad), np.nan, np.float32)
+        host[:, :W] = fr.depth
+        dev = torch.from_numpy(host).cuda()[:, :W]
+        vg.vg_integrate_frame(self.h, dev, vg.pinhole_sensor(fr.intr), vg.make_pose(fr.R, fr.t))
+        ms, st = oracle.integrate_pinhole(self.ref, self.origin(), self.vox_size, self.vox_inf,
+                                          fr.depth, fr.intr, fr.R, fr.t)
+        return ms, st
+
+    def shift(self, d):
+        vg.vg_shift_grid(self.h, *d)
+        self.ref = oracle.shift(self.ref, d)
+        self.shift_total += np.asarray(d, np.int32)
+
+    def check(self, what):
+        got = self.read()
+        if not np.array_equal(got, self.ref):
+            bad = np.argwhere(got != self.ref)
+            z, y, x = bad[0]
+            raise AssertionError(f"{what}: {len(bad)} voxels differ; first (x={x},y={y},z={z}) "
+                                 f"gpu={got[z, y, x]} oracle={self.ref[z, y, x]}")
+
+    def close(self):
+        vg.vg_destroy_grid(self.h)
+
+
+def _fan_rays(fr):
+    return vg.vg_fan_sizes(vg.pinhole_sensor(fr.intr), fr.vox_size)[3]
+
+
+@pytest.mark.parametrize("index", range(4))
+def test_plain_small_frames(index):
+    fr = scenes.make_frame("plain-small", index)
+    _say(f"plain-small frame {index}")
+    g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf, _fan_rays(fr))
+    g.integrate(fr)
+    g.check(f"plain-small {index}")
+    g.close()
+
+
+def test_plain_medium_full_size():
+    """The benchmark's workload (640x480, 200x200x100 at 0.05 m, vox_inf 2),
+    full grid compared."""
+    fr = scenes.make_frame("plain-medium", 0)
+    _say("plain-medium frame 0")
+    g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf, _fan_rays(fr))
+    g.integrate(fr)
+    g.check("plain-medium 0")
+    g.close()
+
+
+def test_sequence_with_recentring_shifts():
+    """Frames of different poses integrated into one resident grid, the grid
+    re-centred on each camera before its frame (step 5, Sec. IV-E)."""
+    frames = [scenes.make_frame("plain-small", i) for i in range(4, 10)]
+    rays = max(_fan_rays(f) for f in frames)
+    g = GpuGrid(frames[0].dims, frames[0].vox_size, frames[0].origin, frames[0].vox_inf, rays)
+    rng = np.random.default_rng(0)
+    for k, fr in enumerate(frames):
+        # keep the cameras close to each other so the shifts keep content
+        fr.t = (frames[0].t + rng.uniform(-1.0, 1.0, 3) * np.array([1, 1, 0.2])).astype(
+            np.float32)
+        d = oracle.center_offset(fr.dims, fr.vox_size, g.origin(), fr.t)
+        assert d == vg.vg_center_offset(g.h, fr.t)
+        _say(f"sequence frame {k} shift {d}")
+        g.shift(d)
+        g.check(f"sequence shift {k}")
+        g.integrate(fr)
+        g.check(f"sequence frame {k}")
+    g.close()
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_random_six_dof_poses(seed):
+    rng = np.random.default_rng(500 + seed)
+    W, H = [(320, 240), (160, 120), (200, 150)][seed]
+    dims = [(96, 80, 64), (128, 100, 72), (64, 64, 64)][seed]
+    r = [1, 2, 3][seed]
+    fr = scenes.random_pose_frame(rng, W, H, (90.0, 60.0), (0.3, 4.0), dims, 0.07, r, 40, 10)
+    _say(f"six-dof seed {seed}")
+    init = rng.integers(0, 3, dims[::-1]).astype(np.uint8)
+    g = GpuGrid(dims, fr.vox_size, fr.origin, r, _fan_rays(fr), init=init)
+    g.integrate(fr)
+    g.check(f"six-dof {seed}")
+    g.close()
+
+
+def test_stage_parity_measurement_grid():
+    """Writing 0xFF into the grid first exposes the measurement grid: after
+    the frame, 2 = occupied, 1 = free, 0 = unknown-and-traced, 0xFF = untouched."""
+    fr = scenes.make_frame("plain-small", 11)
+    _say("stage parity")
+    gx, gy, gz = fr.dims
+    g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf, _fan_rays(fr),
+                init=np.full((gz, gy, gx), 0xFF, np.uint8))
+    ms, st = g.integrate(fr)
+    got = g.read()
+    rebuilt = np.select([got == 2, got == 1, got == 0], [oracle.OCCUPIED, oracle.FREE,
+                                                         oracle.TRACED], oracle.UNKNOWN)
+    assert np.array_equal(rebuilt.astype(np.uint8), ms)
+    assert int((got != 0xFF).sum()) == st["updates"]
+    g.close()
+
+
+def test_points_input():
+    fr = scenes.make_frame("plain-small", 12)
+    H, W = fr.depth.shape
+    ku = ((np.arange(W) - fr.intr["cx"]) / fr.intr["fx"]).astype(np.float32)
+    kv = ((np.arange(H) - fr.intr["cy"]) / fr.intr["fy"]).astype(np.float32)
+    pts = np.stack([fr.depth * ku[None, :], fr.depth * kv[:, None], fr.depth], -1).reshape(-1, 3)
+    pts[::7] = np.nan        # invalid entries are skipped
+    _say("points input")
+    g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf, _fan_rays(fr))
+    vg.vg_integrate_points(g.h, torch.from_numpy(np.ascontiguousarray(pts)).cuda(),
+                           vg.pinhole_sensor(fr.intr), vg.make_pose(fr.R, fr.t))
+    oracle.integrate_points(g.ref, g.origin(), g.vox_size, g.vox_inf, pts, fr.intr["fov_x"],
+                            fr.intr["fov_y"], fr.intr["depth_max"], fr.R, fr.t)
+    g.check("points")
+    g.close()
+
+
+@pytest.mark.parametrize("vfov", [45.0, 30.0])
+def test_spinning_sensor(vfov):
+    rng = np.random.default_rng(77)
+    W, H = 512, 32
+    col, row = scenes.spinning_tables(W, H, vfov)
+    pos = np.array([0.3, -0.2, 1.2])
+    R = scenes.random_rotation(rng) if vfov == 30.0 else np.eye(3)
+    scene = scenes.world_scene(rng, (12.0, 12.0), 60, 20, height=(0.0, 3.0),
+                               avoid=pos[None, :], keep_out=0.6)
+    img = scenes.render_spinning(scene, R, pos, col, row, 0.3, 4.0, 0.005, rng)
+    dims = (96, 96, 48)
+    s = np.float32(0.1)
+    origin = scenes.centred_origin(pos, dims, s)
+    dcol, drow = torch.from_numpy(col).cuda(), torch.from_numpy(row).cuda()
+    sensor = vg.spinning_sensor(W, H, dcol, drow, math.radians(vfov), 0.3, 4.0)
+    rays = vg.vg_fan_sizes(sensor, s)[3]
+    _say(f"spinning vfov {vfov} rays {rays}")
+    g = GpuGrid(dims, s, origin, 1, rays)
+    vg.vg_integrate_frame(g.h, torch.from_numpy(img).cuda(), sensor, vg.make_pose(R, pos))
+    _, st = oracle.integrate_spinning(g.ref, g.origin(), s, 1, img, col, row, math.radians(vfov),
+                                      0.3, 4.0, R.astype(np.float32).reshape(-1),
+                                      pos.astype(np.float32))
+    assert st["rays"] == rays
+    g.check(f"spinning {vfov}")
+    g.close()
+
+
+def test_edge_cases():
+    fr = scenes.make_frame("plain-small", 13, size=(40, 30))
+    rays = _fan_rays(fr)
+    # all-invalid frame: nothing occupied, the whole fan becomes free
+    _say("edge: all-NaN")
+    g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf, rays)
+    fr_nan = scenes.make_frame("plain-small", 13, size=(40, 30))
+    fr_nan.depth[:] = np.nan
+    g.integrate(fr_nan)
+    g.check("all-NaN")
+    # strided rows
+    _say("edge: row pitch")
+    g.integrate(fr, pitch_pad=13)
+    g.check("pitch")
+    g.close()
+    # camera outside the grid: rays start outside and enter
+    _say("edge: camera outside")
+    for off in ([6.0, 0.2, 0.1], [-6.0, 0.3, 0.0], [0.1, 0.2, 3.0]):
+        g = GpuGrid(fr.dims, fr.vox_size, fr.origin + np.array(off, np.float32), fr.vox_inf,
+                    rays)
+        g.integrate(fr)
+        g.check(f"camera outside {off}")
+        g.close()
+    # vox_inf 0 and a grid smaller than the fan
+    for r, dims in [(0, (30, 20, 10)), (3, (7, 5, 3)), (1, (1, 1, 1))]:
+        _say(f"edge: r={r} dims={dims}")
+        g = GpuGrid(dims, fr.vox_size, (fr.t - np.array(dims) * fr.vox_size / 2).astype(np.float32),
+                    r, rays)
+        g.integrate(fr)
+        g.check(f"r={r} dims={dims}")
+        g.close()
+
+
+def test_empty_image_and_empty_point_cloud():
+    fr = scenes.make_frame("plain-small", 14, size=(16, 12))
+    g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf, _fan_rays(fr))
+    _say("edge: empty point cloud")
+    vg.vg_integrate_points(g.h, torch.zeros((0, 3), dtype=torch.float32, device="cuda"),
+                           vg.pinhole_sensor(fr.intr), vg.make_pose(fr.R, fr.t))
+    oracle.integrate_points(g.ref, g.origin(), g.vox_size, g.vox_inf, np.zeros((0, 3)),
+                            fr.intr["fov_x"], fr.intr["fov_y"], fr.intr["depth_max"], fr.R, fr.t)
+    g.check("empty points")
+    g.close()
+
+
+def test_stamp_wraparound_over_many_frames():
+    """The per-frame occupancy stamp is a byte that wraps after 255 frames."""
+    fr = scenes.make_frame("plain-small", 15, size=(24, 18), dims=(24, 24, 12))
+    g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf, _fan_rays(fr))
+    rng = np.random.default_rng(9)
+    _say("stamp wraparound")
+    base = fr.depth.copy()
+    for k in range(300):
+        fr.depth = np.where(rng.uniform(size=base.shape) < 0.5, base,
+                            np.float32(rng.uniform(0.4, 5.0))).astype(np.float32)
+        g.integrate(fr)
+        if k % 50 == 0 or k >= 250:
+            g.check(f"frame {k}")
+    g.close()
+
+
+def test_shift_parity():
+    rng = np.random.default_rng(21)
+    dims = (37, 29, 17)
+    init = rng.integers(0, 3, dims[::-1]).astype(np.uint8)
+    g = GpuGrid(dims, 0.1, [0, 0, 0], 1, 64, init=init)
+    for d in [(1, 0, 0), (-3, 2, 1), (0, 0, -5), (40, 0, 0), (-2, -30, 3), (0, 0, 0)]:
+        _say(f"shift {d}")
+        g.shift(d)
+        g.check(f"shift {d}")
+    assert np.allclose(vg.vg_grid_origin(g.h), g.origin())
+    g.close()
+
+
+def test_determinism_and_budget():
+    fr = scenes.make_frame("plain-small", 16)
+    rays = _fan_rays(fr)
+    outs = []
+    for _ in range(2):
+        g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf, rays)
+        g.integrate(fr)
+        outs.append(g.read())
+        g.close()
+    assert np.array_equal(outs[0], outs[1])
+    # a workspace sized for fewer rays is refused without touching the grid
+    g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf, rays // 2)
+    with pytest.raises(vg.VgError) as ei:
+        g.integrate(fr)
+    assert ei.value.status == vg.VG_ERR_BUDGET
+    g.ref[:] = 0
+    g.check("budget refusal leaves grid unknown")
+    g.close()
