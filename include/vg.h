@@ -153,6 +153,14 @@ vg_status vg_read_grid(const vg_grid *g, uint8_t *dst, int32_t dst_is_device, vo
 /* Overwrite the local grid (restore a checkpoint) from src (linear layout). */
 vg_status vg_write_grid(vg_grid *g, const uint8_t *src, int32_t src_is_device, void *stream);
 
+/* Measurement hook.  With n_sets > 0, each following vg_integrate_frame /
+ * vg_integrate_points call k records the caller's events (hipEvent_t)
+ * events[4*j + 0..3], j = k mod n_sets, on its stream: before the occupied
+ * pass, after it, after the free pass and after the traced pass, so that
+ * event pairs time each kernel.  The array is copied; the events must stay
+ * alive while set.  n_sets = 0 (events may be NULL) turns recording off. */
+vg_status vg_set_profile_events(vg_grid *g, void *const *events, int32_t n_sets);
+
 /* Release the handle (host metadata only; caller buffers are untouched).
  * The caller must make sure no work using the handle is still queued if it
  * frees the buffers afterwards. */

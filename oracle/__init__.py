@@ -131,7 +131,7 @@ def integrate_pinhole(loc, origin_w, vox_size, vox_inf, depth, intr, R, t, want_
     depth = np.ascontiguousarray(depth, dtype=np.float32)
     H, W = depth.shape
     ms = np.zeros_like(loc) if want_ms else None
-    st = np.zeros(4, np.int64)
+    st = np.zeros(5, np.int64)
     rc = lib().og_integrate_pinhole(
         gx, gy, gz, vox_size, _p(_f32(origin_w, 3)), vox_inf, _p(loc),
         _p(ms) if want_ms else None, _p(depth), W, H,
@@ -139,7 +139,8 @@ def integrate_pinhole(loc, origin_w, vox_size, vox_inf, depth, intr, R, t, want_
         intr["depth_min"], intr["depth_max"], _p(_f32(R, 9)), _p(_f32(t, 3)), _p(st))
     if rc:
         raise ValueError("oracle rejected the frame")
-    return ms, dict(updates=int(st[0]), steps=int(st[1]), occupied=int(st[2]), rays=int(st[3]))
+    return ms, dict(updates=int(st[0]), steps=int(st[1]), occupied=int(st[2]), rays=int(st[3]),
+                    steps_after_hit=int(st[4]))
 
 
 def integrate_spinning(loc, origin_w, vox_size, vox_inf, rng_img, col_tab, row_tab, vfov,
@@ -150,14 +151,15 @@ def integrate_spinning(loc, origin_w, vox_size, vox_inf, rng_img, col_tab, row_t
     col_tab = _f32(col_tab, 2 * W)
     row_tab = _f32(row_tab, 2 * H)
     ms = np.zeros_like(loc) if want_ms else None
-    st = np.zeros(4, np.int64)
+    st = np.zeros(5, np.int64)
     rc = lib().og_integrate_spinning(
         gx, gy, gz, vox_size, _p(_f32(origin_w, 3)), vox_inf, _p(loc),
         _p(ms) if want_ms else None, _p(rng_img), W, H, _p(col_tab), _p(row_tab),
         vfov, depth_min, depth_max, _p(_f32(R, 9)), _p(_f32(t, 3)), _p(st))
     if rc:
         raise ValueError("oracle rejected the frame")
-    return ms, dict(updates=int(st[0]), steps=int(st[1]), occupied=int(st[2]), rays=int(st[3]))
+    return ms, dict(updates=int(st[0]), steps=int(st[1]), occupied=int(st[2]), rays=int(st[3]),
+                    steps_after_hit=int(st[4]))
 
 
 def integrate_points(loc, origin_w, vox_size, vox_inf, points, fov_x, fov_y, depth, R, t,
@@ -165,14 +167,15 @@ def integrate_points(loc, origin_w, vox_size, vox_inf, points, fov_x, fov_y, dep
     gx, gy, gz = _grid_args(loc)
     pts = np.ascontiguousarray(points, dtype=np.float32).reshape(-1, 3)
     ms = np.zeros_like(loc) if want_ms else None
-    st = np.zeros(4, np.int64)
+    st = np.zeros(5, np.int64)
     rc = lib().og_integrate_points(
         gx, gy, gz, vox_size, _p(_f32(origin_w, 3)), vox_inf, _p(loc),
         _p(ms) if want_ms else None, _p(pts), pts.shape[0], fov_x, fov_y, depth,
         _p(_f32(R, 9)), _p(_f32(t, 3)), _p(st))
     if rc:
         raise ValueError("oracle rejected the frame")
-    return ms, dict(updates=int(st[0]), steps=int(st[1]), occupied=int(st[2]), rays=int(st[3]))
+    return ms, dict(updates=int(st[0]), steps=int(st[1]), occupied=int(st[2]), rays=int(st[3]),
+                    steps_after_hit=int(st[4]))
 
 
 def merge(ms, loc):

@@ -185,7 +185,8 @@ static void mark(uint8_t *ms, int64_t idx, uint8_t val)
  * assigned to each (og_trace_ray), and the number of in-grid voxels. */
 static int64_t walk(const float o[3], const float dir[3], int64_t m2,
                     int32_t gx, int32_t gy, int32_t gz, uint8_t *ms,
-                    int32_t *out_xyz, uint8_t *out_val, int64_t max_out, int64_t *in_grid)
+                    int32_t *out_xyz, uint8_t *out_val, int64_t max_out, int64_t *in_grid,
+                    int64_t *after_hit)
 {
     /* R12: start voxel = floor of the camera position in voxel units. */
     int32_t v0[3], v[3], step[3];
@@ -211,7 +212,7 @@ static int64_t walk(const float o[3], const float dir[3], int64_t m2,
 
     uint8_t vox_val = OG_FREE;   /* Alg. 2: vox_val <- free */
     int64_t d2 = 0;              /* R15: squared lattice distance from v0 */
-    int64_t nsteps = 0, ingrid = 0;
+    int64_t nsteps = 0, ingrid = 0, post = 0;
     while (d2 < m2) {
         /* R13: move by one voxel along the axis whose boundary is nearest;
          * on ties the later axis wins.  R14: the start voxel is never
@@ -226,6 +227,7 @@ static int64_t walk(const float o[3], const float dir[3], int64_t m2,
         if (inside(gx, gy, gz, v[0], v[1], v[2])) {       /* R17 */
             int64_t idx = lin(gx, gy, v[0], v[1], v[2]);
             ++ingrid;
+            post += vox_val == OG_TRACED;
             /* R16: the occupancy test reads this measurement's grid. */
             if (ms && ms[idx] == OG_OCCUPIED) {
                 vox_val = OG_TRACED;                       /* Alg. 2: after the hit */
@@ -251,6 +253,8 @@ static int64_t walk(const float o[3], const float dir[3], int64_t m2,
     }
     if (in_grid)
         *in_grid += ingrid;
+    if (after_hit)
+        *after_hit += post;
     return nsteps;
 }
 
@@ -261,7 +265,7 @@ int64_t og_trace_ray(const float o[3], const float dir[3], int64_t m2,
     for (int a = 0; a < 3; ++a)
         if (!(fabsf(o[a]) < 16777216.0f) || !isfinite(dir[a]))
             return -1;
-    return walk(o, dir, m2, gx, gy, gz, ms, out_xyz, out_val, max_out, NULL);
+    return walk(o, dir, m2, gx, gy, gz, ms, out_xyz, out_val, max_out, NULL, NULL);
 }
 
 /* ------------------------------------------ Alg. 3: update local grid (IV-D) */
@@ -285,7 +289,7 @@ typedef struct {
     float tv[3];
     const float *R;
     uint8_t *ms;
-    int64_t n_occ_pts;
+    int64_t after_hit;   /* in-grid walk steps after the ray's first hit */
 } frame_ctx;
 
 static int check_grid(int32_t gx, int32_t gy, int32_t gz, float vox_size, int32_t vox_inf)
@@ -321,14 +325,14 @@ static int64_t trace_pinhole_fan(frame_ctx *f, int32_t vd, int32_t hw, int32_t h
             tgt[2] = (float)vd;
             rotate(f->R, tgt, dir);        /* Alg. 2 line 4, R11 */
             int64_t m2 = (int64_t)xi * xi + (int64_t)yi * yi + (int64_t)vd * vd;
-            walk(o, dir, m2, f->gx, f->gy, f->gz, f->ms, NULL, NULL, 0, &steps);
+            walk(o, dir, m2, f->gx, f->gy, f->gz, f->ms, NULL, NULL, 0, &steps, &f->after_hit);
         }
     }
     return steps;
 }
 
 static void finish_frame(frame_ctx *f, uint8_t *loc, uint8_t *ms_out, int64_t rays,
-                         int64_t steps, int64_t stats[4])
+                         int64_t steps, int64_t stats[5])
 {
     int64_t n = (int64_t)f->gx * f->gy * f->gz;
     int64_t upd = 0, occ = 0;
@@ -344,6 +348,7 @@ static void finish_frame(frame_ctx *f, uint8_t *loc, uint8_t *ms_out, int64_t ra
         stats[1] = steps;
         stats[2] = occ;
         stats[3] = rays;
+        stats[4] = f->after_hit;
     }
 }
 
@@ -364,6 +369,7 @@ static int start_frame(frame_ctx *f, int32_t gx, int32_t gy, int32_t gz, float v
     f->vox_size = vox_size;
     f->vox_inf = vox_inf;
     f->R = R;
+    f->after_hit = 0;
     grid_translation(t, origin, f->tv);
     /* Integer voxel coordinates of the camera must stay far from int32 limits. */
     for (int a = 0; a < 3; ++a)
@@ -382,7 +388,7 @@ int og_integrate_pinhole(int32_t gx, int32_t gy, int32_t gz, float vox_size,
                          const float *depth, int32_t width, int32_t height,
                          double fx, double fy, double cx, double cy,
                          double fov_x, double fov_y, float depth_min, float depth_max,
-                         const float R[9], const float t[3], int64_t stats[4])
+                         const float R[9], const float t[3], int64_t stats[5])
 {
     int32_t fan[3];
     if (width < 0 || height < 0 || og_fan_sizes(depth_max, vox_size, fov_x, fov_y, fan))
@@ -418,7 +424,7 @@ int og_integrate_points(int32_t gx, int32_t gy, int32_t gz, float vox_size,
                         uint8_t *loc, uint8_t *ms_out,
                         const float *points, int64_t n_points,
                         double fov_x, double fov_y, float depth,
-                        const float R[9], const float t[3], int64_t stats[4])
+                        const float R[9], const float t[3], int64_t stats[5])
 {
     int32_t fan[3];
     if (n_points < 0 || og_fan_sizes(depth, vox_size, fov_x, fov_y, fan))
@@ -446,7 +452,7 @@ int og_integrate_spinning(int32_t gx, int32_t gy, int32_t gz, float vox_size,
                           const float *range, int32_t width, int32_t height,
                           const float *col_tab, const float *row_tab,
                           double vfov, float depth_min, float depth_max,
-                          const float R[9], const float t[3], int64_t stats[4])
+                          const float R[9], const float t[3], int64_t stats[5])
 {
     double vd_d = round_half_away((double)depth_max / (double)vox_size);   /* R9 */
     if (!(vd_d >= 1.0 && vd_d <= 16384.0) || !(vfov > 0.0 && vfov < 3.14159))
@@ -486,7 +492,7 @@ int og_integrate_spinning(int32_t gx, int32_t gy, int32_t gz, float vox_size,
             tgt[1] = (float)y;
             tgt[2] = (float)z;
             rotate(R, tgt, dir);
-            walk(o, dir, m2, gx, gy, gz, f.ms, NULL, NULL, 0, &steps);
+            walk(o, dir, m2, gx, gy, gz, f.ms, NULL, NULL, 0, &steps, &f.after_hit);
             ++rays;
         }
     }

@@ -71,15 +71,16 @@ int64_t og_trace_ray(const float o[3], const float dir[3], int64_t m2,
  * loc: in/out local grid (gx*gy*gz bytes, x fastest).  ms_out: optional copy of
  * the measurement grid after step 3.  depth: width*height floats, row-major.
  * R (row-major), t: T^w_c.  origin: current grid origin in the world frame.
- * stats (optional, 4 entries): voxel updates (ms != unknown), in-grid walk steps,
- * occupied voxels, rays.  Returns 0 or -1 on invalid arguments. */
+ * stats (optional, 5 entries): voxel updates (ms != unknown), in-grid walk steps,
+ * occupied voxels, rays, in-grid walk steps after each ray's first hit.
+ * Returns 0 or -1 on invalid arguments. */
 int og_integrate_pinhole(int32_t gx, int32_t gy, int32_t gz, float vox_size,
                          const float origin[3], int32_t vox_inf,
                          uint8_t *loc, uint8_t *ms_out,
                          const float *depth, int32_t width, int32_t height,
                          double fx, double fy, double cx, double cy,
                          double fov_x, double fov_y, float depth_min, float depth_max,
-                         const float R[9], const float t[3], int64_t stats[4]);
+                         const float R[9], const float t[3], int64_t stats[5]);
 
 /* Steps 1-4 for one spinning range image (R27).  col_tab: 2*width floats
  * (cos az, sin az per column), row_tab: 2*height floats (cos el, sin el per row).
@@ -90,7 +91,7 @@ int og_integrate_spinning(int32_t gx, int32_t gy, int32_t gz, float vox_size,
                           const float *range, int32_t width, int32_t height,
                           const float *col_tab, const float *row_tab,
                           double vfov, float depth_min, float depth_max,
-                          const float R[9], const float t[3], int64_t stats[4]);
+                          const float R[9], const float t[3], int64_t stats[5]);
 
 /* Steps 1-4 for a dense point cloud given in the camera frame (Sec. IV input
  * form "dense point cloud"); the ray fan is the pinhole fan of fov_x/fov_y. */
@@ -99,7 +100,7 @@ int og_integrate_points(int32_t gx, int32_t gy, int32_t gz, float vox_size,
                         uint8_t *loc, uint8_t *ms_out,
                         const float *points, int64_t n_points,
                         double fov_x, double fov_y, float depth,
-                        const float R[9], const float t[3], int64_t stats[4]);
+                        const float R[9], const float t[3], int64_t stats[5]);
 
 /* Alg. 3 applied to whole grids (R19). */
 void og_merge(int64_t n, const uint8_t *ms, uint8_t *loc);

@@ -135,6 +135,9 @@ struct vg_grid {
     int32_t hz_vd = 0;
     double hz_fov = -1.0;
     std::vector<int32_t> hz_host;   // kept alive for the asynchronous upload
+    // measurement hook: 4 events per set, one set per frame in turn
+    std::vector<hipEvent_t> prof;
+    uint64_t prof_next = 0;
 };
 
 namespace {
@@ -229,6 +232,14 @@ vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_float
         g->hz_fov = sensor->fov_y;
     }
 
+    hipEvent_t *ev = nullptr;
+    if (!g->prof.empty()) {
+        size_t sets = g->prof.size() / 4;
+        ev = &g->prof[4 * (size_t)(g->prof_next++ % sets)];
+        if (hipEventRecord(ev[0], st) != hipSuccess)
+            return VG_ERR_HIP;
+    }
+
     uint32_t *counter = reinterpret_cast<uint32_t *>(g->scratch + g->lay.counter);
     OccParams op;
     std::memcpy(op.R, T->R, sizeof op.R);
@@ -254,6 +265,8 @@ vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_float
     op.parked_count = counter;
     op.epoch = epoch;
     e = launch_occupied(op, st);
+    if (e == hipSuccess && ev)
+        e = hipEventRecord(ev[1], st);
     if (e != hipSuccess)
         return VG_ERR_HIP;
 
@@ -285,7 +298,9 @@ vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_float
     rp.parked_count = counter;
     rp.parked_cap = (uint32_t)std::min<size_t>(cap, 0xffffffffu);
     rp.epoch = epoch;
-    e = launch_rays(rp, st);
+    e = launch_rays(rp, st, ev ? ev[2] : nullptr);
+    if (e == hipSuccess && ev)
+        e = hipEventRecord(ev[3], st);
     if (e != hipSuccess)
         return VG_ERR_HIP;
     g->epoch = epoch;
@@ -473,6 +488,21 @@ vg_status vg_write_grid(vg_grid *g, const uint8_t *src, int32_t src_is_device, v
                                      src_is_device ? hipMemcpyDeviceToDevice
                                                    : hipMemcpyHostToDevice,
                                      static_cast<hipStream_t>(stream)));
+}
+
+vg_status vg_set_profile_events(vg_grid *g, void *const *events, int32_t n_sets)
+{
+    if (!g || n_sets < 0 || (n_sets > 0 && !events))
+        return VG_ERR_ARG;
+    std::vector<hipEvent_t> v;
+    for (int64_t i = 0; i < 4 * (int64_t)n_sets; ++i) {
+        if (!events[i])
+            return VG_ERR_ARG;
+        v.push_back(static_cast<hipEvent_t>(events[i]));
+    }
+    g->prof.swap(v);
+    g->prof_next = 0;
+    return VG_OK;
 }
 
 vg_status vg_destroy_grid(vg_grid *g)

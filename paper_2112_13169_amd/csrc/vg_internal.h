@@ -70,7 +70,8 @@ struct RayParams {
 
 hipError_t launch_fill(void *dst, uint8_t value, size_t bytes, hipStream_t st);
 hipError_t launch_occupied(const OccParams &p, hipStream_t st);
-hipError_t launch_rays(const RayParams &p, hipStream_t st);
+// mid: optional event recorded between the free and the traced pass.
+hipError_t launch_rays(const RayParams &p, hipStream_t st, hipEvent_t mid);
 hipError_t launch_shift(const uint8_t *src, uint8_t *dst, const int32_t n[3],
                         const int32_t d[3], hipStream_t st);
 

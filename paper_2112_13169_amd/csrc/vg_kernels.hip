@@ -419,7 +419,7 @@ hipError_t launch_occupied(const OccParams &p, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_rays(const RayParams &p, hipStream_t st)
+hipError_t launch_rays(const RayParams &p, hipStream_t st, hipEvent_t mid)
 {
     const int waves = kBlock / 64;
     uint32_t blocks = (uint32_t)((p.tiles + waves - 1) / waves);
@@ -427,6 +427,8 @@ hipError_t launch_rays(const RayParams &p, hipStream_t st)
         return hipSuccess;
     hipLaunchKernelGGL(k_ray_free, dim3(blocks), dim3(kBlock), 0, st, p);
     hipError_t e = hipGetLastError();
+    if (e == hipSuccess && mid)
+        e = hipEventRecord(mid, st);
     if (e != hipSuccess)
         return e;
     uint32_t tblocks = (uint32_t)(((uint64_t)p.tiles * 64 + kBlock - 1) / kBlock);

@@ -67,11 +67,13 @@ def lib():
         L.vg_read_grid.argtypes = [P, P, i32, P]
         L.vg_write_grid.argtypes = [P, P, i32, P]
         L.vg_destroy_grid.argtypes = [P]
+        L.vg_set_profile_events.argtypes = [P, P, i32]
         L.vg_status_str.argtypes = [i32]
         L.vg_status_str.restype = ctypes.c_char_p
         for name in ("vg_fan_sizes", "vg_create_grid", "vg_integrate_frame",
                      "vg_integrate_points", "vg_shift_grid", "vg_center_offset",
-                     "vg_grid_origin", "vg_read_grid", "vg_write_grid", "vg_destroy_grid"):
+                     "vg_grid_origin", "vg_read_grid", "vg_write_grid", "vg_destroy_grid",
+                     "vg_set_profile_events"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -193,6 +195,20 @@ def vg_read_grid(g, dst, stream=None):
 
 def vg_write_grid(g, src, stream=None):
     _check(lib().vg_write_grid(g, _ptr(src), int(src.is_cuda), _stream(stream)), "vg_write_grid")
+
+
+def vg_set_profile_events(g, events):
+    """events: list of torch.cuda.Event (enable_timing=True), 4 per set; [] off.
+    Each event is recorded once on the current device before its handle is
+    passed on."""
+    n = len(events)
+    assert n % 4 == 0
+    arr = (ctypes.c_void_p * max(n, 1))()
+    for i, e in enumerate(events):
+        if not e.cuda_event:
+            e.record()          # torch creates the hipEvent_t lazily
+        arr[i] = e.cuda_event
+    _check(lib().vg_set_profile_events(g, arr if n else None, n // 4), "vg_set_profile_events")
 
 
 def vg_destroy_grid(g):
