@@ -8,7 +8,7 @@ z-depth frame (90x60 deg pinhole, 0.3-8 m, 200 boxes + 50 spheres, depth noise
 N(0, (0.005 d^2)^2), 5 % invalid pixels in 8x8 blocks), integrated into a
 resident 200x200x100 uint8 grid at 0.05 m with vox_inf 2: re-centre the grid
 on the camera (vg_shift_grid by vg_center_offset), then vg_integrate_frame
-(occupied pass, free pass, traced pass).  A pool of seeded frames with random
+(seed, dilation, free pass, traced pass, occupied marking).  A pool of seeded frames with random
 yaw and position is cycled; depth images are resident on the GPU before the
 timed region starts.
 """
@@ -93,7 +93,7 @@ def main():
     nvox = gx * gy * gz
 
     def new_grid():
-        buf = vg.GridBuffers(fr0.dims, rays)
+        buf = vg.GridBuffers(fr0.dims, fr0.vox_inf, rays)
         h = vg.vg_create_grid(fr0.dims, fr0.vox_size, fr0.origin, fr0.vox_inf, buf.loc, buf.spare,
                               buf.scratch)
         return buf, h
@@ -159,8 +159,9 @@ def main():
     for k in range(args.warmup):
         step(h, k)
     K = args.steps
+    E = vg.PROFILE_EVENTS
     ev_start = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
-    ev_stage = [torch.cuda.Event(enable_timing=True) for _ in range(4 * K)]
+    ev_stage = [torch.cuda.Event(enable_timing=True) for _ in range(E * K)]
     vg.vg_set_profile_events(h, ev_stage)
     origins = []
     torch.cuda.synchronize()
@@ -172,12 +173,12 @@ def main():
     wall = time.perf_counter() - w0
     vg.vg_set_profile_events(h, [])
 
-    lat = np.array([ev_start[k].elapsed_time(ev_stage[4 * k + 3]) for k in range(K)])
-    shift_ms = np.array([ev_start[k].elapsed_time(ev_stage[4 * k + 0]) for k in range(K)])
-    occ_ms = np.array([ev_stage[4 * k].elapsed_time(ev_stage[4 * k + 1]) for k in range(K)])
-    free_ms = np.array([ev_stage[4 * k + 1].elapsed_time(ev_stage[4 * k + 2]) for k in range(K)])
-    trc_ms = np.array([ev_stage[4 * k + 2].elapsed_time(ev_stage[4 * k + 3]) for k in range(K)])
-    gpu_span = ev_start[0].elapsed_time(ev_stage[4 * (K - 1) + 3])  # ms, first start .. last end
+    lat = np.array([ev_start[k].elapsed_time(ev_stage[E * k + E - 1]) for k in range(K)])
+    stage_ms = {"k_shift": np.array([ev_start[k].elapsed_time(ev_stage[E * k]) for k in range(K)])}
+    for j, name in enumerate(vg.PROFILE_STAGES):
+        stage_ms["k_" + name] = np.array([ev_stage[E * k + j].elapsed_time(ev_stage[E * k + j + 1])
+                                          for k in range(K)])
+    gpu_span = ev_start[0].elapsed_time(ev_stage[E * (K - 1) + E - 1])  # first start .. last end
     ms_per_step = max(wall * 1e3, gpu_span) / K
     fps = 1e3 / ms_per_step
 
@@ -195,12 +196,7 @@ def main():
     after = np.array([s["steps_after_hit"] for s in st_steps], float)
     before = walk - after
 
-    kernels = {
-        "k_shift": float(shift_ms.mean()),
-        "k_occupied": float(occ_ms.mean()),
-        "k_ray_free": float(free_ms.mean()),
-        "k_ray_traced": float(trc_ms.mean()),
-    }
+    kernels = {k: float(v.mean()) for k, v in stage_ms.items()}
     dominant = max(kernels, key=kernels.get)
     if dominant in ("k_ray_free", "k_ray_traced"):
         units = before.mean() if dominant == "k_ray_free" else after.mean()
@@ -210,14 +206,15 @@ def main():
                 "kernel": dominant, "units_per_launch": float(units),
                 "unit_kind": "in-grid walk steps", "ops_per_unit": OPS_PER_STEP}
     else:
-        if dominant == "k_shift":
-            nbytes = 2.0 * nvox
-        else:
-            nbytes = 4.0 * fr0.depth.size
+        # algorithmic HBM bytes of the streaming stages
+        nbytes = {"k_shift": 2.0 * nvox,                   # read + write the grid
+                  "k_seed": 5.0 * fr0.depth.size,           # depth in, stamp out
+                  "k_dilate": nvox / 8.0 * 2 + nvox,        # seeds in, bit planes out
+                  "k_mark_occ": nvox / 8.0 + upd.mean()}[dominant]
         achieved = nbytes / (kernels[dominant] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": dominant}
+                "kernel": dominant, "bytes_per_launch": float(nbytes)}
 
     cpu = None
     if cpu_times:

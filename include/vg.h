@@ -91,19 +91,20 @@ typedef struct vg_sensor {
  * (vox_depth > 16384, half sizes > 16384). */
 vg_status vg_fan_sizes(const vg_sensor *sensor, float vox_size, int64_t out[4]);
 
-/* Bytes of device scratch a grid of this size needs to integrate frames from
- * sensors with up to `max_rays` rays (vg_fan_sizes out[3]).  Host-only. */
+/* Bytes of device scratch a grid of this size and vox_inf needs to integrate
+ * frames from sensors with up to `max_rays` rays (vg_fan_sizes out[3]).
+ * Host-only; 0 for invalid sizes. */
 size_t vg_scratch_bytes(int32_t grid_size_x, int32_t grid_size_y, int32_t grid_size_z,
-                        int64_t max_rays);
+                        int32_t vox_inf, int64_t max_rays);
 
 /* Step 1 (Sec. IV-A): bind caller buffers to a new grid and set every voxel
  * of loc_grid to unknown (enqueued on `stream`).
  *   loc_grid, loc_spare: device, grid_size_x*y*z bytes each, distinct.  The
  *     spare buffer receives shifted grids (vg_shift_grid swaps the two).
- *   scratch: device, scratch_bytes >= vg_scratch_bytes(..., max_rays), 256-byte
+ *   scratch: device, scratch_bytes >= vg_scratch_bytes(.., vox_inf, max_rays), 256-byte
  *     aligned; it is cleared here and owned by the grid until destroyed.
  *   origin_w: world position (m) of the grid corner (voxel (0,0,0)'s minimum
- *     corner); vox_size > 0 m; vox_inf in [0, 64] voxels of inflation.
+ *     corner); vox_size > 0 m; vox_inf in [0, 16] voxels of inflation.
  *   Dimensions in [1, 65535] with grid_size_x*y*z < 2^31.
  * On success *out receives the handle. */
 vg_status vg_create_grid(int32_t grid_size_x, int32_t grid_size_y, int32_t grid_size_z,
@@ -155,10 +156,11 @@ vg_status vg_write_grid(vg_grid *g, const uint8_t *src, int32_t src_is_device, v
 
 /* Measurement hook.  With n_sets > 0, each following vg_integrate_frame /
  * vg_integrate_points call k records the caller's events (hipEvent_t)
- * events[4*j + 0..3], j = k mod n_sets, on its stream: before the occupied
- * pass, after it, after the free pass and after the traced pass, so that
- * event pairs time each kernel.  The array is copied; the events must stay
- * alive while set.  n_sets = 0 (events may be NULL) turns recording off. */
+ * events[6*j + 0..5], j = k mod n_sets, on its stream: before the seed pass,
+ * after it, after the dilation, after the free pass, after the traced pass
+ * and after the occupied marking, so that event pairs time each stage.  The
+ * array is copied; the events must stay alive while set.  n_sets = 0 (events
+ * may be NULL) turns recording off. */
 vg_status vg_set_profile_events(vg_grid *g, void *const *events, int32_t n_sets);
 
 /* Release the handle (host metadata only; caller buffers are untouched).

@@ -24,20 +24,29 @@ constexpr size_t kHzBytes = (size_t)8 * kMaxFan * sizeof(int32_t);
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Scratch layout (all offsets 256-aligned):
-//   [0, 256)               parked-ray counter
-//   [256, 256+N')          occupancy stamps, one byte per voxel
-//   [.., + kHzBytes)       spinning fan: half height per ring column
-//   [.., end)              parked rays, 32 bytes each
+//   counter   parked-ray counter
+//   seed      seed stamps on the grid padded by vox_inf, rows of seed_pitch bytes
+//   bitx      seeds dilated along x, one 32-bit word per 32 voxels of a padded row
+//   occ       occupied voxels of the frame, one bit per voxel
+//   hz        spinning fan: half height per ring column
+//   parked    parked rays, 32 bytes each, up to the end of the workspace
 struct Layout {
-    size_t counter, occ, hz, parked, fixed;
+    int32_t wx, py, pz, seed_pitch;
+    size_t counter, seed, bitx, occ, hz, parked, fixed;
 };
 
-Layout layout_for(int64_t voxels)
+Layout layout_for(int32_t gx, int32_t gy, int32_t gz, int32_t r)
 {
     Layout l;
+    l.wx = (gx + 31) / 32;
+    l.py = gy + 2 * r;
+    l.pz = gz + 2 * r;
+    l.seed_pitch = (32 * l.wx + 64 + 63) / 64 * 64;
     l.counter = 0;
-    l.occ = kAlign;
-    l.hz = l.occ + align_up((size_t)voxels);
+    l.seed = kAlign;
+    l.bitx = l.seed + align_up((size_t)l.seed_pitch * l.py * l.pz);
+    l.occ = l.bitx + align_up((size_t)4 * l.wx * l.py * l.pz);
+    l.hz = l.occ + align_up((size_t)4 * l.wx * gy * gz);
     l.parked = l.hz + kHzBytes;
     l.fixed = l.parked;
     return l;
@@ -135,12 +144,14 @@ struct vg_grid {
     int32_t hz_vd = 0;
     double hz_fov = -1.0;
     std::vector<int32_t> hz_host;   // kept alive for the asynchronous upload
-    // measurement hook: 4 events per set, one set per frame in turn
+    // measurement hook: kProfileEvents events per set, one set per frame in turn
     std::vector<hipEvent_t> prof;
     uint64_t prof_next = 0;
 };
 
 namespace {
+
+constexpr int kProfileEvents = 6;
 
 vg_status hip_status(hipError_t e) { return e == hipSuccess ? VG_OK : VG_ERR_HIP; }
 
@@ -179,6 +190,77 @@ bool valid_sensor(const vg_sensor *s)
     return true;
 }
 
+// Padded-coordinate box that holds every seed a frame can produce, from the
+// sensor's frustum (pinhole: the 8 corners of the depth range over the image;
+// spinning: a ball of the largest range), widened by a bound on the fp32
+// rounding of the device's transform.  Points: the whole padded grid.
+void seed_box(const vg_grid *g, int kind, const vg_sensor &s, const vg_pose &T,
+              const float tv[3], int32_t lo[3], int32_t hi[3])
+{
+    const int32_t r = g->r;
+    for (int a = 0; a < 3; ++a) {
+        lo[a] = 0;
+        hi[a] = g->n[a] - 1 + 2 * r;
+    }
+    if (kind == kPoints || !std::isfinite(s.depth_min))
+        return;
+    if (s.width == 0 || s.height == 0 || s.depth_min > s.depth) {
+        lo[0] = 1;
+        hi[0] = 0;   // no measurement can exist
+        return;
+    }
+    double qmin[3], qmax[3], mag = 0.0, tmag = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        qmin[a] = INFINITY;
+        qmax[a] = -INFINITY;
+        tmag = std::max(tmag, std::fabs((double)tv[a]));
+    }
+    if (kind == kPinhole) {
+        const double ku[2] = {(0.0 - s.cx) / s.fx, ((double)s.width - 1.0 - s.cx) / s.fx};
+        const double kv[2] = {(0.0 - s.cy) / s.fy, ((double)s.height - 1.0 - s.cy) / s.fy};
+        const double dd[2] = {(double)s.depth_min, (double)s.depth};
+        for (double d : dd)
+            for (double u : ku)
+                for (double v : kv) {
+                    const double pc[3] = {d * u, d * v, d};
+                    double m = 0.0;
+                    for (int a = 0; a < 3; ++a) {
+                        double pv = (double)tv[a];
+                        for (int j = 0; j < 3; ++j) {
+                            pv += (double)T.R[3 * a + j] * pc[j];
+                            m += std::fabs((double)T.R[3 * a + j] * pc[j]);
+                        }
+                        qmin[a] = std::min(qmin[a], pv / g->s);
+                        qmax[a] = std::max(qmax[a], pv / g->s);
+                    }
+                    mag = std::max(mag, m);
+                }
+    } else {
+        const double rho = std::max(std::fabs((double)s.depth_min), std::fabs((double)s.depth));
+        for (int a = 0; a < 3; ++a) {
+            double ext = 0.0;
+            for (int j = 0; j < 3; ++j)
+                ext += std::fabs((double)T.R[3 * a + j]) * rho * 1.0001;
+            qmin[a] = ((double)tv[a] - ext) / g->s;
+            qmax[a] = ((double)tv[a] + ext) / g->s;
+            mag = std::max(mag, 3.0 * ext);
+        }
+    }
+    const double slack = 4.0 + 4e-6 * (mag + tmag) / g->s;
+    for (int a = 0; a < 3; ++a) {
+        double l = std::floor(qmin[a] - slack) + r, h = std::floor(qmax[a] + slack) + r;
+        l = std::max(l, 0.0);
+        h = std::min(h, (double)(g->n[a] - 1 + 2 * r));
+        if (!(l <= h)) {
+            lo[0] = 1;
+            hi[0] = 0;
+            return;
+        }
+        lo[a] = (int32_t)l;
+        hi[a] = (int32_t)h;
+    }
+}
+
 // Common part of steps 2-4: per-frame constants, stamp, launches.
 vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_floats, int32_t W,
                     int32_t H, const vg_sensor *sensor, const vg_pose *T, hipStream_t st)
@@ -202,16 +284,21 @@ vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_float
         v0[a] = (int32_t)std::floor(o[a]);
     }
 
+    // fan tiles of 8 x 8 targets, one wavefront each
+    const int32_t fan_a = kind == kSpinning ? 8 * fan.vd : 2 * fan.hw + 1;
+    const int64_t tiles = (int64_t)((fan_a + 7) / 8) * ((2 * fan.hh + 1 + 7) / 8);
+    if (tiles * 64 > (int64_t)0x7fffffff)
+        return VG_ERR_ARG;
     size_t cap = (g->scratch_bytes - g->lay.fixed) / sizeof(ParkedRay);
     if ((int64_t)cap < fan.rays)
         return VG_ERR_BUDGET;
     if (!same_device(g))
         return VG_ERR_STATE;
 
-    // Per-frame occupancy stamp 1..255; the plane is cleared when it wraps.
+    // Per-frame seed stamp 1..255; the seed plane is cleared when it wraps.
     hipError_t e = hipSuccess;
     if (g->epoch == 255) {
-        e = launch_fill(g->scratch + g->lay.occ, 0, (size_t)g->n[0] * g->n[1] * g->n[2], st);
+        e = launch_fill(g->scratch + g->lay.seed, 0, g->lay.bitx - g->lay.seed, st);
         if (e != hipSuccess)
             return VG_ERR_HIP;
         g->epoch = 0;
@@ -234,47 +321,54 @@ vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_float
 
     hipEvent_t *ev = nullptr;
     if (!g->prof.empty()) {
-        size_t sets = g->prof.size() / 4;
-        ev = &g->prof[4 * (size_t)(g->prof_next++ % sets)];
-        if (hipEventRecord(ev[0], st) != hipSuccess)
-            return VG_ERR_HIP;
+        size_t sets = g->prof.size() / kProfileEvents;
+        ev = &g->prof[kProfileEvents * (size_t)(g->prof_next++ % sets)];
     }
+    auto mark = [&](int k) {
+        if (ev && e == hipSuccess)
+            e = hipEventRecord(ev[k], st);
+    };
+
+    Planes pl;
+    std::memcpy(pl.n, g->n, sizeof pl.n);
+    pl.r = g->r;
+    pl.wx = g->lay.wx;
+    pl.py = g->lay.py;
+    pl.pz = g->lay.pz;
+    pl.seed_pitch = g->lay.seed_pitch;
+    pl.seed = g->scratch + g->lay.seed;
+    pl.bitx = reinterpret_cast<uint32_t *>(g->scratch + g->lay.bitx);
+    pl.occ = reinterpret_cast<uint32_t *>(g->scratch + g->lay.occ);
+    seed_box(g, kind, *sensor, *T, tv, pl.lo, pl.hi);
+    pl.epoch = epoch;
 
     uint32_t *counter = reinterpret_cast<uint32_t *>(g->scratch + g->lay.counter);
-    OccParams op;
-    std::memcpy(op.R, T->R, sizeof op.R);
-    std::memcpy(op.tv, tv, sizeof op.tv);
-    op.s = g->s;
-    std::memcpy(op.n, g->n, sizeof op.n);
-    op.r = g->r;
-    op.kind = kind;
-    op.W = W;
-    op.H = H;
-    op.pitch = pitch_floats;
-    op.fx = sensor->fx;
-    op.fy = sensor->fy;
-    op.cx = sensor->cx;
-    op.cy = sensor->cy;
-    op.dmin = sensor->depth_min;
-    op.dmax = sensor->depth;
-    op.img = data;
-    op.col_tab = sensor->col_tab;
-    op.row_tab = sensor->row_tab;
-    op.loc = g->loc;
-    op.occ = g->scratch + g->lay.occ;
-    op.parked_count = counter;
-    op.epoch = epoch;
-    e = launch_occupied(op, st);
-    if (e == hipSuccess && ev)
-        e = hipEventRecord(ev[1], st);
-    if (e != hipSuccess)
-        return VG_ERR_HIP;
+    SeedParams sp;
+    sp.pl = pl;
+    std::memcpy(sp.R, T->R, sizeof sp.R);
+    std::memcpy(sp.tv, tv, sizeof sp.tv);
+    sp.s = g->s;
+    sp.kind = kind;
+    sp.W = W;
+    sp.H = H;
+    sp.pitch = pitch_floats;
+    sp.fx = sensor->fx;
+    sp.fy = sensor->fy;
+    sp.cx = sensor->cx;
+    sp.cy = sensor->cy;
+    sp.dmin = sensor->depth_min;
+    sp.dmax = sensor->depth;
+    sp.img = data;
+    sp.col_tab = sensor->col_tab;
+    sp.row_tab = sensor->row_tab;
+    sp.parked_count = counter;
 
     RayParams rp;
     std::memcpy(rp.R, T->R, sizeof rp.R);
     std::memcpy(rp.o, o, sizeof rp.o);
     std::memcpy(rp.v0, v0, sizeof rp.v0);
     std::memcpy(rp.n, g->n, sizeof rp.n);
+    rp.wx = g->lay.wx;
     rp.kind = kind == kSpinning ? kSpinning : kPinhole;
     rp.vd = fan.vd;
     rp.hw = fan.hw;
@@ -287,20 +381,27 @@ vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_float
         rp.nb = 2 * fan.hh + 1;
     }
     rp.tiles_a = (rp.na + 7) / 8;
-    int64_t tiles = (int64_t)rp.tiles_a * ((rp.nb + 7) / 8);
-    if (tiles * 64 > (int64_t)0x7fffffff)
-        return VG_ERR_ARG;
     rp.tiles = (int32_t)tiles;
     rp.hz = reinterpret_cast<const int32_t *>(g->scratch + g->lay.hz);
     rp.loc = g->loc;
-    rp.occ = g->scratch + g->lay.occ;
+    rp.occ = pl.occ;
     rp.parked = reinterpret_cast<ParkedRay *>(g->scratch + g->lay.parked);
     rp.parked_count = counter;
     rp.parked_cap = (uint32_t)std::min<size_t>(cap, 0xffffffffu);
-    rp.epoch = epoch;
-    e = launch_rays(rp, st, ev ? ev[2] : nullptr);
-    if (e == hipSuccess && ev)
-        e = hipEventRecord(ev[3], st);
+
+    mark(0);
+    if (e == hipSuccess)
+        e = launch_seeds(sp, st);
+    mark(1);
+    if (e == hipSuccess)
+        e = launch_dilate(pl, st);
+    mark(2);
+    if (e == hipSuccess)
+        e = launch_rays(rp, st, ev ? ev[3] : nullptr);
+    mark(4);
+    if (e == hipSuccess)
+        e = launch_mark_occupied(pl, g->loc, st);
+    mark(5);
     if (e != hipSuccess)
         return VG_ERR_HIP;
     g->epoch = epoch;
@@ -325,14 +426,15 @@ vg_status vg_fan_sizes(const vg_sensor *sensor, float vox_size, int64_t out[4])
     return VG_OK;
 }
 
-size_t vg_scratch_bytes(int32_t gx, int32_t gy, int32_t gz, int64_t max_rays)
+size_t vg_scratch_bytes(int32_t gx, int32_t gy, int32_t gz, int32_t vox_inf, int64_t max_rays)
 {
-    if (gx < 1 || gy < 1 || gz < 1 || max_rays < 0)
+    if (gx < 1 || gy < 1 || gz < 1 || gx > 65535 || gy > 65535 || gz > 65535 || max_rays < 0 ||
+        vox_inf < 0 || vox_inf > kMaxInflation)
         return 0;
     int64_t n = (int64_t)gx * gy * gz;
     if (n >= ((int64_t)1 << 31))
         return 0;
-    return layout_for(n).fixed + align_up((size_t)max_rays * sizeof(ParkedRay));
+    return layout_for(gx, gy, gz, vox_inf).fixed + align_up((size_t)max_rays * sizeof(ParkedRay));
 }
 
 vg_status vg_create_grid(int32_t gx, int32_t gy, int32_t gz, float vox_size,
@@ -346,7 +448,7 @@ vg_status vg_create_grid(int32_t gx, int32_t gy, int32_t gz, float vox_size,
     if (gx < 1 || gy < 1 || gz < 1 || gx > 65535 || gy > 65535 || gz > 65535 ||
         (int64_t)gx * gy * gz >= ((int64_t)1 << 31))
         return VG_ERR_ARG;
-    if (!(vox_size > 0.0f) || !std::isfinite(vox_size) || vox_inf < 0 || vox_inf > 64)
+    if (!(vox_size > 0.0f) || !std::isfinite(vox_size) || vox_inf < 0 || vox_inf > kMaxInflation)
         return VG_ERR_ARG;
     if (!origin_w || !std::isfinite(origin_w[0]) || !std::isfinite(origin_w[1]) ||
         !std::isfinite(origin_w[2]))
@@ -355,7 +457,7 @@ vg_status vg_create_grid(int32_t gx, int32_t gy, int32_t gz, float vox_size,
         ((uintptr_t)scratch % kAlign) != 0)
         return VG_ERR_ARG;
     const int64_t n = (int64_t)gx * gy * gz;
-    Layout lay = layout_for(n);
+    Layout lay = layout_for(gx, gy, gz, vox_inf);
     if (scratch_bytes < lay.fixed)
         return VG_ERR_BUDGET;
 
@@ -495,7 +597,7 @@ vg_status vg_set_profile_events(vg_grid *g, void *const *events, int32_t n_sets)
     if (!g || n_sets < 0 || (n_sets > 0 && !events))
         return VG_ERR_ARG;
     std::vector<hipEvent_t> v;
-    for (int64_t i = 0; i < 4 * (int64_t)n_sets; ++i) {
+    for (int64_t i = 0; i < kProfileEvents * (int64_t)n_sets; ++i) {
         if (!events[i])
             return VG_ERR_ARG;
         v.push_back(static_cast<hipEvent_t>(events[i]));

@@ -1,19 +1,25 @@
 // vg_kernels.hip -- gfx950 kernels for depth-frame -> voxel-grid generation
 // (Toumieh & Lambert, arXiv 2112.13169, Sec. IV).
 //
-// Frame = three launches on one stream:
-//   k_occupied  Alg. 1: one lane per pixel / point: unproject, transform,
-//               quantise, mark the vox_inf cube occupied in the local grid and
-//               stamp it in the per-frame occupancy plane.
-//   k_ray_free  Alg. 2 up to the first occupied voxel: one wavefront per 8x8
-//               tile of fan targets; every voxel walked before the hit becomes
-//               free in the local grid.  Rays that hit park their walk state.
-//   k_ray_traced Alg. 2 after the hit: parked rays continue; the voxels they
-//               walk ("unknown and traced") become unknown in the local grid.
-// Alg. 3 (merge) needs no pass of its own: the three launches write the merged
-// values straight into the local grid, and their stream order gives the
-// merge's priorities (traced beats free; rays never touch occupied voxels).
-// All stores are idempotent byte stores; no atomics on voxels.
+// One frame is a chain of launches on one stream:
+//   k_seed        Alg. 1 lines 2-5: one lane per pixel / point: unproject,
+//                 transform, quantise; stamp the point's voxel in a seed plane
+//                 padded by vox_inf (byte stores of the frame's stamp: no
+//                 clearing between frames, no atomics).
+//   k_dilate_x    Alg. 1 lines 6-9, separably: seeds -> bits dilated by
+//   k_dilate_yz   vox_inf along x, then along y and z.  The union of the
+//                 (2 vox_inf + 1)^3 cubes is exactly this separable dilation.
+//   k_ray_free    Alg. 2 up to the first occupied voxel: one wavefront per 8x8
+//                 tile of fan targets; every voxel walked before the hit
+//                 becomes free in the local grid.  Rays that hit park their
+//                 walk state.  Occupancy words are fetched for 8 walk steps at
+//                 a time so the loads overlap.
+//   k_ray_traced  Alg. 2 after the hit: parked rays continue and mark every
+//                 voxel they walk "unknown and traced" (stored as unknown).
+//   k_mark_occ    the frame's occupied voxels become occupied in the grid.
+// Alg. 3 (merge) needs no pass of its own: the launches write the merged
+// values straight into the local grid and their order gives the merge's
+// priorities (traced beats free, occupied beats both).
 //
 // Floating point: contraction is off (also on the command line) so every fp32
 // operation rounds exactly as written; fp32 division is the correctly rounded
@@ -30,6 +36,7 @@ namespace vg {
 namespace {
 
 constexpr int kBlock = 256;
+constexpr int kChunk = 8;   // walk steps whose occupancy words load together
 
 // ----------------------------------------------------------------- helpers
 
@@ -170,13 +177,10 @@ __device__ __forceinline__ bool walk_step(Walker &w, const int32_t n[3])
     return !((va < 0 && st < 0) || (va >= na && st > 0));
 }
 
-__device__ __forceinline__ bool in_grid(const Walker &w, const int32_t n[3], int64_t &idx)
+__device__ __forceinline__ bool in_grid(const Walker &w, const int32_t n[3])
 {
-    if ((uint32_t)w.vx >= (uint32_t)n[0] || (uint32_t)w.vy >= (uint32_t)n[1] ||
-        (uint32_t)w.vz >= (uint32_t)n[2])
-        return false;
-    idx = (int64_t)w.vx + (int64_t)n[0] * ((int64_t)w.vy + (int64_t)n[1] * w.vz);
-    return true;
+    return (uint32_t)w.vx < (uint32_t)n[0] && (uint32_t)w.vy < (uint32_t)n[1] &&
+           (uint32_t)w.vz < (uint32_t)n[2];
 }
 
 // A ray that starts outside the grid and does not move towards it on that
@@ -195,6 +199,16 @@ __device__ __forceinline__ void ray_direction(const RayParams &p, int32_t tx, in
     dir[0] = row_dot(p.R + 0, x, y, z);
     dir[1] = row_dot(p.R + 3, x, y, z);
     dir[2] = row_dot(p.R + 6, x, y, z);
+}
+
+// Bit j (j < 4) set iff byte j of w equals the byte replicated in rep.
+__device__ __forceinline__ uint32_t byte_eq_mask(uint32_t w, uint32_t rep)
+{
+    uint32_t x = w ^ rep;                                  // zero bytes = matches
+    uint32_t y = (x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu;
+    y = ~(y | x | 0x7F7F7F7Fu);                            // 0x80 exactly in zero bytes
+    uint32_t t = (y >> 7) & 0x01010101u;
+    return (t * 0x01020408u) >> 24;                        // gather the four flags
 }
 
 // ----------------------------------------------------------------- kernels
@@ -217,9 +231,9 @@ __global__ __launch_bounds__(kBlock) void k_fill(uint8_t *dst, uint8_t value, si
     }
 }
 
-// Alg. 1.  Images: block = 64 x 4 pixels, one wavefront per image row
-// segment (coalesced row reads).  Points: 256 points per block.
-__global__ __launch_bounds__(kBlock) void k_occupied(OccParams p)
+// Alg. 1 lines 2-5.  Images: block = 64 x 4 pixels, one wavefront per image
+// row segment (coalesced row reads).  Points: 256 points per block.
+__global__ __launch_bounds__(kBlock) void k_seed(SeedParams p)
 {
     if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
         *p.parked_count = 0;   // the traced pass of this frame starts empty
@@ -261,25 +275,79 @@ __global__ __launch_bounds__(kBlock) void k_occupied(OccParams p)
         }
     }
 
-    int32_t lo[3], hi[3];
+    const Planes &pl = p.pl;
+    int32_t pp[3];
     for (int a = 0; a < 3; ++a) {
         float pv = row_dot(p.R + 3 * a, pc[0], pc[1], pc[2]) + p.tv[a];
         float q = floorf(pv / p.s);
-        if (!(q >= (float)(-p.r) && q <= (float)(p.n[a] - 1 + p.r)))
-            return;   // the cube cannot reach the grid
-        int32_t qi = (int32_t)q;
-        lo[a] = max(qi - p.r, 0);
-        hi[a] = min(qi + p.r, p.n[a] - 1);
+        // the cube cannot reach the grid: drop the point
+        if (!(q >= (float)(-pl.r) && q <= (float)(pl.n[a] - 1 + pl.r)))
+            return;
+        pp[a] = (int32_t)q + pl.r;   // padded coordinate
     }
-    const uint8_t stamp = (uint8_t)p.epoch;
-    for (int32_t z = lo[2]; z <= hi[2]; ++z)
-        for (int32_t y = lo[1]; y <= hi[1]; ++y) {
-            int64_t row = ((int64_t)z * p.n[1] + y) * p.n[0];
-            for (int32_t x = lo[0]; x <= hi[0]; ++x) {
-                p.occ[row + x] = stamp;
-                p.loc[row + x] = kOccupied;
-            }
+    pl.seed[(int64_t)pl.seed_pitch * (pp[1] + (int64_t)pl.py * pp[2]) + pp[0]] =
+        (uint8_t)pl.epoch;
+}
+
+// Seeds -> bits dilated along x.  One lane per 32-voxel word of a padded row
+// inside the seed box; output voxel x is set iff a seed lies at padded
+// x .. x + 2r of the same padded row.
+__global__ __launch_bounds__(kBlock) void k_dilate_x(Planes pl)
+{
+    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int32_t ny = pl.hi[1] - pl.lo[1] + 1;
+    const int32_t nz = pl.hi[2] - pl.lo[2] + 1;
+    if (gid >= (int64_t)pl.wx * ny * nz)
+        return;
+    const int32_t w = (int32_t)(gid % pl.wx);
+    const int64_t row = gid / pl.wx;
+    const int32_t y = pl.lo[1] + (int32_t)(row % ny);
+    const int32_t z = pl.lo[2] + (int32_t)(row / ny);
+    const int32_t x0 = 32 * w;
+    uint32_t out = 0;
+    if (x0 <= pl.hi[0] && x0 + 31 + 2 * pl.r >= pl.lo[0]) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(
+            pl.seed + (int64_t)pl.seed_pitch * (y + (int64_t)pl.py * z) + x0);
+        const uint32_t rep = (pl.epoch & 0xFFu) * 0x01010101u;
+        uint64_t m = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            uint4 q = src[k];
+            uint32_t b = byte_eq_mask(q.x, rep) | (byte_eq_mask(q.y, rep) << 4) |
+                         (byte_eq_mask(q.z, rep) << 8) | (byte_eq_mask(q.w, rep) << 12);
+            m |= (uint64_t)b << (16 * k);
         }
+        uint64_t acc = m;
+        for (int d = 1; d <= 2 * pl.r; ++d)
+            acc |= m >> d;
+        out = (uint32_t)acc;
+        const int32_t valid = pl.n[0] - x0;   // output voxels of this word inside the grid
+        if (valid < 32)
+            out &= (1u << valid) - 1u;
+    }
+    pl.bitx[(int64_t)pl.wx * (y + (int64_t)pl.py * z) + w] = out;
+}
+
+// x-dilated rows -> occupied bit plane: OR over the (2r+1) x (2r+1) padded
+// rows y .. y+2r, z .. z+2r.  Every word of the plane is written.
+__global__ __launch_bounds__(kBlock) void k_dilate_yz(Planes pl)
+{
+    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (gid >= (int64_t)pl.wx * pl.n[1] * pl.n[2])
+        return;
+    const int32_t w = (int32_t)(gid % pl.wx);
+    const int64_t row = gid / pl.wx;
+    const int32_t y = (int32_t)(row % pl.n[1]);
+    const int32_t z = (int32_t)(row / pl.n[1]);
+    const int32_t y0 = max(y, pl.lo[1]), y1 = min(y + 2 * pl.r, pl.hi[1]);
+    const int32_t z0 = max(z, pl.lo[2]), z1 = min(z + 2 * pl.r, pl.hi[2]);
+    uint32_t out = 0;
+    for (int32_t zz = z0; zz <= z1; ++zz) {
+        const uint32_t *src = pl.bitx + (int64_t)pl.wx * ((int64_t)pl.py * zz) + w;
+        for (int32_t yy = y0; yy <= y1; ++yy)
+            out |= src[(int64_t)pl.wx * yy];
+    }
+    pl.occ[gid] = out;
 }
 
 // Alg. 2 before the first occupied voxel.
@@ -297,19 +365,49 @@ __global__ __launch_bounds__(kBlock) void k_ray_free(RayParams p)
         float dir[3];
         ray_direction(p, tx, ty, tz, dir);
         walker_setup(w, p.o, p.v0, dir);
-        if (!never_enters(w, p.n)) {
-            const uint8_t stamp = (uint8_t)p.epoch;
-            while (w.d2 < m2) {
-                if (!walk_step(w, p.n))
-                    break;
-                int64_t idx;
-                if (in_grid(w, p.n, idx)) {
-                    if (p.occ[idx] == stamp) {
-                        park = w.d2 < m2;   // anything left to walk after the hit?
-                        break;
+        bool more = !never_enters(w, p.n);
+        while (more) {
+            const Walker snap = w;
+            uint32_t widx[kChunk], lidx[kChunk], bit[kChunk];
+            bool val[kChunk];
+#pragma unroll
+            for (int s = 0; s < kChunk; ++s) {
+                val[s] = false;
+                widx[s] = lidx[s] = bit[s] = 0;
+                if (more) {
+                    if (w.d2 < m2 && walk_step(w, p.n)) {
+                        if (in_grid(w, p.n)) {
+                            val[s] = true;
+                            uint32_t row = (uint32_t)w.vy + (uint32_t)p.n[1] * (uint32_t)w.vz;
+                            widx[s] = ((uint32_t)w.vx >> 5) + (uint32_t)p.wx * row;
+                            bit[s] = (uint32_t)w.vx & 31u;
+                            lidx[s] = (uint32_t)w.vx + (uint32_t)p.n[0] * row;
+                        }
+                    } else {
+                        more = false;
                     }
-                    p.loc[idx] = kFree;
                 }
+            }
+            uint32_t word[kChunk];
+#pragma unroll
+            for (int s = 0; s < kChunk; ++s)
+                word[s] = val[s] ? p.occ[widx[s]] : 0u;
+            int hit = kChunk;
+#pragma unroll
+            for (int s = kChunk - 1; s >= 0; --s)
+                if ((word[s] >> bit[s]) & 1u)
+                    hit = s;
+#pragma unroll
+            for (int s = 0; s < kChunk; ++s)
+                if (val[s] && s < hit)
+                    p.loc[lidx[s]] = kFree;
+            if (hit < kChunk) {
+                // replay the walk up to and including the hit voxel
+                w = snap;
+                for (int s = 0; s <= hit; ++s)
+                    walk_step(w, p.n);
+                park = w.d2 < m2;   // anything left to walk after the hit?
+                break;
             }
         }
     }
@@ -341,7 +439,8 @@ __global__ __launch_bounds__(kBlock) void k_ray_free(RayParams p)
 }
 
 // Alg. 2 after the hit: continue each parked ray, marking "unknown and
-// traced" (stored as unknown) on every non-occupied voxel it walks.
+// traced" (stored as unknown) on every voxel it walks.  Occupied voxels are
+// restored by k_mark_occ afterwards, so this pass needs no loads.
 __global__ __launch_bounds__(kBlock) void k_ray_traced(RayParams p)
 {
     const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
@@ -366,13 +465,35 @@ __global__ __launch_bounds__(kBlock) void k_ray_traced(RayParams p)
     w.cy = abs(w.vy - p.v0[1]);
     w.cz = abs(w.vz - p.v0[2]);
     w.d2 = w.cx * w.cx + w.cy * w.cy + w.cz * w.cz;
-    const uint8_t stamp = (uint8_t)p.epoch;
     while (w.d2 < m2) {
         if (!walk_step(w, p.n))
             break;
-        int64_t idx;
-        if (in_grid(w, p.n, idx) && p.occ[idx] != stamp)
-            p.loc[idx] = kUnknown;
+        if (in_grid(w, p.n))
+            p.loc[(uint32_t)w.vx + (uint32_t)p.n[0] * ((uint32_t)w.vy +
+                                                        (uint32_t)p.n[1] * (uint32_t)w.vz)] =
+                kUnknown;
+    }
+}
+
+// The frame's occupied voxels become occupied in the local grid.  One lane
+// per occupancy word of the rows the seed box can reach.
+__global__ __launch_bounds__(kBlock) void k_mark_occ(Planes pl, uint8_t *loc, int32_t y0,
+                                                     int32_t ny, int32_t z0, int32_t nz)
+{
+    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (gid >= (int64_t)pl.wx * ny * nz)
+        return;
+    const int32_t w = (int32_t)(gid % pl.wx);
+    const int64_t row = gid / pl.wx;
+    const int32_t y = y0 + (int32_t)(row % ny);
+    const int32_t z = z0 + (int32_t)(row / ny);
+    const int64_t r = y + (int64_t)pl.n[1] * z;
+    uint32_t m = pl.occ[(int64_t)pl.wx * r + w];
+    uint8_t *dst = loc + (int64_t)pl.n[0] * r + 32 * w;
+    while (m) {
+        int b = __ffs(m) - 1;
+        dst[b] = kOccupied;
+        m &= m - 1u;
     }
 }
 
@@ -392,6 +513,8 @@ __global__ __launch_bounds__(kBlock) void k_shift(const uint8_t *src, uint8_t *d
     dst[((int64_t)z * ny + y) * nx + x] = val;
 }
 
+uint32_t blocks_for(int64_t threads) { return (uint32_t)((threads + kBlock - 1) / kBlock); }
+
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
@@ -402,20 +525,34 @@ hipError_t launch_fill(void *dst, uint8_t value, size_t bytes, hipStream_t st)
         return hipSuccess;
     uintptr_t base = (uintptr_t)dst & ~(uintptr_t)15;
     size_t chunks = ((uintptr_t)dst + bytes - base + 15) / 16;
-    size_t blocks = (chunks + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_fill, dim3((uint32_t)blocks), dim3(kBlock), 0, st, (uint8_t *)dst, value,
-                       bytes);
+    hipLaunchKernelGGL(k_fill, dim3(blocks_for((int64_t)chunks)), dim3(kBlock), 0, st,
+                       (uint8_t *)dst, value, bytes);
     return hipGetLastError();
 }
 
-hipError_t launch_occupied(const OccParams &p, hipStream_t st)
+hipError_t launch_seeds(const SeedParams &p, hipStream_t st)
 {
     dim3 grid;
     if (p.kind == kPoints)
-        grid = dim3((uint32_t)std::max<int64_t>(((int64_t)p.W + kBlock - 1) / kBlock, 1), 1);
+        grid = dim3(std::max<uint32_t>(blocks_for(p.W), 1u), 1);
     else
         grid = dim3((uint32_t)std::max((p.W + 63) / 64, 1), (uint32_t)std::max((p.H + 3) / 4, 1));
-    hipLaunchKernelGGL(k_occupied, grid, dim3(kBlock), 0, st, p);
+    hipLaunchKernelGGL(k_seed, grid, dim3(kBlock), 0, st, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_dilate(const Planes &pl, hipStream_t st)
+{
+    const bool any = pl.lo[0] <= pl.hi[0] && pl.lo[1] <= pl.hi[1] && pl.lo[2] <= pl.hi[2];
+    if (any) {
+        int64_t n = (int64_t)pl.wx * (pl.hi[1] - pl.lo[1] + 1) * (pl.hi[2] - pl.lo[2] + 1);
+        hipLaunchKernelGGL(k_dilate_x, dim3(blocks_for(n)), dim3(kBlock), 0, st, pl);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    int64_t n = (int64_t)pl.wx * pl.n[1] * pl.n[2];
+    hipLaunchKernelGGL(k_dilate_yz, dim3(blocks_for(n)), dim3(kBlock), 0, st, pl);
     return hipGetLastError();
 }
 
@@ -431,8 +568,21 @@ hipError_t launch_rays(const RayParams &p, hipStream_t st, hipEvent_t mid)
         e = hipEventRecord(mid, st);
     if (e != hipSuccess)
         return e;
-    uint32_t tblocks = (uint32_t)(((uint64_t)p.tiles * 64 + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_ray_traced, dim3(tblocks), dim3(kBlock), 0, st, p);
+    hipLaunchKernelGGL(k_ray_traced, dim3(blocks_for((int64_t)p.tiles * 64)), dim3(kBlock), 0,
+                       st, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_mark_occupied(const Planes &pl, uint8_t *loc, hipStream_t st)
+{
+    // output rows y with a seed row in y .. y + 2r inside the box
+    const int32_t y0 = std::max(pl.lo[1] - 2 * pl.r, 0), y1 = std::min(pl.hi[1], pl.n[1] - 1);
+    const int32_t z0 = std::max(pl.lo[2] - 2 * pl.r, 0), z1 = std::min(pl.hi[2], pl.n[2] - 1);
+    if (pl.lo[0] > pl.hi[0] || y0 > y1 || z0 > z1)
+        return hipSuccess;
+    int64_t n = (int64_t)pl.wx * (y1 - y0 + 1) * (z1 - z0 + 1);
+    hipLaunchKernelGGL(k_mark_occ, dim3(blocks_for(n)), dim3(kBlock), 0, st, pl, loc, y0,
+                       y1 - y0 + 1, z0, z1 - z0 + 1);
     return hipGetLastError();
 }
 

@@ -17,6 +17,8 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "vg.h")
 VG_OK, VG_ERR_ARG, VG_ERR_HIP, VG_ERR_BUDGET, VG_ERR_STATE = 0, -1, -2, -3, -4
 VG_UNKNOWN, VG_FREE, VG_OCCUPIED = 0, 1, 2
 VG_PINHOLE, VG_SPINNING = 0, 1
+PROFILE_EVENTS = 6   # events per frame of vg_set_profile_events
+PROFILE_STAGES = ("seed", "dilate", "ray_free", "ray_traced", "mark_occ")
 
 
 class VgError(RuntimeError):
@@ -55,7 +57,7 @@ def lib():
         sp = ctypes.POINTER(vg_sensor)
         pp = ctypes.POINTER(vg_pose)
         L.vg_fan_sizes.argtypes = [sp, f32, P]
-        L.vg_scratch_bytes.argtypes = [i32, i32, i32, i64]
+        L.vg_scratch_bytes.argtypes = [i32, i32, i32, i32, i64]
         L.vg_scratch_bytes.restype = ctypes.c_size_t
         L.vg_create_grid.argtypes = [i32, i32, i32, f32, P, i32, P, P, P, ctypes.c_size_t, P,
                                      ctypes.POINTER(P)]
@@ -140,8 +142,8 @@ def vg_fan_sizes(sensor, vox_size):
     return tuple(int(v) for v in out)
 
 
-def vg_scratch_bytes(gx, gy, gz, max_rays):
-    return int(lib().vg_scratch_bytes(gx, gy, gz, max_rays))
+def vg_scratch_bytes(gx, gy, gz, vox_inf, max_rays):
+    return int(lib().vg_scratch_bytes(gx, gy, gz, vox_inf, max_rays))
 
 
 def vg_create_grid(dims, vox_size, origin_w, vox_inf, loc, spare, scratch, stream=None):
@@ -198,17 +200,18 @@ def vg_write_grid(g, src, stream=None):
 
 
 def vg_set_profile_events(g, events):
-    """events: list of torch.cuda.Event (enable_timing=True), 4 per set; [] off.
+    """events: list of torch.cuda.Event (enable_timing=True), 6 per set; [] off.
     Each event is recorded once on the current device before its handle is
     passed on."""
     n = len(events)
-    assert n % 4 == 0
+    assert n % PROFILE_EVENTS == 0
     arr = (ctypes.c_void_p * max(n, 1))()
     for i, e in enumerate(events):
         if not e.cuda_event:
             e.record()          # torch creates the hipEvent_t lazily
         arr[i] = e.cuda_event
-    _check(lib().vg_set_profile_events(g, arr if n else None, n // 4), "vg_set_profile_events")
+    _check(lib().vg_set_profile_events(g, arr if n else None, n // PROFILE_EVENTS),
+           "vg_set_profile_events")
 
 
 def vg_destroy_grid(g):
@@ -219,16 +222,16 @@ def vg_destroy_grid(g):
 
 class GridBuffers:
     """Device buffers one grid needs, allocated with torch (the library itself
-    never allocates): loc, spare and scratch sized for `max_rays`."""
+    never allocates): loc, spare and scratch sized for vox_inf and `max_rays`."""
 
-    def __init__(self, dims, max_rays, device="cuda"):
+    def __init__(self, dims, vox_inf, max_rays, device="cuda"):
         import torch
         gx, gy, gz = dims
         n = gx * gy * gz
         self.dims = tuple(dims)
         self.loc = torch.empty(n, dtype=torch.uint8, device=device)
         self.spare = torch.empty(n, dtype=torch.uint8, device=device)
-        nbytes = vg_scratch_bytes(gx, gy, gz, max_rays)
+        nbytes = vg_scratch_bytes(gx, gy, gz, vox_inf, max_rays)
         if nbytes == 0:
             raise ValueError("invalid grid size")
         self.scratch = torch.empty(nbytes, dtype=torch.uint8, device=device)

@@ -28,7 +28,7 @@ class GpuGrid:
     def __init__(self, dims, vox_size, origin, vox_inf, max_rays, init=None):
         self.dims = tuple(dims)
         gx, gy, gz = dims
-        self.buf = vg.GridBuffers(dims, max_rays)
+        self.buf = vg.GridBuffers(dims, vox_inf, max_rays)
         self.h = vg.vg_create_grid(dims, vox_size, origin, vox_inf, self.buf.loc, self.buf.spare,
                                    self.buf.scratch)
         self.vox_size = np.float32(vox_size)
