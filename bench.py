@@ -93,7 +93,7 @@ def main():
     nvox = gx * gy * gz
 
     def new_grid():
-        buf = vg.GridBuffers(fr0.dims, fr0.vox_inf, rays)
+        buf = vg.GridBuffers(fr0.dims, fr0.vox_inf)
         h = vg.vg_create_grid(fr0.dims, fr0.vox_size, fr0.origin, fr0.vox_inf, buf.loc, buf.spare,
                               buf.scratch)
         return buf, h
@@ -198,8 +198,8 @@ def main():
 
     kernels = {k: float(v.mean()) for k, v in stage_ms.items()}
     dominant = max(kernels, key=kernels.get)
-    if dominant in ("k_ray_free", "k_ray_traced"):
-        units = before.mean() if dominant == "k_ray_free" else after.mean()
+    if dominant == "k_rays":
+        units = walk.mean()
         achieved = units * OPS_PER_STEP / (kernels[dominant] * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 1),
                 "unit": "TOP/s", "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None,
@@ -210,7 +210,7 @@ def main():
         nbytes = {"k_shift": 2.0 * nvox,                   # read + write the grid
                   "k_seed": 5.0 * fr0.depth.size,           # depth in, stamp out
                   "k_dilate": nvox / 8.0 * 2 + nvox,        # seeds in, bit planes out
-                  "k_mark_occ": nvox / 8.0 + upd.mean()}[dominant]
+                  "k_resolve": nvox * (1 + 1 / 8.0) + 2.0 * upd.mean()}[dominant]
         achieved = nbytes / (kernels[dominant] * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,

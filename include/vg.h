@@ -21,9 +21,12 @@
  *  - Errors: argument errors are detected before any device work is enqueued,
  *    return VG_ERR_ARG and leave the grid unchanged.  HIP launch / copy errors
  *    return VG_ERR_HIP.  Nothing throws across the ABI.
- *  - Layout: grids are uint8[grid_size_z][grid_size_y][grid_size_x] with the
- *    paper's linear index idx = x + y*grid_size_x + z*grid_size_x*grid_size_y
- *    (Sec. IV-D); grid axes are aligned with the world (ENU) frame.
+ *  - Layout: vg_read_grid / vg_write_grid exchange grids as
+ *    uint8[grid_size_z][grid_size_y][grid_size_x] with the paper's linear index
+ *    idx = x + y*grid_size_x + z*grid_size_x*grid_size_y (Sec. IV-D); grid
+ *    axes are aligned with the world (ENU) frame.  The device buffers bound to
+ *    a grid hold it with rows padded to a multiple of 32 voxels (row pitch
+ *    32*ceil(grid_size_x/32) bytes); their content is for the library only.
  *  - Voxel values: VG_UNKNOWN 0, VG_FREE 1, VG_OCCUPIED 2.  Other byte values
  *    written by vg_write_grid are kept until a frame overwrites them.
  */
@@ -43,7 +46,7 @@ typedef int32_t vg_status;
 #define VG_OK 0
 #define VG_ERR_ARG (-1)    /* invalid argument; nothing was enqueued          */
 #define VG_ERR_HIP (-2)    /* a HIP runtime call failed                       */
-#define VG_ERR_BUDGET (-3) /* the scratch workspace is too small              */
+#define VG_ERR_BUDGET (-3) /* a caller buffer is smaller than required         */
 #define VG_ERR_STATE (-4)  /* handle used on a different device than created  */
 
 #define VG_UNKNOWN 0
@@ -91,26 +94,31 @@ typedef struct vg_sensor {
  * (vox_depth > 16384, half sizes > 16384). */
 vg_status vg_fan_sizes(const vg_sensor *sensor, float vox_size, int64_t out[4]);
 
-/* Bytes of device scratch a grid of this size and vox_inf needs to integrate
- * frames from sensors with up to `max_rays` rays (vg_fan_sizes out[3]).
- * Host-only; 0 for invalid sizes. */
+/* Bytes of each of the two device grid buffers (local grid and its spare)
+ * of a grid of this size.  Host-only; 0 for invalid sizes. */
+size_t vg_grid_bytes(int32_t grid_size_x, int32_t grid_size_y, int32_t grid_size_z);
+
+/* Bytes of device scratch workspace a grid of this size and vox_inf needs
+ * (per-frame stamp and bit planes).  Host-only; 0 for invalid sizes. */
 size_t vg_scratch_bytes(int32_t grid_size_x, int32_t grid_size_y, int32_t grid_size_z,
-                        int32_t vox_inf, int64_t max_rays);
+                        int32_t vox_inf);
 
 /* Step 1 (Sec. IV-A): bind caller buffers to a new grid and set every voxel
  * of loc_grid to unknown (enqueued on `stream`).
- *   loc_grid, loc_spare: device, grid_size_x*y*z bytes each, distinct.  The
- *     spare buffer receives shifted grids (vg_shift_grid swaps the two).
- *   scratch: device, scratch_bytes >= vg_scratch_bytes(.., vox_inf, max_rays), 256-byte
+ *   loc_grid, loc_spare: device, distinct, 16-byte aligned, grid_bytes >=
+ *     vg_grid_bytes(...) bytes each.  The spare buffer receives shifted grids
+ *     (vg_shift_grid swaps the two).
+ *   scratch: device, scratch_bytes >= vg_scratch_bytes(..., vox_inf), 256-byte
  *     aligned; it is cleared here and owned by the grid until destroyed.
  *   origin_w: world position (m) of the grid corner (voxel (0,0,0)'s minimum
  *     corner); vox_size > 0 m; vox_inf in [0, 16] voxels of inflation.
- *   Dimensions in [1, 65535] with grid_size_x*y*z < 2^31.
+ *   Dimensions in [1, 65535] with vg_grid_bytes(...) < 2^31.
+ * Returns VG_ERR_BUDGET if grid_bytes or scratch_bytes is too small.
  * On success *out receives the handle. */
 vg_status vg_create_grid(int32_t grid_size_x, int32_t grid_size_y, int32_t grid_size_z,
                          float vox_size, const float origin_w[3], int32_t vox_inf,
-                         uint8_t *loc_grid, uint8_t *loc_spare, void *scratch,
-                         size_t scratch_bytes, void *stream, vg_grid **out);
+                         uint8_t *loc_grid, uint8_t *loc_spare, size_t grid_bytes,
+                         void *scratch, size_t scratch_bytes, void *stream, vg_grid **out);
 
 /* Steps 2-4 (Alg. 1, 2, 3) for one frame, enqueued on `stream`:
  *   depth: device, sensor->height rows of sensor->width float32, rows
@@ -156,11 +164,10 @@ vg_status vg_write_grid(vg_grid *g, const uint8_t *src, int32_t src_is_device, v
 
 /* Measurement hook.  With n_sets > 0, each following vg_integrate_frame /
  * vg_integrate_points call k records the caller's events (hipEvent_t)
- * events[6*j + 0..5], j = k mod n_sets, on its stream: before the seed pass,
- * after it, after the dilation, after the free pass, after the traced pass
- * and after the occupied marking, so that event pairs time each stage.  The
- * array is copied; the events must stay alive while set.  n_sets = 0 (events
- * may be NULL) turns recording off. */
+ * events[5*j + 0..4], j = k mod n_sets, on its stream: before the seed pass,
+ * after it, after the dilation, after the ray walk and after the resolve pass,
+ * so that event pairs time each stage.  The array is copied; the events must
+ * stay alive while set.  n_sets = 0 (events may be NULL) turns recording off. */
 vg_status vg_set_profile_events(vg_grid *g, void *const *events, int32_t n_sets);
 
 /* Release the handle (host metadata only; caller buffers are untouched).

@@ -24,31 +24,30 @@ constexpr size_t kHzBytes = (size_t)8 * kMaxFan * sizeof(int32_t);
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Scratch layout (all offsets 256-aligned):
-//   counter   parked-ray counter
 //   seed      seed stamps on the grid padded by vox_inf, rows of seed_pitch bytes
 //   bitx      seeds dilated along x, one 32-bit word per 32 voxels of a padded row
-//   occ       occupied voxels of the frame, one bit per voxel
+//   occ       occupied voxels of the frame, one bit per device-layout voxel
+//   traced    "unknown and traced" stamps, one byte per device-layout voxel
 //   hz        spinning fan: half height per ring column
-//   parked    parked rays, 32 bytes each, up to the end of the workspace
 struct Layout {
-    int32_t wx, py, pz, seed_pitch;
-    size_t counter, seed, bitx, occ, hz, parked, fixed;
+    int32_t gxp, wx, py, pz, seed_pitch;
+    size_t seed, bitx, occ, traced, hz, fixed;
 };
 
 Layout layout_for(int32_t gx, int32_t gy, int32_t gz, int32_t r)
 {
     Layout l;
-    l.wx = (gx + 31) / 32;
+    l.gxp = grid_pitch(gx);
+    l.wx = l.gxp / 32;
     l.py = gy + 2 * r;
     l.pz = gz + 2 * r;
     l.seed_pitch = (32 * l.wx + 64 + 63) / 64 * 64;
-    l.counter = 0;
-    l.seed = kAlign;
+    l.seed = 0;
     l.bitx = l.seed + align_up((size_t)l.seed_pitch * l.py * l.pz);
     l.occ = l.bitx + align_up((size_t)4 * l.wx * l.py * l.pz);
-    l.hz = l.occ + align_up((size_t)4 * l.wx * gy * gz);
-    l.parked = l.hz + kHzBytes;
-    l.fixed = l.parked;
+    l.traced = l.occ + align_up((size_t)4 * l.wx * gy * gz);
+    l.hz = l.traced + align_up((size_t)l.gxp * gy * gz);
+    l.fixed = l.hz + kHzBytes;
     return l;
 }
 
@@ -151,7 +150,7 @@ struct vg_grid {
 
 namespace {
 
-constexpr int kProfileEvents = 6;
+constexpr int kProfileEvents = 5;
 
 vg_status hip_status(hipError_t e) { return e == hipSuccess ? VG_OK : VG_ERR_HIP; }
 
@@ -261,6 +260,61 @@ void seed_box(const vg_grid *g, int kind, const vg_sensor &s, const vg_pose &T,
     }
 }
 
+// Rows of the grid the ray fan can reach: the fan is the pyramid with apex at
+// the camera and the targets as base (a ball of radius vox_depth for a
+// spinning fan); a walk ends within one voxel of its target's length, and
+// every voxel it visits touches the ray.  The box of the pyramid scaled by
+// (1 + 3 / vox_depth), widened by 3 voxels, holds all of them.
+RowBox fan_rows(const vg_grid *g, int kind, const Fan &fan, const vg_pose &T, const float o[3])
+{
+    double lo[3], hi[3];
+    for (int a = 0; a < 3; ++a)
+        lo[a] = hi[a] = (double)o[a];
+    if (kind == kSpinning) {
+        for (int a = 0; a < 3; ++a) {
+            lo[a] -= fan.vd + 3.0;
+            hi[a] += fan.vd + 3.0;
+        }
+    } else {
+        const double k = 1.0 + 3.0 / fan.vd;
+        for (int sa = -1; sa <= 1; sa += 2)
+            for (int sb = -1; sb <= 1; sb += 2) {
+                const double t[3] = {(double)sa * fan.hw * k, (double)sb * fan.hh * k,
+                                     (double)fan.vd * k};
+                for (int a = 0; a < 3; ++a) {
+                    double c = (double)o[a];
+                    for (int j = 0; j < 3; ++j)
+                        c += (double)T.R[3 * a + j] * t[j];
+                    lo[a] = std::min(lo[a], c);
+                    hi[a] = std::max(hi[a], c);
+                }
+            }
+        for (int a = 0; a < 3; ++a) {
+            lo[a] -= 3.0;
+            hi[a] += 3.0;
+        }
+    }
+    RowBox b;
+    b.y0 = (int32_t)std::max(std::floor(lo[1]), 0.0);
+    b.y1 = (int32_t)std::min(std::floor(hi[1]), (double)(g->n[1] - 1));
+    b.z0 = (int32_t)std::max(std::floor(lo[2]), 0.0);
+    b.z1 = (int32_t)std::min(std::floor(hi[2]), (double)(g->n[2] - 1));
+    if (std::floor(hi[0]) < 0.0 || std::floor(lo[0]) > g->n[0] - 1)
+        b.y0 = 1, b.y1 = 0;
+    return b;
+}
+
+RowBox row_union(const RowBox &a, const RowBox &b)
+{
+    const bool ea = a.y0 > a.y1 || a.z0 > a.z1, eb = b.y0 > b.y1 || b.z0 > b.z1;
+    if (ea)
+        return b;
+    if (eb)
+        return a;
+    return RowBox{std::min(a.y0, b.y0), std::max(a.y1, b.y1), std::min(a.z0, b.z0),
+                  std::max(a.z1, b.z1)};
+}
+
 // Common part of steps 2-4: per-frame constants, stamp, launches.
 vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_floats, int32_t W,
                     int32_t H, const vg_sensor *sensor, const vg_pose *T, hipStream_t st)
@@ -283,22 +337,21 @@ vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_float
             return VG_ERR_ARG;
         v0[a] = (int32_t)std::floor(o[a]);
     }
-
     // fan tiles of 8 x 8 targets, one wavefront each
     const int32_t fan_a = kind == kSpinning ? 8 * fan.vd : 2 * fan.hw + 1;
-    const int64_t tiles = (int64_t)((fan_a + 7) / 8) * ((2 * fan.hh + 1 + 7) / 8);
+    const int32_t fan_b = 2 * fan.hh + 1;
+    const int64_t tiles = (int64_t)((fan_a + 7) / 8) * ((fan_b + 7) / 8);
     if (tiles * 64 > (int64_t)0x7fffffff)
         return VG_ERR_ARG;
-    size_t cap = (g->scratch_bytes - g->lay.fixed) / sizeof(ParkedRay);
-    if ((int64_t)cap < fan.rays)
-        return VG_ERR_BUDGET;
     if (!same_device(g))
         return VG_ERR_STATE;
 
-    // Per-frame seed stamp 1..255; the seed plane is cleared when it wraps.
+    // Per-frame stamp 1..255; the stamp planes are cleared when it wraps.
     hipError_t e = hipSuccess;
     if (g->epoch == 255) {
         e = launch_fill(g->scratch + g->lay.seed, 0, g->lay.bitx - g->lay.seed, st);
+        if (e == hipSuccess)
+            e = launch_fill(g->scratch + g->lay.traced, 0, g->lay.hz - g->lay.traced, st);
         if (e != hipSuccess)
             return VG_ERR_HIP;
         g->epoch = 0;
@@ -339,10 +392,10 @@ vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_float
     pl.seed = g->scratch + g->lay.seed;
     pl.bitx = reinterpret_cast<uint32_t *>(g->scratch + g->lay.bitx);
     pl.occ = reinterpret_cast<uint32_t *>(g->scratch + g->lay.occ);
+    pl.traced = g->scratch + g->lay.traced;
     seed_box(g, kind, *sensor, *T, tv, pl.lo, pl.hi);
     pl.epoch = epoch;
 
-    uint32_t *counter = reinterpret_cast<uint32_t *>(g->scratch + g->lay.counter);
     SeedParams sp;
     sp.pl = pl;
     std::memcpy(sp.R, T->R, sizeof sp.R);
@@ -361,33 +414,36 @@ vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_float
     sp.img = data;
     sp.col_tab = sensor->col_tab;
     sp.row_tab = sensor->row_tab;
-    sp.parked_count = counter;
 
     RayParams rp;
     std::memcpy(rp.R, T->R, sizeof rp.R);
     std::memcpy(rp.o, o, sizeof rp.o);
     std::memcpy(rp.v0, v0, sizeof rp.v0);
     std::memcpy(rp.n, g->n, sizeof rp.n);
-    rp.wx = g->lay.wx;
+    rp.gxp = g->lay.gxp;
     rp.kind = kind == kSpinning ? kSpinning : kPinhole;
     rp.vd = fan.vd;
     rp.hw = fan.hw;
     rp.hh = fan.hh;
-    if (kind == kSpinning) {
-        rp.na = 8 * fan.vd;
-        rp.nb = 2 * fan.hh + 1;
-    } else {
-        rp.na = 2 * fan.hw + 1;
-        rp.nb = 2 * fan.hh + 1;
-    }
-    rp.tiles_a = (rp.na + 7) / 8;
+    rp.na = fan_a;
+    rp.nb = fan_b;
+    rp.tiles_a = (fan_a + 7) / 8;
     rp.tiles = (int32_t)tiles;
     rp.hz = reinterpret_cast<const int32_t *>(g->scratch + g->lay.hz);
     rp.loc = g->loc;
     rp.occ = pl.occ;
-    rp.parked = reinterpret_cast<ParkedRay *>(g->scratch + g->lay.parked);
-    rp.parked_count = counter;
-    rp.parked_cap = (uint32_t)std::min<size_t>(cap, 0xffffffffu);
+    rp.traced = pl.traced;
+    rp.epoch = epoch;
+    const bool inside = v0[0] >= 0 && v0[0] < g->n[0] && v0[1] >= 0 && v0[1] < g->n[1] &&
+                        v0[2] >= 0 && v0[2] < g->n[2];
+
+    // rows holding occupied voxels (seed box minus padding, widened by the
+    // inflation) or traced stamps (the fan's reach)
+    RowBox seed_rows{1, 0, 1, 0};
+    if (pl.lo[0] <= pl.hi[0])
+        seed_rows = RowBox{std::max(pl.lo[1] - 2 * pl.r, 0), std::min(pl.hi[1], g->n[1] - 1),
+                           std::max(pl.lo[2] - 2 * pl.r, 0), std::min(pl.hi[2], g->n[2] - 1)};
+    const RowBox rows = row_union(seed_rows, fan_rows(g, kind, fan, *T, o));
 
     mark(0);
     if (e == hipSuccess)
@@ -397,11 +453,11 @@ vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_float
         e = launch_dilate(pl, st);
     mark(2);
     if (e == hipSuccess)
-        e = launch_rays(rp, st, ev ? ev[3] : nullptr);
-    mark(4);
+        e = launch_rays(rp, inside, st);
+    mark(3);
     if (e == hipSuccess)
-        e = launch_mark_occupied(pl, g->loc, st);
-    mark(5);
+        e = launch_resolve(pl, g->loc, rows, st);
+    mark(4);
     if (e != hipSuccess)
         return VG_ERR_HIP;
     g->epoch = epoch;
@@ -426,27 +482,31 @@ vg_status vg_fan_sizes(const vg_sensor *sensor, float vox_size, int64_t out[4])
     return VG_OK;
 }
 
-size_t vg_scratch_bytes(int32_t gx, int32_t gy, int32_t gz, int32_t vox_inf, int64_t max_rays)
+size_t vg_grid_bytes(int32_t gx, int32_t gy, int32_t gz)
 {
-    if (gx < 1 || gy < 1 || gz < 1 || gx > 65535 || gy > 65535 || gz > 65535 || max_rays < 0 ||
-        vox_inf < 0 || vox_inf > kMaxInflation)
+    if (gx < 1 || gy < 1 || gz < 1 || gx > 65535 || gy > 65535 || gz > 65535)
         return 0;
-    int64_t n = (int64_t)gx * gy * gz;
-    if (n >= ((int64_t)1 << 31))
+    if ((int64_t)grid_pitch(gx) * gy * gz >= ((int64_t)1 << 31))
         return 0;
-    return layout_for(gx, gy, gz, vox_inf).fixed + align_up((size_t)max_rays * sizeof(ParkedRay));
+    return (size_t)grid_pitch(gx) * gy * gz;
+}
+
+size_t vg_scratch_bytes(int32_t gx, int32_t gy, int32_t gz, int32_t vox_inf)
+{
+    if (vg_grid_bytes(gx, gy, gz) == 0 || vox_inf < 0 || vox_inf > kMaxInflation)
+        return 0;
+    return layout_for(gx, gy, gz, vox_inf).fixed;
 }
 
 vg_status vg_create_grid(int32_t gx, int32_t gy, int32_t gz, float vox_size,
                          const float origin_w[3], int32_t vox_inf, uint8_t *loc_grid,
-                         uint8_t *loc_spare, void *scratch, size_t scratch_bytes, void *stream,
-                         vg_grid **out)
+                         uint8_t *loc_spare, size_t grid_bytes, void *scratch,
+                         size_t scratch_bytes, void *stream, vg_grid **out)
 {
     if (!out)
         return VG_ERR_ARG;
     *out = nullptr;
-    if (gx < 1 || gy < 1 || gz < 1 || gx > 65535 || gy > 65535 || gz > 65535 ||
-        (int64_t)gx * gy * gz >= ((int64_t)1 << 31))
+    if (vg_grid_bytes(gx, gy, gz) == 0)
         return VG_ERR_ARG;
     if (!(vox_size > 0.0f) || !std::isfinite(vox_size) || vox_inf < 0 || vox_inf > kMaxInflation)
         return VG_ERR_ARG;
@@ -454,11 +514,12 @@ vg_status vg_create_grid(int32_t gx, int32_t gy, int32_t gz, float vox_size,
         !std::isfinite(origin_w[2]))
         return VG_ERR_ARG;
     if (!loc_grid || !loc_spare || loc_grid == loc_spare || !scratch ||
-        ((uintptr_t)scratch % kAlign) != 0)
+        ((uintptr_t)scratch % kAlign) != 0 || ((uintptr_t)loc_grid % 16) != 0 ||
+        ((uintptr_t)loc_spare % 16) != 0)
         return VG_ERR_ARG;
-    const int64_t n = (int64_t)gx * gy * gz;
+    const size_t n = vg_grid_bytes(gx, gy, gz);
     Layout lay = layout_for(gx, gy, gz, vox_inf);
-    if (scratch_bytes < lay.fixed)
+    if (scratch_bytes < lay.fixed || grid_bytes < n)
         return VG_ERR_BUDGET;
 
     vg_grid *g = new (std::nothrow) vg_grid;
@@ -485,7 +546,7 @@ vg_status vg_create_grid(int32_t gx, int32_t gy, int32_t gz, float vox_size,
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
     // Step 1: every voxel of the local grid starts unknown; stamps start clear.
-    if (launch_fill(loc_grid, VG_UNKNOWN, (size_t)n, st) != hipSuccess ||
+    if (launch_fill(loc_grid, VG_UNKNOWN, n, st) != hipSuccess ||
         launch_fill(scratch, 0, lay.fixed, st) != hipSuccess) {
         delete g;
         return VG_ERR_HIP;
@@ -574,22 +635,18 @@ vg_status vg_read_grid(const vg_grid *g, uint8_t *dst, int32_t dst_is_device, vo
 {
     if (!g || !dst)
         return VG_ERR_ARG;
-    size_t n = (size_t)g->n[0] * g->n[1] * g->n[2];
-    return hip_status(hipMemcpyAsync(dst, g->loc, n,
-                                     dst_is_device ? hipMemcpyDeviceToDevice
-                                                   : hipMemcpyDeviceToHost,
-                                     static_cast<hipStream_t>(stream)));
+    return hip_status(copy_grid(dst, g->n[0], g->loc, g->lay.gxp, g->n,
+                                dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                static_cast<hipStream_t>(stream)));
 }
 
 vg_status vg_write_grid(vg_grid *g, const uint8_t *src, int32_t src_is_device, void *stream)
 {
     if (!g || !src)
         return VG_ERR_ARG;
-    size_t n = (size_t)g->n[0] * g->n[1] * g->n[2];
-    return hip_status(hipMemcpyAsync(g->loc, src, n,
-                                     src_is_device ? hipMemcpyDeviceToDevice
-                                                   : hipMemcpyHostToDevice,
-                                     static_cast<hipStream_t>(stream)));
+    return hip_status(copy_grid(g->loc, g->lay.gxp, src, g->n[0], g->n,
+                                src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                static_cast<hipStream_t>(stream)));
 }
 
 vg_status vg_set_profile_events(vg_grid *g, void *const *events, int32_t n_sets)

@@ -1,5 +1,11 @@
 // vg_internal.h -- parameter blocks and kernel launchers shared by the host
 // API (vg_api.cpp) and the gfx950 kernels (vg_kernels.hip).  Not installed.
+//
+// Device layout of a grid: rows of gx voxels are stored with a pitch of
+// gxp = 32 * ceil(gx / 32) bytes (voxel (x, y, z) at x + gxp * (y + gy * z)),
+// so that the same linear index addresses the grid byte and its bit in the
+// per-frame occupancy plane (32-voxel words never straddle rows).  The
+// padding bytes x >= gx are never part of the grid.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -21,28 +27,27 @@ constexpr int kPoints = 2;
 // 32 output voxels plus 2 * vox_inf neighbours.
 constexpr int kMaxInflation = 16;
 
-// A ray that met an occupied voxel in the free pass, parked for the traced
-// pass: its fan coordinates (to rebuild direction and step sizes) and the
-// walk state right after the hit voxel.
-struct alignas(16) ParkedRay {
-    int32_t ta, tb;      // fan target: pinhole (a, b); spinning (column, z)
-    int32_t vx, vy, vz;  // current voxel
-    float tmx, tmy, tmz; // next boundary crossing per axis
-};
-static_assert(sizeof(ParkedRay) == 32, "ParkedRay is 32 bytes");
+// Row pitch of the device grid layout.
+inline int32_t grid_pitch(int32_t gx) { return 32 * ((gx + 31) / 32); }
 
-// Occupancy planes of one frame.  Seeds live on the grid padded by vox_inf on
-// every side (a point just outside the grid still inflates into it); padded
-// coordinate = voxel coordinate + vox_inf.
+// A box of rows [y0, y1] x [z0, z1] (inclusive; empty if y0 > y1).
+struct RowBox {
+    int32_t y0, y1, z0, z1;
+};
+
+// Per-frame planes.  Seeds live on the grid padded by vox_inf on every side
+// (a point just outside the grid still inflates into it); padded coordinate =
+// voxel coordinate + vox_inf.
 struct Planes {
     int32_t n[3];        // grid size
     int32_t r;           // vox_inf
-    int32_t wx;          // 32-voxel words per grid row: ceil(gx / 32)
+    int32_t wx;          // 32-voxel words per grid row: gxp / 32
     int32_t py, pz;      // padded rows: gy + 2r, gz + 2r
     int32_t seed_pitch;  // bytes per padded seed row (multiple of 64, >= 32*wx + 64)
-    uint8_t *seed;       // per-frame seed stamps, [pz][py][seed_pitch]
+    uint8_t *seed;       // seed stamps, [pz][py][seed_pitch]
     uint32_t *bitx;      // seeds dilated along x, [pz][py][wx] words
-    uint32_t *occ;       // occupied voxels of the frame, [gz][gy][wx] words
+    uint32_t *occ;       // occupied voxels of the frame, bit i = grid index i
+    uint8_t *traced;     // "unknown and traced" stamps, one byte per grid index
     int32_t lo[3], hi[3];  // padded box that holds every seed (lo > hi: none)
     uint32_t epoch;      // stamp of this frame (1..255)
 };
@@ -61,7 +66,6 @@ struct SeedParams {
     const float *img;     // depth / range image, or points[W][3]
     const float *col_tab; // spinning: cos/sin azimuth per column
     const float *row_tab; // spinning: cos/sin elevation per row
-    uint32_t *parked_count;
 };
 
 // Step 3: the bundled ray fan.  One wavefront owns an 8 x 8 tile of fan
@@ -71,7 +75,7 @@ struct RayParams {
     float o[3];       // camera position in voxel units
     int32_t v0[3];    // camera voxel
     int32_t n[3];
-    int32_t wx;       // occupancy words per row
+    int32_t gxp;      // grid row pitch
     int32_t kind;     // kPinhole (also points) or kSpinning
     int32_t vd, hw, hh;   // pinhole fan; spinning: hh = largest half height
     int32_t na, nb;       // fan extent along a and b
@@ -79,20 +83,22 @@ struct RayParams {
     const int32_t *hz;    // spinning: half height per column
     uint8_t *loc;
     const uint32_t *occ;
-    ParkedRay *parked;
-    uint32_t *parked_count;
-    uint32_t parked_cap;
+    uint8_t *traced;
+    uint32_t epoch;
 };
 
 hipError_t launch_fill(void *dst, uint8_t value, size_t bytes, hipStream_t st);
 hipError_t launch_seeds(const SeedParams &p, hipStream_t st);
 // Seeds -> occupied bit plane (dilation by vox_inf along x, then y and z).
 hipError_t launch_dilate(const Planes &pl, hipStream_t st);
-// mid: optional event recorded between the free and the traced pass.
-hipError_t launch_rays(const RayParams &p, hipStream_t st, hipEvent_t mid);
-// Occupied bit plane -> local grid (runs after the traced pass).
-hipError_t launch_mark_occupied(const Planes &pl, uint8_t *loc, hipStream_t st);
+// The walk of every fan ray.  camera_inside: the camera voxel lies in the grid.
+hipError_t launch_rays(const RayParams &p, bool camera_inside, hipStream_t st);
+// Traced stamps and occupied bits -> the local grid, over the given rows.
+hipError_t launch_resolve(const Planes &pl, uint8_t *loc, const RowBox &rows, hipStream_t st);
 hipError_t launch_shift(const uint8_t *src, uint8_t *dst, const int32_t n[3],
                         const int32_t d[3], hipStream_t st);
+// Linear (pitch gx) <-> device layout (pitch gxp) copies of a whole grid.
+hipError_t copy_grid(uint8_t *dst, int64_t dst_pitch, const uint8_t *src, int64_t src_pitch,
+                     const int32_t n[3], hipMemcpyKind kind, hipStream_t st);
 
 }  // namespace vg

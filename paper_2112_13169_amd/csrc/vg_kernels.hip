@@ -9,17 +9,16 @@
 //   k_dilate_x    Alg. 1 lines 6-9, separably: seeds -> bits dilated by
 //   k_dilate_yz   vox_inf along x, then along y and z.  The union of the
 //                 (2 vox_inf + 1)^3 cubes is exactly this separable dilation.
-//   k_ray_free    Alg. 2 up to the first occupied voxel: one wavefront per 8x8
-//                 tile of fan targets; every voxel walked before the hit
-//                 becomes free in the local grid.  Rays that hit park their
-//                 walk state.  Occupancy words are fetched for 8 walk steps at
-//                 a time so the loads overlap.
-//   k_ray_traced  Alg. 2 after the hit: parked rays continue and mark every
-//                 voxel they walk "unknown and traced" (stored as unknown).
-//   k_mark_occ    the frame's occupied voxels become occupied in the grid.
-// Alg. 3 (merge) needs no pass of its own: the launches write the merged
-// values straight into the local grid and their order gives the merge's
-// priorities (traced beats free, occupied beats both).
+//   k_rays        Alg. 2: one wavefront per 8x8 tile of fan targets, one lane
+//                 per ray.  Before its first occupied voxel a ray marks voxels
+//                 free in the local grid; after it, it stamps them "unknown and
+//                 traced" in a separate plane.  Occupancy words are fetched for
+//                 8 walk steps at a time so that the loads overlap.
+//   k_resolve     Alg. 3 for the marks that need priority: traced stamps become
+//                 unknown, then the frame's occupied voxels become occupied.
+// The free marks need no merge pass: free lands only on voxels no traced stamp
+// or occupied bit overrides later.  All voxel stores are idempotent byte
+// stores; no atomics on voxels.
 //
 // Floating point: contraction is off (also on the command line) so every fp32
 // operation rounds exactly as written; fp32 division is the correctly rounded
@@ -113,83 +112,94 @@ __device__ __forceinline__ void axis_setup(float o, int32_t v0, float d, int32_t
     }
 }
 
-// Walk state of one ray (scalar fields: a per-axis array indexed by the
-// stepping axis would be demoted to private memory).
-struct Walker {
-    int32_t vx, vy, vz;       // current voxel
-    int32_t sx, sy, sz;       // step per axis (-1, 0, +1)
-    int32_t cx, cy, cz;       // |v - v0| per axis: steps taken on that axis
+// Walk state of one ray.  Scalar fields and select chains: an array indexed
+// by the stepping axis would be demoted to private memory, and if / else
+// chains become exec-mask branches.
+struct Walk {
     float tmx, tmy, tmz;      // ray parameter of the next boundary per axis
     float tdx, tdy, tdz;      // ray parameter per voxel per axis
+    int32_t cx, cy, cz;       // steps taken on each axis (= |v - v0| per axis)
+    int32_t lx, ly, lz;       // steps on each axis after which the ray is outside
+    int32_t ex, ey, ez;       // steps on each axis before the ray is inside
+    int32_t sx, sy, sz;       // index stride of one step on each axis
     int32_t d2;               // squared lattice distance from the camera voxel
+    uint32_t idx;             // device-layout index of the current voxel (mod 2^32)
 };
 
-__device__ __forceinline__ void walker_setup(Walker &w, const float o[3], const int32_t v0[3],
-                                             const float dir[3])
+// Steps along one axis before the walk leaves the grid (0 for an axis the
+// ray does not move on: choosing it ends the walk) and before it enters.
+__device__ __forceinline__ void axis_limits(int32_t step, int32_t v0, int32_t n, int32_t &leave,
+                                            int32_t &enter)
 {
-    axis_setup(o[0], v0[0], dir[0], w.sx, w.tmx, w.tdx);
-    axis_setup(o[1], v0[1], dir[1], w.sy, w.tmy, w.tdy);
-    axis_setup(o[2], v0[2], dir[2], w.sz, w.tmz, w.tdz);
-    w.vx = v0[0];
-    w.vy = v0[1];
-    w.vz = v0[2];
+    leave = step > 0 ? n - v0 : (step < 0 ? v0 + 1 : 0);
+    enter = step > 0 ? max(-v0, 0) : (step < 0 ? max(v0 - n + 1, 0) : 0);
+}
+
+__device__ __forceinline__ void walk_setup(Walk &w, const RayParams &p, const float dir[3])
+{
+    int32_t sx, sy, sz;
+    axis_setup(p.o[0], p.v0[0], dir[0], sx, w.tmx, w.tdx);
+    axis_setup(p.o[1], p.v0[1], dir[1], sy, w.tmy, w.tdy);
+    axis_setup(p.o[2], p.v0[2], dir[2], sz, w.tmz, w.tdz);
+    axis_limits(sx, p.v0[0], p.n[0], w.lx, w.ex);
+    axis_limits(sy, p.v0[1], p.n[1], w.ly, w.ey);
+    axis_limits(sz, p.v0[2], p.n[2], w.lz, w.ez);
+    w.sx = sx;
+    w.sy = sy * p.gxp;
+    w.sz = sz * p.gxp * p.n[1];
     w.cx = w.cy = w.cz = 0;
     w.d2 = 0;
+    w.idx = (uint32_t)((int64_t)p.v0[0] + (int64_t)p.gxp * (p.v0[1] + (int64_t)p.n[1] * p.v0[2]));
 }
 
-// One walk step: move along the axis whose boundary is nearest (ties go to
-// the later axis).  Returns false when the walk cannot continue: zero
-// direction, or the ray left the grid on an axis it keeps moving away on
-// (the grid is convex, so it can never come back).
-__device__ __forceinline__ bool walk_step(Walker &w, const int32_t n[3])
+// An axis on which the camera lies outside the grid and the ray does not
+// move towards it: such a ray never enters the grid.
+__device__ __forceinline__ bool axis_dead(int32_t step, int32_t v0, int32_t n)
 {
-    const bool cxy = w.tmx < w.tmy, cxz = w.tmx < w.tmz, cyz = w.tmy < w.tmz;
-    const bool ax = cxy && cxz;
-    const bool ay = !cxy && cyz;
-    int32_t st, va, na;
-    if (ax) {
-        st = w.sx;
-        w.vx += st;
-        w.tmx += w.tdx;
-        w.d2 += 2 * w.cx + 1;
-        w.cx += 1;
-        va = w.vx;
-        na = n[0];
-    } else if (ay) {
-        st = w.sy;
-        w.vy += st;
-        w.tmy += w.tdy;
-        w.d2 += 2 * w.cy + 1;
-        w.cy += 1;
-        va = w.vy;
-        na = n[1];
-    } else {
-        st = w.sz;
-        w.vz += st;
-        w.tmz += w.tdz;
-        w.d2 += 2 * w.cz + 1;
-        w.cz += 1;
-        va = w.vz;
-        na = n[2];
-    }
-    if (st == 0)
+    const bool outside = v0 < 0 || v0 >= n;
+    const bool towards = (step > 0 && v0 < 0) || (step < 0 && v0 >= n);
+    return outside && !towards;
+}
+
+// One step of Alg. 2: move along the axis whose boundary is nearest (ties
+// go to the later axis).  Returns false when the walk is over: the length
+// of Alg. 2 is reached, the direction is zero, or the ray left the grid on
+// an axis it keeps moving away on (the grid is convex: it cannot return).
+// kGeneral: the camera may be outside, so `in` reports whether the new voxel
+// lies in the grid; otherwise every voxel of the walk does.
+// Value selects.  A conditional expression over two lvalues is itself an
+// lvalue in C++, so `c ? w.a : w.b` selects an address and forces the walk
+// state into memory; selecting copied values keeps it in registers.
+__device__ __forceinline__ int32_t sel(bool c, int32_t a, int32_t b) { return c ? a : b; }
+__device__ __forceinline__ float self(bool c, float a, float b) { return c ? a : b; }
+
+template <bool kGeneral>
+__device__ __forceinline__ bool walk_step(Walk &w, int32_t m2, bool &in)
+{
+    if (w.d2 >= m2)
         return false;
-    return !((va < 0 && st < 0) || (va >= na && st > 0));
-}
-
-__device__ __forceinline__ bool in_grid(const Walker &w, const int32_t n[3])
-{
-    return (uint32_t)w.vx < (uint32_t)n[0] && (uint32_t)w.vy < (uint32_t)n[1] &&
-           (uint32_t)w.vz < (uint32_t)n[2];
-}
-
-// A ray that starts outside the grid and does not move towards it on that
-// axis never enters.
-__device__ __forceinline__ bool never_enters(const Walker &w, const int32_t n[3])
-{
-    return (w.vx < 0 && w.sx <= 0) || (w.vx >= n[0] && w.sx >= 0) ||
-           (w.vy < 0 && w.sy <= 0) || (w.vy >= n[1] && w.sy >= 0) ||
-           (w.vz < 0 && w.sz <= 0) || (w.vz >= n[2] && w.sz >= 0);
+    const float tmx = w.tmx, tmy = w.tmy, tmz = w.tmz;
+    const int32_t cx = w.cx, cy = w.cy, cz = w.cz;
+    const bool lxy = tmx < tmy;
+    const bool ax = lxy && (tmx < tmz);
+    const bool ay = !lxy && (tmy < tmz);
+    const bool az = !(ax || ay);
+    const int32_t c = sel(ax, cx, sel(ay, cy, cz));
+    const int32_t leave = sel(ax, w.lx, sel(ay, w.ly, w.lz));
+    if (c + 1 >= leave)
+        return false;
+    const int32_t stride = sel(ax, w.sx, sel(ay, w.sy, w.sz));
+    w.tmx = self(ax, tmx + w.tdx, tmx);
+    w.tmy = self(ay, tmy + w.tdy, tmy);
+    w.tmz = self(az, tmz + w.tdz, tmz);
+    w.cx = cx + sel(ax, 1, 0);
+    w.cy = cy + sel(ay, 1, 0);
+    w.cz = cz + sel(az, 1, 0);
+    w.d2 += 2 * c + 1;
+    w.idx += (uint32_t)stride;
+    if (kGeneral)
+        in = w.cx >= w.ex && w.cy >= w.ey && w.cz >= w.ez;
+    return true;
 }
 
 __device__ __forceinline__ void ray_direction(const RayParams &p, int32_t tx, int32_t ty,
@@ -235,9 +245,6 @@ __global__ __launch_bounds__(kBlock) void k_fill(uint8_t *dst, uint8_t value, si
 // row segment (coalesced row reads).  Points: 256 points per block.
 __global__ __launch_bounds__(kBlock) void k_seed(SeedParams p)
 {
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)
-        *p.parked_count = 0;   // the traced pass of this frame starts empty
-
     float pc[3];
     if (p.kind == kPoints) {
         int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -350,167 +357,121 @@ __global__ __launch_bounds__(kBlock) void k_dilate_yz(Planes pl)
     pl.occ[gid] = out;
 }
 
-// Alg. 2 before the first occupied voxel.
-__global__ __launch_bounds__(kBlock) void k_ray_free(RayParams p)
+// Alg. 2 for every ray of the fan.
+template <bool kGeneral>
+__global__ __launch_bounds__(kBlock) void k_rays(RayParams p)
 {
     const int lane = threadIdx.x & 63;
     const int32_t tile = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
     const int32_t ta = tile % p.tiles_a, tb = tile / p.tiles_a;
     const int32_t ia = ta * 8 + (lane & 7), ib = tb * 8 + (lane >> 3);
-
     int32_t tx, ty, tz, m2;
-    bool park = false;
-    Walker w;
-    if (tile < p.tiles && fan_target(p, ia, ib, tx, ty, tz, m2)) {
-        float dir[3];
-        ray_direction(p, tx, ty, tz, dir);
-        walker_setup(w, p.o, p.v0, dir);
-        bool more = !never_enters(w, p.n);
-        while (more) {
-            const Walker snap = w;
-            uint32_t widx[kChunk], lidx[kChunk], bit[kChunk];
-            bool val[kChunk];
-#pragma unroll
-            for (int s = 0; s < kChunk; ++s) {
-                val[s] = false;
-                widx[s] = lidx[s] = bit[s] = 0;
-                if (more) {
-                    if (w.d2 < m2 && walk_step(w, p.n)) {
-                        if (in_grid(w, p.n)) {
-                            val[s] = true;
-                            uint32_t row = (uint32_t)w.vy + (uint32_t)p.n[1] * (uint32_t)w.vz;
-                            widx[s] = ((uint32_t)w.vx >> 5) + (uint32_t)p.wx * row;
-                            bit[s] = (uint32_t)w.vx & 31u;
-                            lidx[s] = (uint32_t)w.vx + (uint32_t)p.n[0] * row;
-                        }
-                    } else {
-                        more = false;
-                    }
-                }
-            }
-            uint32_t word[kChunk];
-#pragma unroll
-            for (int s = 0; s < kChunk; ++s)
-                word[s] = val[s] ? p.occ[widx[s]] : 0u;
-            int hit = kChunk;
-#pragma unroll
-            for (int s = kChunk - 1; s >= 0; --s)
-                if ((word[s] >> bit[s]) & 1u)
-                    hit = s;
-#pragma unroll
-            for (int s = 0; s < kChunk; ++s)
-                if (val[s] && s < hit)
-                    p.loc[lidx[s]] = kFree;
-            if (hit < kChunk) {
-                // replay the walk up to and including the hit voxel
-                w = snap;
-                for (int s = 0; s <= hit; ++s)
-                    walk_step(w, p.n);
-                park = w.d2 < m2;   // anything left to walk after the hit?
-                break;
-            }
-        }
-    }
-
-    // Park the rays that hit: one atomic per wavefront.
-    const uint64_t mask = __ballot(park);
-    if (mask == 0)
-        return;
-    const int leader = __ffsll((unsigned long long)mask) - 1;
-    uint32_t base = 0;
-    if (lane == leader)
-        base = atomicAdd(p.parked_count, (uint32_t)__popcll(mask));
-    base = __shfl(base, leader);
-    if (park) {
-        uint32_t slot = base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
-        if (slot < p.parked_cap) {
-            ParkedRay r;
-            r.ta = ia;
-            r.tb = ib;
-            r.vx = w.vx;
-            r.vy = w.vy;
-            r.vz = w.vz;
-            r.tmx = w.tmx;
-            r.tmy = w.tmy;
-            r.tmz = w.tmz;
-            p.parked[slot] = r;
-        }
-    }
-}
-
-// Alg. 2 after the hit: continue each parked ray, marking "unknown and
-// traced" (stored as unknown) on every voxel it walks.  Occupied voxels are
-// restored by k_mark_occ afterwards, so this pass needs no loads.
-__global__ __launch_bounds__(kBlock) void k_ray_traced(RayParams p)
-{
-    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-    const uint32_t count = min(*p.parked_count, p.parked_cap);
-    if (i >= count)
-        return;
-    const ParkedRay r = p.parked[i];
-    int32_t tx, ty, tz, m2;
-    if (!fan_target(p, r.ta, r.tb, tx, ty, tz, m2))
+    if (tile >= p.tiles || !fan_target(p, ia, ib, tx, ty, tz, m2))
         return;
     float dir[3];
     ray_direction(p, tx, ty, tz, dir);
-    Walker w;
-    walker_setup(w, p.o, p.v0, dir);   // steps and step sizes of this ray
-    w.vx = r.vx;                       // resume right after the hit voxel
-    w.vy = r.vy;
-    w.vz = r.vz;
-    w.tmx = r.tmx;
-    w.tmy = r.tmy;
-    w.tmz = r.tmz;
-    w.cx = abs(w.vx - p.v0[0]);
-    w.cy = abs(w.vy - p.v0[1]);
-    w.cz = abs(w.vz - p.v0[2]);
-    w.d2 = w.cx * w.cx + w.cy * w.cy + w.cz * w.cz;
-    while (w.d2 < m2) {
-        if (!walk_step(w, p.n))
-            break;
-        if (in_grid(w, p.n))
-            p.loc[(uint32_t)w.vx + (uint32_t)p.n[0] * ((uint32_t)w.vy +
-                                                        (uint32_t)p.n[1] * (uint32_t)w.vz)] =
-                kUnknown;
+    if (kGeneral && (axis_dead(dir[0] > 0.0f ? 1 : (dir[0] < 0.0f ? -1 : 0), p.v0[0], p.n[0]) ||
+                     axis_dead(dir[1] > 0.0f ? 1 : (dir[1] < 0.0f ? -1 : 0), p.v0[1], p.n[1]) ||
+                     axis_dead(dir[2] > 0.0f ? 1 : (dir[2] < 0.0f ? -1 : 0), p.v0[2], p.n[2])))
+        return;
+    Walk w;
+    walk_setup(w, p, dir);
+
+    const uint8_t stamp = (uint8_t)p.epoch;
+    bool before_hit = true;   // Alg. 2: vox_val is still "free"
+    bool alive = true;
+    while (alive) {
+        uint32_t ids[kChunk];
+        bool val[kChunk];
+#pragma unroll
+        for (int s = 0; s < kChunk; ++s) {
+            bool in = true;
+            val[s] = false;
+            if (alive) {
+                alive = walk_step<kGeneral>(w, m2, in);
+                val[s] = alive && in;
+            }
+            ids[s] = w.idx;
+        }
+        // occupancy of the new voxels (only needed before the hit)
+        uint32_t word[kChunk];
+#pragma unroll
+        for (int s = 0; s < kChunk; ++s)
+            word[s] = (val[s] && before_hit) ? p.occ[ids[s] >> 5] : 0u;
+        int hit = kChunk;
+#pragma unroll
+        for (int s = kChunk - 1; s >= 0; --s)
+            if ((word[s] >> (ids[s] & 31u)) & 1u)
+                hit = s;
+#pragma unroll
+        for (int s = 0; s < kChunk; ++s) {
+            if (!val[s])
+                continue;
+            if (before_hit && s < hit)
+                p.loc[ids[s]] = kFree;
+            else if (s != hit)
+                p.traced[ids[s]] = stamp;
+        }
+        if (hit < kChunk)
+            before_hit = false;
     }
 }
 
-// The frame's occupied voxels become occupied in the local grid.  One lane
-// per occupancy word of the rows the seed box can reach.
-__global__ __launch_bounds__(kBlock) void k_mark_occ(Planes pl, uint8_t *loc, int32_t y0,
-                                                     int32_t ny, int32_t z0, int32_t nz)
+// Alg. 3 for the prioritised marks.  One lane per 16 voxels of a grid row:
+// occupied bit -> occupied; else traced stamp -> unknown; else unchanged.
+__global__ __launch_bounds__(kBlock) void k_resolve(Planes pl, uint8_t *loc, int32_t y0,
+                                                    int32_t ny, int32_t z0, int32_t nz)
 {
+    const int32_t chunks = pl.wx * 2;   // 16-voxel chunks per row
     const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (gid >= (int64_t)pl.wx * ny * nz)
+    if (gid >= (int64_t)chunks * ny * nz)
         return;
-    const int32_t w = (int32_t)(gid % pl.wx);
-    const int64_t row = gid / pl.wx;
+    const int32_t k = (int32_t)(gid % chunks);
+    const int64_t row = gid / chunks;
     const int32_t y = y0 + (int32_t)(row % ny);
     const int32_t z = z0 + (int32_t)(row / ny);
-    const int64_t r = y + (int64_t)pl.n[1] * z;
-    uint32_t m = pl.occ[(int64_t)pl.wx * r + w];
-    uint8_t *dst = loc + (int64_t)pl.n[0] * r + 32 * w;
-    while (m) {
-        int b = __ffs(m) - 1;
-        dst[b] = kOccupied;
-        m &= m - 1u;
+    const int64_t base = 32 * (int64_t)pl.wx * (y + (int64_t)pl.n[1] * z) + 16 * k;
+    const uint32_t occ16 = (pl.occ[base >> 5] >> (base & 16)) & 0xFFFFu;
+    const uint4 tr = *reinterpret_cast<const uint4 *>(pl.traced + base);
+    const uint32_t rep = (pl.epoch & 0xFFu) * 0x01010101u;
+    const uint32_t tr16 = byte_eq_mask(tr.x, rep) | (byte_eq_mask(tr.y, rep) << 4) |
+                          (byte_eq_mask(tr.z, rep) << 8) | (byte_eq_mask(tr.w, rep) << 12);
+    if ((occ16 | tr16) == 0)
+        return;
+    uint4 v = *reinterpret_cast<const uint4 *>(loc + base);
+    uint32_t *vw = reinterpret_cast<uint32_t *>(&v);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        // spread 4 mask bits to 4 byte masks
+        uint32_t om = (((occ16 >> (4 * j)) & 0xFu) * 0x00204081u & 0x01010101u) * 0xFFu;
+        uint32_t tm = (((tr16 >> (4 * j)) & 0xFu) * 0x00204081u & 0x01010101u) * 0xFFu;
+        vw[j] = (vw[j] & ~(om | tm)) | (0x02020202u & om);
     }
+    *reinterpret_cast<uint4 *>(loc + base) = v;
 }
 
-// Sec. IV-E: dst[x,y,z] = src[x+dx, y+dy, z+dz] inside, else unknown.
+// Sec. IV-E: dst[x,y,z] = src[x+dx, y+dy, z+dz] inside, else unknown.  One
+// lane per 4 voxels of a device-layout row (padding bytes become unknown).
 __global__ __launch_bounds__(kBlock) void k_shift(const uint8_t *src, uint8_t *dst, int32_t nx,
-                                                  int32_t ny, int32_t nz, int32_t dx, int32_t dy,
-                                                  int32_t dz)
+                                                  int32_t ny, int32_t nz, int32_t pitch,
+                                                  int32_t dx, int32_t dy, int32_t dz)
 {
-    int32_t x = blockIdx.x * kBlock + threadIdx.x;
-    int32_t y = blockIdx.y, z = blockIdx.z;
-    if (x >= nx)
+    const int32_t x0 = 4 * (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    const int32_t y = blockIdx.y, z = blockIdx.z;
+    if (x0 >= pitch)
         return;
-    int64_t sx = (int64_t)x + dx, sy = (int64_t)y + dy, sz = (int64_t)z + dz;
-    uint8_t val = kUnknown;
-    if (sx >= 0 && sx < nx && sy >= 0 && sy < ny && sz >= 0 && sz < nz)
-        val = src[(sz * ny + sy) * nx + sx];
-    dst[((int64_t)z * ny + y) * nx + x] = val;
+    const int64_t sy = (int64_t)y + dy, sz = (int64_t)z + dz;
+    uint32_t out = 0;
+    if (sy >= 0 && sy < ny && sz >= 0 && sz < nz) {
+        const uint8_t *row = src + pitch * (sy + (int64_t)ny * sz);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t x = (int64_t)x0 + j, sx = x + dx;
+            if (x < nx && sx >= 0 && sx < nx)
+                out |= (uint32_t)row[sx] << (8 * j);
+        }
+    }
+    *reinterpret_cast<uint32_t *>(dst + pitch * (y + (int64_t)ny * z) + x0) = out;
 }
 
 uint32_t blocks_for(int64_t threads) { return (uint32_t)((threads + kBlock - 1) / kBlock); }
@@ -556,43 +517,45 @@ hipError_t launch_dilate(const Planes &pl, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_rays(const RayParams &p, hipStream_t st, hipEvent_t mid)
+hipError_t launch_rays(const RayParams &p, bool camera_inside, hipStream_t st)
 {
     const int waves = kBlock / 64;
     uint32_t blocks = (uint32_t)((p.tiles + waves - 1) / waves);
     if (blocks == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_ray_free, dim3(blocks), dim3(kBlock), 0, st, p);
-    hipError_t e = hipGetLastError();
-    if (e == hipSuccess && mid)
-        e = hipEventRecord(mid, st);
-    if (e != hipSuccess)
-        return e;
-    hipLaunchKernelGGL(k_ray_traced, dim3(blocks_for((int64_t)p.tiles * 64)), dim3(kBlock), 0,
-                       st, p);
+    if (camera_inside)
+        hipLaunchKernelGGL(k_rays<false>, dim3(blocks), dim3(kBlock), 0, st, p);
+    else
+        hipLaunchKernelGGL(k_rays<true>, dim3(blocks), dim3(kBlock), 0, st, p);
     return hipGetLastError();
 }
 
-hipError_t launch_mark_occupied(const Planes &pl, uint8_t *loc, hipStream_t st)
+hipError_t launch_resolve(const Planes &pl, uint8_t *loc, const RowBox &rows, hipStream_t st)
 {
-    // output rows y with a seed row in y .. y + 2r inside the box
-    const int32_t y0 = std::max(pl.lo[1] - 2 * pl.r, 0), y1 = std::min(pl.hi[1], pl.n[1] - 1);
-    const int32_t z0 = std::max(pl.lo[2] - 2 * pl.r, 0), z1 = std::min(pl.hi[2], pl.n[2] - 1);
-    if (pl.lo[0] > pl.hi[0] || y0 > y1 || z0 > z1)
+    if (rows.y0 > rows.y1 || rows.z0 > rows.z1)
         return hipSuccess;
-    int64_t n = (int64_t)pl.wx * (y1 - y0 + 1) * (z1 - z0 + 1);
-    hipLaunchKernelGGL(k_mark_occ, dim3(blocks_for(n)), dim3(kBlock), 0, st, pl, loc, y0,
-                       y1 - y0 + 1, z0, z1 - z0 + 1);
+    const int32_t ny = rows.y1 - rows.y0 + 1, nz = rows.z1 - rows.z0 + 1;
+    int64_t n = (int64_t)pl.wx * 2 * ny * nz;
+    hipLaunchKernelGGL(k_resolve, dim3(blocks_for(n)), dim3(kBlock), 0, st, pl, loc, rows.y0,
+                       ny, rows.z0, nz);
     return hipGetLastError();
 }
 
 hipError_t launch_shift(const uint8_t *src, uint8_t *dst, const int32_t n[3], const int32_t d[3],
                         hipStream_t st)
 {
-    dim3 grid((uint32_t)((n[0] + kBlock - 1) / kBlock), (uint32_t)n[1], (uint32_t)n[2]);
-    hipLaunchKernelGGL(k_shift, grid, dim3(kBlock), 0, st, src, dst, n[0], n[1], n[2], d[0], d[1],
-                       d[2]);
+    const int32_t pitch = grid_pitch(n[0]);
+    dim3 grid((uint32_t)((pitch / 4 + kBlock - 1) / kBlock), (uint32_t)n[1], (uint32_t)n[2]);
+    hipLaunchKernelGGL(k_shift, grid, dim3(kBlock), 0, st, src, dst, n[0], n[1], n[2], pitch,
+                       d[0], d[1], d[2]);
     return hipGetLastError();
+}
+
+hipError_t copy_grid(uint8_t *dst, int64_t dst_pitch, const uint8_t *src, int64_t src_pitch,
+                     const int32_t n[3], hipMemcpyKind kind, hipStream_t st)
+{
+    return hipMemcpy2DAsync(dst, (size_t)dst_pitch, src, (size_t)src_pitch, (size_t)n[0],
+                            (size_t)n[1] * n[2], kind, st);
 }
 
 }  // namespace vg

@@ -17,8 +17,8 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "vg.h")
 VG_OK, VG_ERR_ARG, VG_ERR_HIP, VG_ERR_BUDGET, VG_ERR_STATE = 0, -1, -2, -3, -4
 VG_UNKNOWN, VG_FREE, VG_OCCUPIED = 0, 1, 2
 VG_PINHOLE, VG_SPINNING = 0, 1
-PROFILE_EVENTS = 6   # events per frame of vg_set_profile_events
-PROFILE_STAGES = ("seed", "dilate", "ray_free", "ray_traced", "mark_occ")
+PROFILE_EVENTS = 5   # events per frame of vg_set_profile_events
+PROFILE_STAGES = ("seed", "dilate", "rays", "resolve")
 
 
 class VgError(RuntimeError):
@@ -57,10 +57,12 @@ def lib():
         sp = ctypes.POINTER(vg_sensor)
         pp = ctypes.POINTER(vg_pose)
         L.vg_fan_sizes.argtypes = [sp, f32, P]
-        L.vg_scratch_bytes.argtypes = [i32, i32, i32, i32, i64]
+        L.vg_scratch_bytes.argtypes = [i32, i32, i32, i32]
+        L.vg_grid_bytes.argtypes = [i32, i32, i32]
+        L.vg_grid_bytes.restype = ctypes.c_size_t
         L.vg_scratch_bytes.restype = ctypes.c_size_t
-        L.vg_create_grid.argtypes = [i32, i32, i32, f32, P, i32, P, P, P, ctypes.c_size_t, P,
-                                     ctypes.POINTER(P)]
+        L.vg_create_grid.argtypes = [i32, i32, i32, f32, P, i32, P, P, ctypes.c_size_t, P,
+                                     ctypes.c_size_t, P, ctypes.POINTER(P)]
         L.vg_integrate_frame.argtypes = [P, P, i64, sp, pp, P]
         L.vg_integrate_points.argtypes = [P, P, i64, sp, pp, P]
         L.vg_shift_grid.argtypes = [P, i32, i32, i32, P]
@@ -142,18 +144,24 @@ def vg_fan_sizes(sensor, vox_size):
     return tuple(int(v) for v in out)
 
 
-def vg_scratch_bytes(gx, gy, gz, vox_inf, max_rays):
-    return int(lib().vg_scratch_bytes(gx, gy, gz, vox_inf, max_rays))
+def vg_grid_bytes(gx, gy, gz):
+    return int(lib().vg_grid_bytes(gx, gy, gz))
+
+
+def vg_scratch_bytes(gx, gy, gz, vox_inf):
+    return int(lib().vg_scratch_bytes(gx, gy, gz, vox_inf))
 
 
 def vg_create_grid(dims, vox_size, origin_w, vox_inf, loc, spare, scratch, stream=None):
-    """dims = (gx, gy, gz); loc / spare: uint8 device tensors of gx*gy*gz
-    elements; scratch: uint8 device tensor (256-byte aligned)."""
+    """dims = (gx, gy, gz); loc / spare: uint8 device tensors of
+    vg_grid_bytes(gx, gy, gz) elements; scratch: uint8 device tensor of
+    vg_scratch_bytes(gx, gy, gz, vox_inf) elements (256-byte aligned)."""
     gx, gy, gz = (int(v) for v in dims)
     org = (ctypes.c_float * 3)(*[float(v) for v in np.asarray(origin_w, np.float32)])
     h = ctypes.c_void_p()
+    nb = min(loc.numel(), spare.numel())
     _check(lib().vg_create_grid(gx, gy, gz, vox_size, org, int(vox_inf), _ptr(loc), _ptr(spare),
-                                _ptr(scratch), scratch.numel() * scratch.element_size(),
+                                nb, _ptr(scratch), scratch.numel() * scratch.element_size(),
                                 _stream(stream), ctypes.byref(h)), "vg_create_grid")
     return h
 
@@ -191,7 +199,7 @@ def vg_grid_origin(g):
 
 
 def vg_read_grid(g, dst, stream=None):
-    """dst: uint8 tensor of gx*gy*gz elements (device or pinned/host)."""
+    """dst: uint8 tensor of gx*gy*gz elements (device or host), linear layout."""
     _check(lib().vg_read_grid(g, _ptr(dst), int(dst.is_cuda), _stream(stream)), "vg_read_grid")
 
 
@@ -200,7 +208,7 @@ def vg_write_grid(g, src, stream=None):
 
 
 def vg_set_profile_events(g, events):
-    """events: list of torch.cuda.Event (enable_timing=True), 6 per set; [] off.
+    """events: list of torch.cuda.Event (enable_timing=True), 5 per set; [] off.
     Each event is recorded once on the current device before its handle is
     passed on."""
     n = len(events)
@@ -222,17 +230,17 @@ def vg_destroy_grid(g):
 
 class GridBuffers:
     """Device buffers one grid needs, allocated with torch (the library itself
-    never allocates): loc, spare and scratch sized for vox_inf and `max_rays`."""
+    never allocates): loc, spare and scratch sized for the grid and vox_inf."""
 
-    def __init__(self, dims, vox_inf, max_rays, device="cuda"):
+    def __init__(self, dims, vox_inf, device="cuda"):
         import torch
         gx, gy, gz = dims
-        n = gx * gy * gz
+        n = vg_grid_bytes(gx, gy, gz)
+        nbytes = vg_scratch_bytes(gx, gy, gz, vox_inf)
+        if n == 0 or nbytes == 0:
+            raise ValueError("invalid grid size")
         self.dims = tuple(dims)
         self.loc = torch.empty(n, dtype=torch.uint8, device=device)
         self.spare = torch.empty(n, dtype=torch.uint8, device=device)
-        nbytes = vg_scratch_bytes(gx, gy, gz, vox_inf, max_rays)
-        if nbytes == 0:
-            raise ValueError("invalid grid size")
         self.scratch = torch.empty(nbytes, dtype=torch.uint8, device=device)
         assert self.scratch.data_ptr() % 256 == 0

@@ -25,10 +25,10 @@ def _say(msg):
 class GpuGrid:
     """One grid on the GPU plus an oracle twin fed the same frames."""
 
-    def __init__(self, dims, vox_size, origin, vox_inf, max_rays, init=None):
+    def __init__(self, dims, vox_size, origin, vox_inf, init=None):
         self.dims = tuple(dims)
         gx, gy, gz = dims
-        self.buf = vg.GridBuffers(dims, vox_inf, max_rays)
+        self.buf = vg.GridBuffers(dims, vox_inf)
         self.h = vg.vg_create_grid(dims, vox_size, origin, vox_inf, self.buf.loc, self.buf.spare,
                                    self.buf.scratch)
         self.vox_size = np.float32(vox_size)
@@ -90,7 +90,7 @@ def _fan_rays(fr):
 def test_plain_small_frames(index):
     fr = scenes.make_frame("plain-small", index)
     _say(f"plain-small frame {index}")
-    g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf, _fan_rays(fr))
+    g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf)
     g.integrate(fr)
     g.check(f"plain-small {index}")
     g.close()
@@ -101,7 +101,7 @@ def test_plain_medium_full_size():
     full grid compared."""
     fr = scenes.make_frame("plain-medium", 0)
     _say("plain-medium frame 0")
-    g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf, _fan_rays(fr))
+    g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf)
     g.integrate(fr)
     g.check("plain-medium 0")
     g.close()
@@ -111,8 +111,7 @@ def test_sequence_with_recentring_shifts():
     """Frames of different poses integrated into one resident grid, the grid
     re-centred on each camera before its frame (step 5, Sec. IV-E)."""
     frames = [scenes.make_frame("plain-small", i) for i in range(4, 10)]
-    rays = max(_fan_rays(f) for f in frames)
-    g = GpuGrid(frames[0].dims, frames[0].vox_size, frames[0].origin, frames[0].vox_inf, rays)
+    g = GpuGrid(frames[0].dims, frames[0].vox_size, frames[0].origin, frames[0].vox_inf)
     rng = np.random.default_rng(0)
     for k, fr in enumerate(frames):
         # keep the cameras close to each other so the shifts keep content
@@ -137,7 +136,7 @@ def test_random_six_dof_poses(seed):
     fr = scenes.random_pose_frame(rng, W, H, (90.0, 60.0), (0.3, 4.0), dims, 0.07, r, 40, 10)
     _say(f"six-dof seed {seed}")
     init = rng.integers(0, 3, dims[::-1]).astype(np.uint8)
-    g = GpuGrid(dims, fr.vox_size, fr.origin, r, _fan_rays(fr), init=init)
+    g = GpuGrid(dims, fr.vox_size, fr.origin, r, init=init)
     g.integrate(fr)
     g.check(f"six-dof {seed}")
     g.close()
@@ -149,7 +148,7 @@ def test_stage_parity_measurement_grid():
     fr = scenes.make_frame("plain-small", 11)
     _say("stage parity")
     gx, gy, gz = fr.dims
-    g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf, _fan_rays(fr),
+    g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf,
                 init=np.full((gz, gy, gx), 0xFF, np.uint8))
     ms, st = g.integrate(fr)
     got = g.read()
@@ -168,7 +167,7 @@ def test_points_input():
     pts = np.stack([fr.depth * ku[None, :], fr.depth * kv[:, None], fr.depth], -1).reshape(-1, 3)
     pts[::7] = np.nan        # invalid entries are skipped
     _say("points input")
-    g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf, _fan_rays(fr))
+    g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf)
     vg.vg_integrate_points(g.h, torch.from_numpy(np.ascontiguousarray(pts)).cuda(),
                            vg.pinhole_sensor(fr.intr), vg.make_pose(fr.R, fr.t))
     oracle.integrate_points(g.ref, g.origin(), g.vox_size, g.vox_inf, pts, fr.intr["fov_x"],
@@ -194,7 +193,7 @@ def test_spinning_sensor(vfov):
     sensor = vg.spinning_sensor(W, H, dcol, drow, math.radians(vfov), 0.3, 4.0)
     rays = vg.vg_fan_sizes(sensor, s)[3]
     _say(f"spinning vfov {vfov} rays {rays}")
-    g = GpuGrid(dims, s, origin, 1, rays)
+    g = GpuGrid(dims, s, origin, 1)
     vg.vg_integrate_frame(g.h, torch.from_numpy(img).cuda(), sensor, vg.make_pose(R, pos))
     _, st = oracle.integrate_spinning(g.ref, g.origin(), s, 1, img, col, row, math.radians(vfov),
                                       0.3, 4.0, R.astype(np.float32).reshape(-1),
@@ -206,10 +205,9 @@ def test_spinning_sensor(vfov):
 
 def test_edge_cases():
     fr = scenes.make_frame("plain-small", 13, size=(40, 30))
-    rays = _fan_rays(fr)
     # all-invalid frame: nothing occupied, the whole fan becomes free
     _say("edge: all-NaN")
-    g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf, rays)
+    g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf)
     fr_nan = scenes.make_frame("plain-small", 13, size=(40, 30))
     fr_nan.depth[:] = np.nan
     g.integrate(fr_nan)
@@ -222,8 +220,7 @@ def test_edge_cases():
     # camera outside the grid: rays start outside and enter
     _say("edge: camera outside")
     for off in ([6.0, 0.2, 0.1], [-6.0, 0.3, 0.0], [0.1, 0.2, 3.0]):
-        g = GpuGrid(fr.dims, fr.vox_size, fr.origin + np.array(off, np.float32), fr.vox_inf,
-                    rays)
+        g = GpuGrid(fr.dims, fr.vox_size, fr.origin + np.array(off, np.float32), fr.vox_inf)
         g.integrate(fr)
         g.check(f"camera outside {off}")
         g.close()
@@ -231,7 +228,7 @@ def test_edge_cases():
     for r, dims in [(0, (30, 20, 10)), (3, (7, 5, 3)), (1, (1, 1, 1))]:
         _say(f"edge: r={r} dims={dims}")
         g = GpuGrid(dims, fr.vox_size, (fr.t - np.array(dims) * fr.vox_size / 2).astype(np.float32),
-                    r, rays)
+                    r)
         g.integrate(fr)
         g.check(f"r={r} dims={dims}")
         g.close()
@@ -239,7 +236,7 @@ def test_edge_cases():
 
 def test_empty_image_and_empty_point_cloud():
     fr = scenes.make_frame("plain-small", 14, size=(16, 12))
-    g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf, _fan_rays(fr))
+    g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf)
     _say("edge: empty point cloud")
     vg.vg_integrate_points(g.h, torch.zeros((0, 3), dtype=torch.float32, device="cuda"),
                            vg.pinhole_sensor(fr.intr), vg.make_pose(fr.R, fr.t))
@@ -252,7 +249,7 @@ def test_empty_image_and_empty_point_cloud():
 def test_stamp_wraparound_over_many_frames():
     """The per-frame occupancy stamp is a byte that wraps after 255 frames."""
     fr = scenes.make_frame("plain-small", 15, size=(24, 18), dims=(24, 24, 12))
-    g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf, _fan_rays(fr))
+    g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf)
     rng = np.random.default_rng(9)
     _say("stamp wraparound")
     base = fr.depth.copy()
@@ -269,7 +266,7 @@ def test_shift_parity():
     rng = np.random.default_rng(21)
     dims = (37, 29, 17)
     init = rng.integers(0, 3, dims[::-1]).astype(np.uint8)
-    g = GpuGrid(dims, 0.1, [0, 0, 0], 1, 64, init=init)
+    g = GpuGrid(dims, 0.1, [0, 0, 0], 1, init=init)
     for d in [(1, 0, 0), (-3, 2, 1), (0, 0, -5), (40, 0, 0), (-2, -30, 3), (0, 0, 0)]:
         _say(f"shift {d}")
         g.shift(d)
@@ -280,19 +277,22 @@ def test_shift_parity():
 
 def test_determinism_and_budget():
     fr = scenes.make_frame("plain-small", 16)
-    rays = _fan_rays(fr)
     outs = []
     for _ in range(2):
-        g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf, rays)
+        g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf)
         g.integrate(fr)
         outs.append(g.read())
         g.close()
     assert np.array_equal(outs[0], outs[1])
-    # a workspace sized for fewer rays is refused without touching the grid
-    g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf, rays // 2)
+    # buffers smaller than the grid needs are refused
+    gx, gy, gz = fr.dims
+    small = torch.empty(vg.vg_scratch_bytes(gx, gy, gz, fr.vox_inf) - 256, dtype=torch.uint8,
+                        device="cuda")
+    buf = vg.GridBuffers(fr.dims, fr.vox_inf)
     with pytest.raises(vg.VgError) as ei:
-        g.integrate(fr)
+        vg.vg_create_grid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf, buf.loc, buf.spare, small)
     assert ei.value.status == vg.VG_ERR_BUDGET
-    g.ref[:] = 0
-    g.check("budget refusal leaves grid unknown")
-    g.close()
+    with pytest.raises(vg.VgError) as ei:
+        vg.vg_create_grid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf, buf.loc[:-32],
+                          buf.spare, buf.scratch)
+    assert ei.value.status == vg.VG_ERR_BUDGET

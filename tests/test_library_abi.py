@@ -65,14 +65,15 @@ def test_fan_sizes_rejects_bad_sensors():
         vg.vg_fan_sizes(s, 0.1)
 
 
-def test_scratch_bytes():
-    a = vg.vg_scratch_bytes(100, 100, 50, 2, 1000)
-    b = vg.vg_scratch_bytes(100, 100, 50, 2, 2000)
-    c = vg.vg_scratch_bytes(100, 100, 50, 3, 1000)
-    assert a > 100 * 100 * 50 and b - a == 1000 * 32 and c > a
-    assert vg.vg_scratch_bytes(0, 1, 1, 1, 10) == 0
-    assert vg.vg_scratch_bytes(2048, 2048, 1024, 1, 10) == 0     # >= 2^31 voxels
-    assert vg.vg_scratch_bytes(8, 8, 8, 17, 10) == 0             # vox_inf above 16
+def test_scratch_and_grid_bytes():
+    a = vg.vg_scratch_bytes(100, 100, 50, 2)
+    c = vg.vg_scratch_bytes(100, 100, 50, 3)
+    assert a > 128 * 100 * 50 and c > a
+    assert vg.vg_grid_bytes(100, 100, 50) == 128 * 100 * 50     # rows padded to 32 voxels
+    assert vg.vg_grid_bytes(200, 200, 100) == 224 * 200 * 100
+    assert vg.vg_scratch_bytes(0, 1, 1, 1) == 0
+    assert vg.vg_grid_bytes(2048, 2048, 1024) == 0               # >= 2^31 bytes
+    assert vg.vg_scratch_bytes(8, 8, 8, 17) == 0                 # vox_inf above 16
 
 
 def test_create_grid_argument_errors_leave_no_handle():
@@ -80,23 +81,26 @@ def test_create_grid_argument_errors_leave_no_handle():
     P = ctypes.c_void_p
     org = (ctypes.c_float * 3)(0, 0, 0)
     fake_a, fake_b, fake_s = P(0x100000), P(0x200000), P(0x300000)
-    big = vg.vg_scratch_bytes(4, 4, 4, 1, 64)
+    big = vg.vg_scratch_bytes(4, 4, 4, 1)
+    gb = vg.vg_grid_bytes(4, 4, 4)
 
-    def create(gx=4, gy=4, gz=4, s=0.1, origin=org, r=1, a=fake_a, b=fake_b, scr=fake_s,
-               nbytes=big):
+    def create(gx=4, gy=4, gz=4, s=0.1, origin=org, r=1, a=fake_a, b=fake_b, nb=gb,
+               scr=fake_s, nbytes=big):
         h = P(1234)
-        st = L.vg_create_grid(gx, gy, gz, s, origin, r, a, b, scr, nbytes, None, ctypes.byref(h))
+        st = L.vg_create_grid(gx, gy, gz, s, origin, r, a, b, nb, scr, nbytes, None,
+                              ctypes.byref(h))
         return st, h.value
 
     for kw in [dict(gx=0), dict(gz=-1), dict(gx=2048, gy=2048, gz=1024), dict(s=0.0),
                dict(s=float("nan")), dict(r=-1), dict(r=17), dict(gy=70000),
                dict(origin=(ctypes.c_float * 3)(0, float("inf"), 0)), dict(a=P(0)),
-               dict(b=fake_a), dict(scr=P(0x300010))]:
+               dict(b=fake_a), dict(scr=P(0x300010)), dict(a=P(0x100004))]:
         st, h = create(**kw)
         assert st == vg.VG_ERR_ARG and h is None, kw
-    st, h = create(nbytes=100)
-    assert st == vg.VG_ERR_BUDGET and h is None
-    assert L.vg_create_grid(4, 4, 4, 0.1, org, 1, fake_a, fake_b, fake_s, big, None,
+    for kw in [dict(nbytes=100), dict(nb=gb - 1)]:
+        st, h = create(**kw)
+        assert st == vg.VG_ERR_BUDGET and h is None, kw
+    assert L.vg_create_grid(4, 4, 4, 0.1, org, 1, fake_a, fake_b, gb, fake_s, big, None,
                             None) == vg.VG_ERR_ARG
 
 
