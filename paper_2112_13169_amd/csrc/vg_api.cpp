@@ -417,10 +417,10 @@ vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_float
 
     RayParams rp;
     std::memcpy(rp.R, T->R, sizeof rp.R);
-    std::memcpy(rp.o, o, sizeof rp.o);
-    std::memcpy(rp.v0, v0, sizeof rp.v0);
-    std::memcpy(rp.n, g->n, sizeof rp.n);
-    rp.gxp = g->lay.gxp;
+    std::memcpy(rp.wf.o, o, sizeof rp.wf.o);
+    std::memcpy(rp.wf.v0, v0, sizeof rp.wf.v0);
+    std::memcpy(rp.wf.n, g->n, sizeof rp.wf.n);
+    rp.wf.gxp = g->lay.gxp;
     rp.kind = kind == kSpinning ? kSpinning : kPinhole;
     rp.vd = fan.vd;
     rp.hw = fan.hw;

@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "vg_walk.h"
+
 namespace vg {
 
 // Voxel values in the local grid.
@@ -72,10 +74,7 @@ struct SeedParams {
 // targets (tile_a along a / column, tile_b along b / z).
 struct RayParams {
     float R[9];
-    float o[3];       // camera position in voxel units
-    int32_t v0[3];    // camera voxel
-    int32_t n[3];
-    int32_t gxp;      // grid row pitch
+    WalkFrame wf;     // camera position / voxel, grid size and pitch
     int32_t kind;     // kPinhole (also points) or kSpinning
     int32_t vd, hw, hh;   // pinhole fan; spinning: hh = largest half height
     int32_t na, nb;       // fan extent along a and b

@@ -25,6 +25,7 @@
 // one, fp32 denormals are kept.  The fixed operation orders are those of the
 // transform (R p + t, left to right) and of the Amanatides & Woo walk.
 #include "vg_internal.h"
+#include "vg_walk.h"
 
 #include <algorithm>
 
@@ -35,7 +36,6 @@ namespace vg {
 namespace {
 
 constexpr int kBlock = 256;
-constexpr int kChunk = 8;   // walk steps whose occupancy words load together
 
 // ----------------------------------------------------------------- helpers
 
@@ -90,115 +90,6 @@ __device__ __forceinline__ bool fan_target(const RayParams &p, int32_t ia, int32
         tz = p.vd;
         m2 = tx * tx + ty * ty + p.vd * p.vd;
     }
-    return true;
-}
-
-// Amanatides & Woo set-up on one axis.
-__device__ __forceinline__ void axis_setup(float o, int32_t v0, float d, int32_t &step,
-                                           float &tmax, float &tdelta)
-{
-    if (d > 0.0f) {
-        step = 1;
-        tmax = ((float)(v0 + 1) - o) / d;
-        tdelta = 1.0f / d;
-    } else if (d < 0.0f) {
-        step = -1;
-        tmax = ((float)v0 - o) / d;
-        tdelta = -1.0f / d;
-    } else {
-        step = 0;
-        tmax = __builtin_inff();
-        tdelta = __builtin_inff();
-    }
-}
-
-// Walk state of one ray.  Scalar fields and select chains: an array indexed
-// by the stepping axis would be demoted to private memory, and if / else
-// chains become exec-mask branches.
-struct Walk {
-    float tmx, tmy, tmz;      // ray parameter of the next boundary per axis
-    float tdx, tdy, tdz;      // ray parameter per voxel per axis
-    int32_t cx, cy, cz;       // steps taken on each axis (= |v - v0| per axis)
-    int32_t lx, ly, lz;       // steps on each axis after which the ray is outside
-    int32_t ex, ey, ez;       // steps on each axis before the ray is inside
-    int32_t sx, sy, sz;       // index stride of one step on each axis
-    int32_t d2;               // squared lattice distance from the camera voxel
-    uint32_t idx;             // device-layout index of the current voxel (mod 2^32)
-};
-
-// Steps along one axis before the walk leaves the grid (0 for an axis the
-// ray does not move on: choosing it ends the walk) and before it enters.
-__device__ __forceinline__ void axis_limits(int32_t step, int32_t v0, int32_t n, int32_t &leave,
-                                            int32_t &enter)
-{
-    leave = step > 0 ? n - v0 : (step < 0 ? v0 + 1 : 0);
-    enter = step > 0 ? max(-v0, 0) : (step < 0 ? max(v0 - n + 1, 0) : 0);
-}
-
-__device__ __forceinline__ void walk_setup(Walk &w, const RayParams &p, const float dir[3])
-{
-    int32_t sx, sy, sz;
-    axis_setup(p.o[0], p.v0[0], dir[0], sx, w.tmx, w.tdx);
-    axis_setup(p.o[1], p.v0[1], dir[1], sy, w.tmy, w.tdy);
-    axis_setup(p.o[2], p.v0[2], dir[2], sz, w.tmz, w.tdz);
-    axis_limits(sx, p.v0[0], p.n[0], w.lx, w.ex);
-    axis_limits(sy, p.v0[1], p.n[1], w.ly, w.ey);
-    axis_limits(sz, p.v0[2], p.n[2], w.lz, w.ez);
-    w.sx = sx;
-    w.sy = sy * p.gxp;
-    w.sz = sz * p.gxp * p.n[1];
-    w.cx = w.cy = w.cz = 0;
-    w.d2 = 0;
-    w.idx = (uint32_t)((int64_t)p.v0[0] + (int64_t)p.gxp * (p.v0[1] + (int64_t)p.n[1] * p.v0[2]));
-}
-
-// An axis on which the camera lies outside the grid and the ray does not
-// move towards it: such a ray never enters the grid.
-__device__ __forceinline__ bool axis_dead(int32_t step, int32_t v0, int32_t n)
-{
-    const bool outside = v0 < 0 || v0 >= n;
-    const bool towards = (step > 0 && v0 < 0) || (step < 0 && v0 >= n);
-    return outside && !towards;
-}
-
-// One step of Alg. 2: move along the axis whose boundary is nearest (ties
-// go to the later axis).  Returns false when the walk is over: the length
-// of Alg. 2 is reached, the direction is zero, or the ray left the grid on
-// an axis it keeps moving away on (the grid is convex: it cannot return).
-// kGeneral: the camera may be outside, so `in` reports whether the new voxel
-// lies in the grid; otherwise every voxel of the walk does.
-// Value selects.  A conditional expression over two lvalues is itself an
-// lvalue in C++, so `c ? w.a : w.b` selects an address and forces the walk
-// state into memory; selecting copied values keeps it in registers.
-__device__ __forceinline__ int32_t sel(bool c, int32_t a, int32_t b) { return c ? a : b; }
-__device__ __forceinline__ float self(bool c, float a, float b) { return c ? a : b; }
-
-template <bool kGeneral>
-__device__ __forceinline__ bool walk_step(Walk &w, int32_t m2, bool &in)
-{
-    if (w.d2 >= m2)
-        return false;
-    const float tmx = w.tmx, tmy = w.tmy, tmz = w.tmz;
-    const int32_t cx = w.cx, cy = w.cy, cz = w.cz;
-    const bool lxy = tmx < tmy;
-    const bool ax = lxy && (tmx < tmz);
-    const bool ay = !lxy && (tmy < tmz);
-    const bool az = !(ax || ay);
-    const int32_t c = sel(ax, cx, sel(ay, cy, cz));
-    const int32_t leave = sel(ax, w.lx, sel(ay, w.ly, w.lz));
-    if (c + 1 >= leave)
-        return false;
-    const int32_t stride = sel(ax, w.sx, sel(ay, w.sy, w.sz));
-    w.tmx = self(ax, tmx + w.tdx, tmx);
-    w.tmy = self(ay, tmy + w.tdy, tmy);
-    w.tmz = self(az, tmz + w.tdz, tmz);
-    w.cx = cx + sel(ax, 1, 0);
-    w.cy = cy + sel(ay, 1, 0);
-    w.cz = cz + sel(az, 1, 0);
-    w.d2 += 2 * c + 1;
-    w.idx += (uint32_t)stride;
-    if (kGeneral)
-        in = w.cx >= w.ex && w.cy >= w.ey && w.cz >= w.ez;
     return true;
 }
 
@@ -370,51 +261,13 @@ __global__ __launch_bounds__(kBlock) void k_rays(RayParams p)
         return;
     float dir[3];
     ray_direction(p, tx, ty, tz, dir);
-    if (kGeneral && (axis_dead(dir[0] > 0.0f ? 1 : (dir[0] < 0.0f ? -1 : 0), p.v0[0], p.n[0]) ||
-                     axis_dead(dir[1] > 0.0f ? 1 : (dir[1] < 0.0f ? -1 : 0), p.v0[1], p.n[1]) ||
-                     axis_dead(dir[2] > 0.0f ? 1 : (dir[2] < 0.0f ? -1 : 0), p.v0[2], p.n[2])))
+    if (kGeneral && (axis_dead(sgn(dir[0]), p.wf.v0[0], p.wf.n[0]) ||
+                     axis_dead(sgn(dir[1]), p.wf.v0[1], p.wf.n[1]) ||
+                     axis_dead(sgn(dir[2]), p.wf.v0[2], p.wf.n[2])))
         return;
     Walk w;
-    walk_setup(w, p, dir);
-
-    const uint8_t stamp = (uint8_t)p.epoch;
-    bool before_hit = true;   // Alg. 2: vox_val is still "free"
-    bool alive = true;
-    while (alive) {
-        uint32_t ids[kChunk];
-        bool val[kChunk];
-#pragma unroll
-        for (int s = 0; s < kChunk; ++s) {
-            bool in = true;
-            val[s] = false;
-            if (alive) {
-                alive = walk_step<kGeneral>(w, m2, in);
-                val[s] = alive && in;
-            }
-            ids[s] = w.idx;
-        }
-        // occupancy of the new voxels (only needed before the hit)
-        uint32_t word[kChunk];
-#pragma unroll
-        for (int s = 0; s < kChunk; ++s)
-            word[s] = (val[s] && before_hit) ? p.occ[ids[s] >> 5] : 0u;
-        int hit = kChunk;
-#pragma unroll
-        for (int s = kChunk - 1; s >= 0; --s)
-            if ((word[s] >> (ids[s] & 31u)) & 1u)
-                hit = s;
-#pragma unroll
-        for (int s = 0; s < kChunk; ++s) {
-            if (!val[s])
-                continue;
-            if (before_hit && s < hit)
-                p.loc[ids[s]] = kFree;
-            else if (s != hit)
-                p.traced[ids[s]] = stamp;
-        }
-        if (hit < kChunk)
-            before_hit = false;
-    }
+    walk_setup(w, p.wf, dir);
+    walk_ray<kGeneral>(w, m2, p.occ, p.loc, p.traced, (uint8_t)p.epoch);
 }
 
 // Alg. 3 for the prioritised marks.  One lane per 16 voxels of a grid row:

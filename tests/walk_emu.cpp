@@ -1,0 +1,103 @@
+// Host build of the kernel's ray walk (paper_2112_13169_amd/csrc/vg_walk.h),
+// checked ray by ray against the CPU oracle's walk.  Random grids, random
+// occupancy, random rays from inside and outside the grid.  Prints the
+// number of mismatching voxels and exits non-zero if there is any.
+#include <cstdio>
+#include <cstdlib>
+#include <vector>
+
+#include "../oracle/vg_oracle.h"
+#include "../paper_2112_13169_amd/csrc/vg_walk.h"
+
+using namespace vg;
+
+static uint64_t rng_state = 0x9E3779B97F4A7C15ull;
+static uint32_t rnd()
+{
+    rng_state ^= rng_state << 13;
+    rng_state ^= rng_state >> 7;
+    rng_state ^= rng_state << 17;
+    return (uint32_t)(rng_state >> 11);
+}
+
+int main(int argc, char **argv)
+{
+    const int trials = argc > 1 ? atoi(argv[1]) : 2000;
+    rng_state += argc > 2 ? (uint64_t)atoll(argv[2]) : 0;
+    long long bad = 0, voxels = 0, steps = 0;
+    for (int trial = 0; trial < trials; ++trial) {
+        WalkFrame f;
+        f.n[0] = 1 + rnd() % 48;
+        f.n[1] = 1 + rnd() % 40;
+        f.n[2] = 1 + rnd() % 24;
+        f.gxp = 32 * ((f.n[0] + 31) / 32);
+        const int nx = f.n[0], ny = f.n[1], nz = f.n[2];
+        const bool outside = trial % 4 == 3;
+        for (int a = 0; a < 3; ++a) {
+            float span = outside ? 3.0f * f.n[a] : (float)f.n[a];
+            float off = outside ? -1.0f * f.n[a] : 0.0f;
+            f.o[a] = off + span * (float)(rnd() % 100000) / 100000.0f;
+            if (!outside && f.o[a] >= f.n[a])
+                f.o[a] = f.n[a] - 0.5f;
+            if (trial % 7 == 0)
+                f.o[a] = floorf(f.o[a]) + 0.5f;   // voxel centres: ties in the walk
+            f.v0[a] = (int32_t)floorf(f.o[a]);
+        }
+        const bool inside = f.v0[0] >= 0 && f.v0[0] < nx && f.v0[1] >= 0 && f.v0[1] < ny &&
+                            f.v0[2] >= 0 && f.v0[2] < nz;
+        std::vector<uint32_t> occ((size_t)f.gxp / 32 * ny * nz + 1, 0);
+        std::vector<uint8_t> ms((size_t)nx * ny * nz, 0);
+        const uint32_t density = 8 + rnd() % 120;
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x)
+                    if (rnd() % density == 0) {
+                        size_t j = (size_t)x + (size_t)f.gxp * (y + (size_t)ny * z);
+                        occ[j >> 5] |= 1u << (j & 31);
+                        ms[x + (size_t)nx * (y + (size_t)ny * z)] = OG_OCCUPIED;
+                    }
+        float dir[3];
+        for (int a = 0; a < 3; ++a) {
+            int k = (int)(rnd() % 61) - 30;
+            dir[a] = trial % 5 == 0 ? (float)k : (float)k * 0.37f + (float)(rnd() % 1000) * 1e-4f;
+            if (trial % 11 == 0 && a == trial % 3)
+                dir[a] = 0.0f;
+        }
+        const int32_t m2 = 1 + (int32_t)(rnd() % 4000);
+        std::vector<uint8_t> loc((size_t)f.gxp * ny * nz, 0), tr((size_t)f.gxp * ny * nz, 0);
+        const uint8_t stamp = 1 + rnd() % 255;
+
+        bool dead = false;
+        for (int a = 0; a < 3; ++a)
+            dead = dead || axis_dead(sgn(dir[a]), f.v0[a], f.n[a]);
+        if (!dead) {
+            Walk w;
+            walk_setup(w, f, dir);
+            if (inside)
+                walk_ray<false>(w, m2, occ.data(), loc.data(), tr.data(), stamp);
+            else
+                walk_ray<true>(w, m2, occ.data(), loc.data(), tr.data(), stamp);
+        }
+        std::vector<uint8_t> ref = ms;
+        steps += og_trace_ray(f.o, dir, m2, nx, ny, nz, ref.data(), nullptr, nullptr, 0);
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    size_t i = x + (size_t)nx * (y + (size_t)ny * z);
+                    size_t j = x + (size_t)f.gxp * (y + (size_t)ny * z);
+                    int got = ms[i] == OG_OCCUPIED ? OG_OCCUPIED
+                              : tr[j] == stamp     ? OG_TRACED
+                              : loc[j] == 1        ? OG_FREE
+                                                   : OG_UNKNOWN;
+                    if (got != ref[i]) {
+                        if (bad < 5)
+                            fprintf(stderr, "trial %d voxel (%d,%d,%d): oracle %d walk %d\n", trial,
+                                    x, y, z, ref[i], got);
+                        ++bad;
+                    }
+                    ++voxels;
+                }
+    }
+    printf("trials %d voxels %lld oracle-steps %lld mismatches %lld\n", trials, voxels, steps, bad);
+    return bad != 0;
+}
