@@ -166,8 +166,9 @@ vg_status vg_write_grid(vg_grid *g, const uint8_t *src, int32_t src_is_device, v
  * vg_integrate_points call k records the caller's events (hipEvent_t)
  * events[5*j + 0..4], j = k mod n_sets, on its stream: before the seed pass,
  * after it, after the dilation, after the ray walk and after the resolve pass,
- * so that event pairs time each stage.  The array is copied; the events must
- * stay alive while set.  n_sets = 0 (events may be NULL) turns recording off. */
+ * so that event pairs time each stage; a NULL entry is not recorded.  The
+ * array is copied; the events must stay alive while set.  n_sets = 0 (events
+ * may be NULL) turns recording off. */
 vg_status vg_set_profile_events(vg_grid *g, void *const *events, int32_t n_sets);
 
 /* Release the handle (host metadata only; caller buffers are untouched).

@@ -378,7 +378,7 @@ vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_float
         ev = &g->prof[kProfileEvents * (size_t)(g->prof_next++ % sets)];
     }
     auto mark = [&](int k) {
-        if (ev && e == hipSuccess)
+        if (ev && ev[k] && e == hipSuccess)
             e = hipEventRecord(ev[k], st);
     };
 
@@ -654,11 +654,8 @@ vg_status vg_set_profile_events(vg_grid *g, void *const *events, int32_t n_sets)
     if (!g || n_sets < 0 || (n_sets > 0 && !events))
         return VG_ERR_ARG;
     std::vector<hipEvent_t> v;
-    for (int64_t i = 0; i < kProfileEvents * (int64_t)n_sets; ++i) {
-        if (!events[i])
-            return VG_ERR_ARG;
+    for (int64_t i = 0; i < kProfileEvents * (int64_t)n_sets; ++i)
         v.push_back(static_cast<hipEvent_t>(events[i]));
-    }
     g->prof.swap(v);
     g->prof_next = 0;
     return VG_OK;

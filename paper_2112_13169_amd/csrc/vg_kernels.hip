@@ -304,27 +304,43 @@ __global__ __launch_bounds__(kBlock) void k_resolve(Planes pl, uint8_t *loc, int
 }
 
 // Sec. IV-E: dst[x,y,z] = src[x+dx, y+dy, z+dz] inside, else unknown.  One
-// lane per 4 voxels of a device-layout row (padding bytes become unknown).
+// lane per 16 voxels of a device-layout row (padding bytes become unknown).
+// Rows whose source row is outside the grid are cleared without loads; the
+// common case reads five aligned dwords and realigns them with v_alignbyte.
 __global__ __launch_bounds__(kBlock) void k_shift(const uint8_t *src, uint8_t *dst, int32_t nx,
                                                   int32_t ny, int32_t nz, int32_t pitch,
                                                   int32_t dx, int32_t dy, int32_t dz)
 {
-    const int32_t x0 = 4 * (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    const int32_t x0 = 16 * (int32_t)(blockIdx.x * kBlock + threadIdx.x);
     const int32_t y = blockIdx.y, z = blockIdx.z;
     if (x0 >= pitch)
         return;
     const int64_t sy = (int64_t)y + dy, sz = (int64_t)z + dz;
-    uint32_t out = 0;
+    uint32_t out[4] = {0u, 0u, 0u, 0u};
     if (sy >= 0 && sy < ny && sz >= 0 && sz < nz) {
         const uint8_t *row = src + pitch * (sy + (int64_t)ny * sz);
+        const int64_t s0 = (int64_t)x0 + dx;
+        if (x0 + 16 <= nx && s0 >= 0 && s0 + 16 <= nx && (s0 & ~3ll) + 20 <= pitch) {
+            const uint32_t *w = reinterpret_cast<const uint32_t *>(row + (s0 & ~3ll));
+            const uint32_t sh = (uint32_t)(s0 & 3);
+            uint32_t v[5];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t x = (int64_t)x0 + j, sx = x + dx;
-            if (x < nx && sx >= 0 && sx < nx)
-                out |= (uint32_t)row[sx] << (8 * j);
+            for (int k = 0; k < 5; ++k)
+                v[k] = w[k];
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                out[k] = __builtin_amdgcn_alignbyte(v[k + 1], v[k], sh);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int64_t x = (int64_t)x0 + j, sx = x + dx;
+                if (x < nx && sx >= 0 && sx < nx)
+                    out[j >> 2] |= (uint32_t)row[sx] << (8 * (j & 3));
+            }
         }
     }
-    *reinterpret_cast<uint32_t *>(dst + pitch * (y + (int64_t)ny * z) + x0) = out;
+    *reinterpret_cast<uint4 *>(dst + pitch * (y + (int64_t)ny * z) + x0) =
+        make_uint4(out[0], out[1], out[2], out[3]);
 }
 
 uint32_t blocks_for(int64_t threads) { return (uint32_t)((threads + kBlock - 1) / kBlock); }
@@ -398,7 +414,7 @@ hipError_t launch_shift(const uint8_t *src, uint8_t *dst, const int32_t n[3], co
                         hipStream_t st)
 {
     const int32_t pitch = grid_pitch(n[0]);
-    dim3 grid((uint32_t)((pitch / 4 + kBlock - 1) / kBlock), (uint32_t)n[1], (uint32_t)n[2]);
+    dim3 grid((uint32_t)((pitch / 16 + kBlock - 1) / kBlock), (uint32_t)n[1], (uint32_t)n[2]);
     hipLaunchKernelGGL(k_shift, grid, dim3(kBlock), 0, st, src, dst, n[0], n[1], n[2], pitch,
                        d[0], d[1], d[2]);
     return hipGetLastError();

@@ -208,13 +208,16 @@ def vg_write_grid(g, src, stream=None):
 
 
 def vg_set_profile_events(g, events):
-    """events: list of torch.cuda.Event (enable_timing=True), 5 per set; [] off.
-    Each event is recorded once on the current device before its handle is
-    passed on."""
+    """events: list of torch.cuda.Event (enable_timing=True) or None (not
+    recorded), 5 per set; [] turns recording off.  Each event is recorded once
+    on the current device before its handle is passed on."""
     n = len(events)
     assert n % PROFILE_EVENTS == 0
     arr = (ctypes.c_void_p * max(n, 1))()
     for i, e in enumerate(events):
+        if e is None:
+            arr[i] = None
+            continue
         if not e.cuda_event:
             e.record()          # torch creates the hipEvent_t lazily
         arr[i] = e.cuda_event
