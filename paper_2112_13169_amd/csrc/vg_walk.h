@@ -10,10 +10,12 @@
 #ifdef __HIPCC__
 #define VG_HD __device__ __forceinline__
 #define VG_INF __builtin_inff()
+#define vg_any(p) __any(p)
 #else
 #include <cmath>
 #define VG_HD static inline
 #define VG_INF INFINITY
+#define vg_any(p) (p)   // host build: one lane per "wavefront"
 #endif
 
 namespace vg {
@@ -169,10 +171,17 @@ VG_HD bool walk_chunk(Walk &w, int32_t m2, bool alive, Chunk &c, bool load,
         c.ids[s] = w.idx;
         c.valid |= (alive && in) ? (1u << s) : 0u;
     }
+    // a wavefront whose rays have all met their obstacle loads nothing
+    if (vg_any(load)) {
 #pragma unroll
-    for (int s = 0; s < kChunk; ++s) {
-        const bool need = load && ((c.valid >> s) & 1u);
-        c.words[s] = occ[need ? c.ids[s] >> 5 : 0u];
+        for (int s = 0; s < kChunk; ++s) {
+            const bool need = load && ((c.valid >> s) & 1u);
+            c.words[s] = occ[need ? c.ids[s] >> 5 : 0u];
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < kChunk; ++s)
+            c.words[s] = 0u;
     }
     return alive;
 }
