@@ -43,31 +43,27 @@ ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 CAL_BYTES = 64 << 20            # calibration copy: 64 MiB read + 64 MiB written
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-KERNEL_SOURCES = ["paper_2112_13169_amd/csrc/vg_kernels.hip", "paper_2112_13169_amd/csrc/vg_walk.h",
-                  "paper_2112_13169_amd/csrc/vg_internal.h"]
 
 
-def kernel_source_hash():
-    import hashlib
-    h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, rel), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+STAGE_KERNELS = {"k_dilate": ["k_dilate_x", "k_dilate_yz"],
+                 "k_rays": ["k_rays<false>", "k_rays<true>"]}
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed counter summary,
-    or None if absent or taken on kernel sources that have changed since."""
+def measured_traffic(stage):
+    """Memory-side bytes per launch of a stage's kernels from the committed
+    counter summary, or None if absent or taken on kernel sources that have
+    changed since."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
+    from paper_2112_13169_amd.prof_summary import kernel_source_hash
     if t.get("source_hash") != kernel_source_hash() or t.get("workload") != WORKLOAD:
         return None
-    k = t.get("kernels", {}).get(kernel)
-    return None if k is None else k.get("hbm_bytes_per_launch")
+    got = [t["kernels"][k]["hbm_bytes_per_launch"] for k in STAGE_KERNELS.get(stage, [stage])
+           if k in t.get("kernels", {})]
+    return float(sum(got)) if got else None
 
 
 def cpu_model():
@@ -181,23 +177,22 @@ def main():
         cpu_times.append(time.perf_counter() - c0)
         k += 1
 
-    # ---- GPU: warmup; a stage pass (every kernel bracketed by events) picks the
-    # dominant kernel; a latency pass (events at each frame's start and end);
-    # then the timed region, where only the dominant kernel is bracketed.
+    # ---- GPU: warmup; a stage pass (every stage timed by events its kernel
+    # dispatches record) picks the dominant kernel; a latency pass (start of the
+    # shift to end of the resolve pass); then the timed region, where only the
+    # dominant kernel's dispatches record events.
     buf, h = new_grid()
     for k in range(args.warmup):
         step(h, k)
     K = args.steps
     E = vg.PROFILE_EVENTS
-    names = ["k_shift"] + ["k_" + n for n in vg.PROFILE_STAGES]
+    names = ["k_" + n for n in vg.PROFILE_STAGES]
 
-    def run(k0, profile, starts=None, origins=None):
+    def run(k0, profile, origins=None):
         vg.vg_set_profile_events(h, profile)
         torch.cuda.synchronize()
         w0 = time.perf_counter()
         for k in range(K):
-            if starts is not None:
-                starts[k].record(stream)
             step(h, k0 + k, origins)
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
@@ -207,43 +202,40 @@ def main():
     def ev():
         return torch.cuda.Event(enable_timing=True)
 
-    # stage pass
-    st_start = [ev() for _ in range(K)]
+    def pair_ms(evs, j):
+        return np.array([evs[E * k + 2 * j].elapsed_time(evs[E * k + 2 * j + 1])
+                         for k in range(K)])
+
+    # stage pass: every stage timed by its own kernel dispatches
     st_ev = [ev() for _ in range(E * K)]
-    run(args.warmup, st_ev, st_start)
-    stage_ms = {"k_shift": np.array([st_start[k].elapsed_time(st_ev[E * k]) for k in range(K)])}
-    for j, name in enumerate(vg.PROFILE_STAGES):
-        stage_ms["k_" + name] = np.array([st_ev[E * k + j].elapsed_time(st_ev[E * k + j + 1])
-                                          for k in range(K)])
+    run(args.warmup, st_ev)
+    stage_ms = {name: pair_ms(st_ev, j) for j, name in enumerate(names)}
     kernels = {k: float(v.mean()) for k, v in stage_ms.items()}
     dominant = max(kernels, key=kernels.get)
 
-    # latency pass: frame start (before the shift) .. end of the resolve pass
+    # latency pass: start of the shift .. end of the resolve pass
     lat_start = [ev() for _ in range(K)]
     lat_end = [ev() for _ in range(K)]
     prof = []
+    i_shift, i_resolve = names.index("k_shift"), names.index("k_resolve")
     for k in range(K):
-        prof += [None] * (E - 1) + [lat_end[k]]
-    run(args.warmup + K, prof, lat_start)
+        row = [None] * E
+        row[2 * i_shift] = lat_start[k]
+        row[2 * i_resolve + 1] = lat_end[k]
+        prof += row
+    run(args.warmup + K, prof)
     lat = np.array([lat_start[k].elapsed_time(lat_end[k]) for k in range(K)])
 
-    # timed region: K steps, only the dominant kernel bracketed by events
-    dom_a = [ev() for _ in range(K)]
-    dom_b = [ev() for _ in range(K)]
-    prof = []
+    # timed region: K steps, only the dominant kernel's dispatches timed
+    dom_ev = []
     j = names.index(dominant)
     for k in range(K):
         row = [None] * E
-        if j > 0:
-            row[j - 1], row[j] = dom_a[k], dom_b[k]
-        prof += row
+        row[2 * j], row[2 * j + 1] = ev(), ev()
+        dom_ev += row
     origins = []
-    wall = run(args.warmup + 2 * K, prof, dom_a if j == 0 else None, origins)
-    if j == 0:   # the shift: from the frame start to the first stage event
-        dom_ms = None
-    else:
-        dom_ms = float(np.mean([dom_a[k].elapsed_time(dom_b[k]) for k in range(K)]))
-    kernel_live_ms = dom_ms if dom_ms is not None else kernels[dominant]
+    wall = run(args.warmup + 2 * K, dom_ev, origins)
+    kernel_live_ms = float(pair_ms(dom_ev, j).mean())
     ms_per_step = wall * 1e3 / K
     fps = 1e3 / ms_per_step
 

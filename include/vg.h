@@ -162,13 +162,18 @@ vg_status vg_read_grid(const vg_grid *g, uint8_t *dst, int32_t dst_is_device, vo
 /* Overwrite the local grid (restore a checkpoint) from src (linear layout). */
 vg_status vg_write_grid(vg_grid *g, const uint8_t *src, int32_t src_is_device, void *stream);
 
-/* Measurement hook.  With n_sets > 0, each following vg_integrate_frame /
- * vg_integrate_points call k records the caller's events (hipEvent_t)
- * events[5*j + 0..4], j = k mod n_sets, on its stream: before the seed pass,
- * after it, after the dilation, after the ray walk and after the resolve pass,
- * so that event pairs time each stage; a NULL entry is not recorded.  The
- * array is copied; the events must stay alive while set.  n_sets = 0 (events
- * may be NULL) turns recording off. */
+/* Measurement hook.  events holds n_sets sets of 10 hipEvent_t: per set the
+ * (start, stop) pairs of five stages in this order: seed pass, dilation, ray
+ * walk, resolve pass, shift.  With n_sets > 0, frame k (each following
+ * vg_integrate_frame / vg_integrate_points call) uses set j = k mod n_sets,
+ * and a vg_shift_grid call uses the set of the frame that follows it.  A
+ * stage's start event takes the start time of its first kernel dispatch and
+ * its stop event the end time of its last (the dispatches record them, so
+ * hipEventElapsedTime gives device execution time with no marker in
+ * between); a stage that launches nothing records both events as markers on
+ * the stream.  NULL entries are not recorded.  The array is copied; the
+ * events must stay alive while set.  n_sets = 0 (events may be NULL) turns
+ * recording off. */
 vg_status vg_set_profile_events(vg_grid *g, void *const *events, int32_t n_sets);
 
 /* Release the handle (host metadata only; caller buffers are untouched).

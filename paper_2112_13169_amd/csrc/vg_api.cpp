@@ -143,14 +143,25 @@ struct vg_grid {
     int32_t hz_vd = 0;
     double hz_fov = -1.0;
     std::vector<int32_t> hz_host;   // kept alive for the asynchronous upload
-    // measurement hook: kProfileEvents events per set, one set per frame in turn
-    std::vector<hipEvent_t> prof;
+    // measurement hook: sets of kStages (start, stop) pairs, one set per frame
+    std::vector<StageEvents> prof;
     uint64_t prof_next = 0;
 };
 
 namespace {
 
-constexpr int kProfileEvents = 5;
+// Stages timed by the measurement hook, in the order of a set's event pairs.
+enum { kStageSeed, kStageDilate, kStageRays, kStageResolve, kStageShift, kStages };
+
+// The event pairs of the frame in turn (the set a vg_shift_grid call uses is
+// that of the frame that follows it), or null when recording is off.
+const StageEvents *stage_events(const vg_grid *g)
+{
+    if (g->prof.empty())
+        return nullptr;
+    const size_t sets = g->prof.size() / kStages;
+    return &g->prof[kStages * (size_t)(g->prof_next % sets)];
+}
 
 vg_status hip_status(hipError_t e) { return e == hipSuccess ? VG_OK : VG_ERR_HIP; }
 
@@ -372,15 +383,9 @@ vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_float
         g->hz_fov = sensor->fov_y;
     }
 
-    hipEvent_t *ev = nullptr;
-    if (!g->prof.empty()) {
-        size_t sets = g->prof.size() / kProfileEvents;
-        ev = &g->prof[kProfileEvents * (size_t)(g->prof_next++ % sets)];
-    }
-    auto mark = [&](int k) {
-        if (ev && ev[k] && e == hipSuccess)
-            e = hipEventRecord(ev[k], st);
-    };
+    const StageEvents *ev = stage_events(g);
+    StageEvents none;
+    auto stage = [&](int k) -> const StageEvents & { return ev ? ev[k] : none; };
 
     Planes pl;
     std::memcpy(pl.n, g->n, sizeof pl.n);
@@ -445,19 +450,16 @@ vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_float
                            std::max(pl.lo[2] - 2 * pl.r, 0), std::min(pl.hi[2], g->n[2] - 1)};
     const RowBox rows = row_union(seed_rows, fan_rows(g, kind, fan, *T, o));
 
-    mark(0);
     if (e == hipSuccess)
-        e = launch_seeds(sp, st);
-    mark(1);
+        e = launch_seeds(sp, st, stage(kStageSeed));
     if (e == hipSuccess)
-        e = launch_dilate(pl, st);
-    mark(2);
+        e = launch_dilate(pl, st, stage(kStageDilate));
     if (e == hipSuccess)
-        e = launch_rays(rp, inside, st);
-    mark(3);
+        e = launch_rays(rp, inside, st, stage(kStageRays));
     if (e == hipSuccess)
-        e = launch_resolve(pl, g->loc, rows, st);
-    mark(4);
+        e = launch_resolve(pl, g->loc, rows, st, stage(kStageResolve));
+    if (ev)
+        ++g->prof_next;
     if (e != hipSuccess)
         return VG_ERR_HIP;
     g->epoch = epoch;
@@ -587,11 +589,17 @@ vg_status vg_shift_grid(vg_grid *g, int32_t dx, int32_t dy, int32_t dz, void *st
         if (s > (1 << 24) || s < -(1 << 24))
             return VG_ERR_ARG;
     }
-    if (dx == 0 && dy == 0 && dz == 0)
-        return VG_OK;
+    const StageEvents *ev = stage_events(g);
+    const StageEvents none;
+    const StageEvents &sev = ev ? ev[kStageShift] : none;
+    if (dx == 0 && dy == 0 && dz == 0) {
+        if (ev && !same_device(g))
+            return VG_ERR_STATE;
+        return hip_status(record_empty_stage(sev, static_cast<hipStream_t>(stream)));
+    }
     if (!same_device(g))
         return VG_ERR_STATE;
-    hipError_t e = launch_shift(g->loc, g->spare, g->n, d, static_cast<hipStream_t>(stream));
+    hipError_t e = launch_shift(g->loc, g->spare, g->n, d, static_cast<hipStream_t>(stream), sev);
     if (e != hipSuccess)
         return VG_ERR_HIP;
     uint8_t *t = g->loc;
@@ -653,9 +661,10 @@ vg_status vg_set_profile_events(vg_grid *g, void *const *events, int32_t n_sets)
 {
     if (!g || n_sets < 0 || (n_sets > 0 && !events))
         return VG_ERR_ARG;
-    std::vector<hipEvent_t> v;
-    for (int64_t i = 0; i < kProfileEvents * (int64_t)n_sets; ++i)
-        v.push_back(static_cast<hipEvent_t>(events[i]));
+    std::vector<StageEvents> v;
+    for (int64_t i = 0; i < kStages * (int64_t)n_sets; ++i)
+        v.push_back(StageEvents{static_cast<hipEvent_t>(events[2 * i]),
+                                static_cast<hipEvent_t>(events[2 * i + 1])});
     g->prof.swap(v);
     g->prof_next = 0;
     return VG_OK;

@@ -86,16 +86,28 @@ struct RayParams {
     uint32_t epoch;
 };
 
+// Optional timing of one stage: `start` takes the start time of the stage's
+// first kernel dispatch and `stop` the end time of its last (recorded by the
+// dispatches themselves, so no marker sits between the kernels).  A stage
+// that launches nothing records both as plain markers.  Null: not recorded.
+struct StageEvents {
+    hipEvent_t start = nullptr, stop = nullptr;
+};
+
 hipError_t launch_fill(void *dst, uint8_t value, size_t bytes, hipStream_t st);
-hipError_t launch_seeds(const SeedParams &p, hipStream_t st);
+hipError_t launch_seeds(const SeedParams &p, hipStream_t st, const StageEvents &ev = {});
 // Seeds -> occupied bit plane (dilation by vox_inf along x, then y and z).
-hipError_t launch_dilate(const Planes &pl, hipStream_t st);
+hipError_t launch_dilate(const Planes &pl, hipStream_t st, const StageEvents &ev = {});
 // The walk of every fan ray.  camera_inside: the camera voxel lies in the grid.
-hipError_t launch_rays(const RayParams &p, bool camera_inside, hipStream_t st);
+hipError_t launch_rays(const RayParams &p, bool camera_inside, hipStream_t st,
+                       const StageEvents &ev = {});
 // Traced stamps and occupied bits -> the local grid, over the given rows.
-hipError_t launch_resolve(const Planes &pl, uint8_t *loc, const RowBox &rows, hipStream_t st);
+hipError_t launch_resolve(const Planes &pl, uint8_t *loc, const RowBox &rows, hipStream_t st,
+                          const StageEvents &ev = {});
 hipError_t launch_shift(const uint8_t *src, uint8_t *dst, const int32_t n[3],
-                        const int32_t d[3], hipStream_t st);
+                        const int32_t d[3], hipStream_t st, const StageEvents &ev = {});
+// Records the events of a stage that launches no kernel.
+hipError_t record_empty_stage(const StageEvents &ev, hipStream_t st);
 // Linear (pitch gx) <-> device layout (pitch gxp) copies of a whole grid.
 hipError_t copy_grid(uint8_t *dst, int64_t dst_pitch, const uint8_t *src, int64_t src_pitch,
                      const int32_t n[3], hipMemcpyKind kind, hipStream_t st);

@@ -27,6 +27,8 @@
 #include "vg_internal.h"
 #include "vg_walk.h"
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 
 #pragma clang fp contract(off)
@@ -360,63 +362,81 @@ hipError_t launch_fill(void *dst, uint8_t value, size_t bytes, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_seeds(const SeedParams &p, hipStream_t st)
+hipError_t record_empty_stage(const StageEvents &ev, hipStream_t st)
+{
+    hipError_t e = hipSuccess;
+    if (ev.start)
+        e = hipEventRecord(ev.start, st);
+    if (e == hipSuccess && ev.stop)
+        e = hipEventRecord(ev.stop, st);
+    return e;
+}
+
+hipError_t launch_seeds(const SeedParams &p, hipStream_t st, const StageEvents &ev)
 {
     dim3 grid;
     if (p.kind == kPoints)
         grid = dim3(std::max<uint32_t>(blocks_for(p.W), 1u), 1);
     else
         grid = dim3((uint32_t)std::max((p.W + 63) / 64, 1), (uint32_t)std::max((p.H + 3) / 4, 1));
-    hipLaunchKernelGGL(k_seed, grid, dim3(kBlock), 0, st, p);
+    hipExtLaunchKernelGGL(k_seed, grid, dim3(kBlock), 0, st, ev.start, ev.stop, 0, p);
     return hipGetLastError();
 }
 
-hipError_t launch_dilate(const Planes &pl, hipStream_t st)
+hipError_t launch_dilate(const Planes &pl, hipStream_t st, const StageEvents &ev)
 {
     const bool any = pl.lo[0] <= pl.hi[0] && pl.lo[1] <= pl.hi[1] && pl.lo[2] <= pl.hi[2];
+    hipEvent_t start = ev.start;
     if (any) {
         int64_t n = (int64_t)pl.wx * (pl.hi[1] - pl.lo[1] + 1) * (pl.hi[2] - pl.lo[2] + 1);
-        hipLaunchKernelGGL(k_dilate_x, dim3(blocks_for(n)), dim3(kBlock), 0, st, pl);
+        hipExtLaunchKernelGGL(k_dilate_x, dim3(blocks_for(n)), dim3(kBlock), 0, st, start,
+                              (hipEvent_t) nullptr, 0, pl);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
+        start = nullptr;
     }
     int64_t n = (int64_t)pl.wx * pl.n[1] * pl.n[2];
-    hipLaunchKernelGGL(k_dilate_yz, dim3(blocks_for(n)), dim3(kBlock), 0, st, pl);
+    hipExtLaunchKernelGGL(k_dilate_yz, dim3(blocks_for(n)), dim3(kBlock), 0, st, start, ev.stop,
+                          0, pl);
     return hipGetLastError();
 }
 
-hipError_t launch_rays(const RayParams &p, bool camera_inside, hipStream_t st)
+hipError_t launch_rays(const RayParams &p, bool camera_inside, hipStream_t st,
+                       const StageEvents &ev)
 {
     const int waves = kBlock / 64;
     uint32_t blocks = (uint32_t)((p.tiles + waves - 1) / waves);
     if (blocks == 0)
-        return hipSuccess;
+        return record_empty_stage(ev, st);
     if (camera_inside)
-        hipLaunchKernelGGL(k_rays<false>, dim3(blocks), dim3(kBlock), 0, st, p);
+        hipExtLaunchKernelGGL(k_rays<false>, dim3(blocks), dim3(kBlock), 0, st, ev.start, ev.stop,
+                              0, p);
     else
-        hipLaunchKernelGGL(k_rays<true>, dim3(blocks), dim3(kBlock), 0, st, p);
+        hipExtLaunchKernelGGL(k_rays<true>, dim3(blocks), dim3(kBlock), 0, st, ev.start, ev.stop,
+                              0, p);
     return hipGetLastError();
 }
 
-hipError_t launch_resolve(const Planes &pl, uint8_t *loc, const RowBox &rows, hipStream_t st)
+hipError_t launch_resolve(const Planes &pl, uint8_t *loc, const RowBox &rows, hipStream_t st,
+                          const StageEvents &ev)
 {
     if (rows.y0 > rows.y1 || rows.z0 > rows.z1)
-        return hipSuccess;
+        return record_empty_stage(ev, st);
     const int32_t ny = rows.y1 - rows.y0 + 1, nz = rows.z1 - rows.z0 + 1;
     int64_t n = (int64_t)pl.wx * 2 * ny * nz;
-    hipLaunchKernelGGL(k_resolve, dim3(blocks_for(n)), dim3(kBlock), 0, st, pl, loc, rows.y0,
-                       ny, rows.z0, nz);
+    hipExtLaunchKernelGGL(k_resolve, dim3(blocks_for(n)), dim3(kBlock), 0, st, ev.start, ev.stop,
+                          0, pl, loc, rows.y0, ny, rows.z0, nz);
     return hipGetLastError();
 }
 
 hipError_t launch_shift(const uint8_t *src, uint8_t *dst, const int32_t n[3], const int32_t d[3],
-                        hipStream_t st)
+                        hipStream_t st, const StageEvents &ev)
 {
     const int32_t pitch = grid_pitch(n[0]);
     dim3 grid((uint32_t)((pitch / 16 + kBlock - 1) / kBlock), (uint32_t)n[1], (uint32_t)n[2]);
-    hipLaunchKernelGGL(k_shift, grid, dim3(kBlock), 0, st, src, dst, n[0], n[1], n[2], pitch,
-                       d[0], d[1], d[2]);
+    hipExtLaunchKernelGGL(k_shift, grid, dim3(kBlock), 0, st, ev.start, ev.stop, 0, src, dst,
+                          n[0], n[1], n[2], pitch, d[0], d[1], d[2]);
     return hipGetLastError();
 }
 

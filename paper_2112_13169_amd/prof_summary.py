@@ -1,0 +1,149 @@
+"""Turn rocprofv3 output of the benchmark into the short summaries kept with
+the library: a per-kernel table (launches, durations, counter bytes) in
+Markdown, and the measured bytes per launch beyond the L2 that the benchmark
+reports beside its roofline.
+
+Inputs are three rocprofv3 runs of the same benchmark command:
+  --kernel-trace --stats --output-format csv      (durations)
+  --pmc FETCH_SIZE --output-format csv            (KiB read per dispatch)
+  --pmc WRITE_SIZE --output-format csv            (KiB written per dispatch)
+The benchmark ends with an untimed device copy of a known size; its counter
+readings give the factor that turns each counter into bytes (on gfx950
+FETCH_SIZE reads half the bytes a streaming copy moves; WRITE_SIZE reads them
+all).  Counter bytes are what the L2 exchanged with the memory side (HBM, or
+the last-level cache in front of it).
+
+    python -m paper_2112_13169_amd.prof_summary --kt DIR --fetch DIR --write DIR \\
+        --workload plain-medium --cal-bytes 67108864 --command "..." \\
+        --md profiles/NAME.md --json profiles/traffic.json
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ["csrc/vg_kernels.hip", "csrc/vg_walk.h", "csrc/vg_internal.h"]
+
+
+def kernel_source_hash():
+    """Hash of the kernel sources: counter readings taken on other sources are
+    stale."""
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def short_name(name):
+    name = name.replace("vg::(anonymous namespace)::", "")
+    if name.startswith("void "):
+        name = name[5:]
+    return name.split("(")[0]
+
+
+def _one(pattern):
+    hits = sorted(glob.glob(pattern))
+    if not hits:
+        raise SystemExit(f"no file matches {pattern}")
+    return hits[0]
+
+
+def read_stats(kt_dir):
+    out = {}
+    with open(_one(os.path.join(kt_dir, "*kernel_stats.csv"))) as fh:
+        for r in csv.DictReader(fh):
+            out[short_name(r["Name"])] = dict(calls=int(r["Calls"]), avg_ns=float(r["AverageNs"]),
+                                              min_ns=float(r["MinNs"]), max_ns=float(r["MaxNs"]),
+                                              pct=float(r["Percentage"]))
+    return out
+
+
+def read_counter(pmc_dir, counter):
+    """Per-kernel list of (grid size, KiB) of each dispatch, in dispatch order."""
+    rows = []
+    with open(_one(os.path.join(pmc_dir, "*counter_collection.csv"))) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] == counter:
+                rows.append((int(r["Dispatch_Id"]), short_name(r["Kernel_Name"]),
+                             int(r["Grid_Size"]), float(r["Counter_Value"])))
+    rows.sort()
+    per = collections.defaultdict(list)
+    for _, k, grid, kib in rows:
+        per[k].append((grid, kib))
+    return per, rows
+
+
+def calibration(rows, cal_bytes):
+    """Counter KiB of the last copy kernel dispatch (the calibration copy)."""
+    copies = [r for r in rows if "copyBuffer" in r[1] and "Rect" not in r[1]]
+    if not copies:
+        raise SystemExit("no calibration copy in the counter run")
+    kib = copies[-1][3]
+    return (cal_bytes / 1024.0) / kib, kib
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--kt", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--workload", required=True)
+    ap.add_argument("--cal-bytes", type=int, required=True)
+    ap.add_argument("--command", required=True, help="the profiled command, for the record")
+    ap.add_argument("--md", required=True)
+    ap.add_argument("--json", required=True)
+    a = ap.parse_args(argv)
+
+    stats = read_stats(a.kt)
+    fetch, frows = read_counter(a.fetch, "FETCH_SIZE")
+    write, wrows = read_counter(a.write, "WRITE_SIZE")
+    f_fac, f_cal = calibration(frows, a.cal_bytes)
+    w_fac, w_cal = calibration(wrows, a.cal_bytes)
+
+    kernels = {}
+    lines = [f"# Kernel durations and memory-side bytes: {a.workload}", "",
+             "Commands (one MI355X; REPO is the repository root):", "", "```"]
+    lines += a.command.strip().splitlines()
+    lines += ["```", "",
+              f"Calibration: a {a.cal_bytes} B device copy read FETCH_SIZE {f_cal:.1f} KiB and "
+              f"WRITE_SIZE {w_cal:.1f} KiB, so bytes = FETCH_SIZE x {f_fac:.4f} KiB + "
+              f"WRITE_SIZE x {w_fac:.4f} KiB.", "",
+              f"Kernel sources hash: `{kernel_source_hash()}`", "",
+              "| kernel | launches | avg us | min us | max us | % time | FETCH KiB | WRITE KiB "
+              "| bytes/launch (calibrated) |",
+              "|---|---|---|---|---|---|---|---|---|"]
+    for k, s in sorted(stats.items(), key=lambda kv: -kv[1]["pct"]):
+        fk = [v for _, v in fetch.get(k, [])]
+        wk = [v for _, v in write.get(k, [])]
+        fr = sum(fk) / len(fk) if fk else None
+        wr = sum(wk) / len(wk) if wk else None
+        nbytes = None
+        if fr is not None and wr is not None:
+            nbytes = 1024.0 * (fr * f_fac + wr * w_fac)
+            if k.startswith("k_"):
+                kernels[k] = dict(hbm_bytes_per_launch=round(nbytes), fetch_kib=round(fr, 1),
+                                  write_kib=round(wr, 1), avg_us=round(s["avg_ns"] / 1e3, 3))
+        lines.append(f"| `{k}` | {s['calls']} | {s['avg_ns'] / 1e3:.2f} | {s['min_ns'] / 1e3:.2f} | "
+                     f"{s['max_ns'] / 1e3:.2f} | {s['pct']:.1f} | "
+                     f"{'-' if fr is None else f'{fr:.1f}'} | {'-' if wr is None else f'{wr:.1f}'} | "
+                     f"{'-' if nbytes is None else f'{nbytes / 1e6:.3f} MB'} |")
+    lines.append("")
+    with open(a.md, "w") as fh:
+        fh.write("\n".join(lines))
+    with open(a.json, "w") as fh:
+        json.dump(dict(workload=a.workload, source_hash=kernel_source_hash(),
+                       fetch_factor=round(f_fac, 4), write_factor=round(w_fac, 4),
+                       kernels=kernels), fh, indent=1)
+        fh.write("\n")
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    main()

@@ -191,19 +191,35 @@ def _box_corners(lo, hi):
 
 def _screen_rect(corners, R, t, intr):
     """Pixel rectangle (u0, u1, v0, v1), end-exclusive, that holds the image of
-    a convex body with the given world corners; None when it is behind the
-    camera; the whole image when it straddles the image plane."""
+    a box with the given 8 world corners (ordered as _box_corners makes them);
+    None when nothing of it lies in front of the camera inside the image, or
+    when it lies wholly deeper than depth_max (its hits could only be invalid
+    depths, and it cannot hide a valid one).  A box that straddles the camera
+    plane is clipped to z >= eps first."""
     W, H = intr["width"], intr["height"]
+    eps = 1e-6
     pc = (corners - t) @ np.asarray(R)
     z = pc[:, 2]
-    if np.all(z <= 1e-9):
+    if np.all(z <= eps) or np.all(z > intr["depth_max"]):
         return None
-    if np.any(z <= 1e-9):
-        return 0, W, 0, H
-    u = intr["fx"] * pc[:, 0] / z + intr["cx"]
-    v = intr["fy"] * pc[:, 1] / z + intr["cy"]
-    u0, u1 = max(int(math.floor(u.min())) - 1, 0), min(int(math.ceil(u.max())) + 2, W)
-    v0, v1 = max(int(math.floor(v.min())) - 1, 0), min(int(math.ceil(v.max())) + 2, H)
+    pts = [pc[z > eps]]
+    if np.any(z <= eps):
+        cut = []
+        for i in range(8):
+            for bit in (1, 2, 4):
+                j = i | bit
+                if j != i and (z[i] > eps) != (z[j] > eps):
+                    a = (eps - z[i]) / (z[j] - z[i])
+                    cut.append(pc[i] + a * (pc[j] - pc[i]))
+        pts.append(np.array(cut))
+    p = np.concatenate(pts)
+    zz = np.maximum(p[:, 2], eps)
+    u = intr["fx"] * p[:, 0] / zz + intr["cx"]
+    v = intr["fy"] * p[:, 1] / zz + intr["cy"]
+    lo_u, hi_u = np.clip([u.min(), u.max()], -4.0 * W, 5.0 * W)
+    lo_v, hi_v = np.clip([v.min(), v.max()], -4.0 * H, 5.0 * H)
+    u0, u1 = max(int(math.floor(lo_u)) - 1, 0), min(int(math.ceil(hi_u)) + 2, W)
+    v0, v1 = max(int(math.floor(lo_v)) - 1, 0), min(int(math.ceil(hi_v)) + 2, H)
     if u0 >= u1 or v0 >= v1:
         return None
     return u0, u1, v0, v1
@@ -241,14 +257,61 @@ def render_pinhole(scene, R, t, intr, noise_k=0.0, rng=None):
     return z.astype(np.float32)
 
 
+def _angular_window(c, rad, R, t, el, n_cols):
+    """Rows and columns of a spinning image whose rays can meet a body inside
+    the sphere (c, rad): (None, None) when every ray may, else a row slice and
+    a column index array (wrapping at 360 deg).  Conservative by one pixel."""
+    d = np.asarray(R).T @ (np.asarray(c, float) - t)
+    dist = float(np.linalg.norm(d))
+    if dist <= rad * 1.001 + 1e-9:
+        return None, None
+    alpha = math.asin(min(1.0, rad / dist))
+    theta = math.asin(max(-1.0, min(1.0, d[2] / dist)))
+    d_el = abs(el[0] - el[-1]) / max(len(el) - 1, 1)
+    keep = np.nonzero((el >= theta - alpha - d_el) & (el <= theta + alpha + d_el))[0]
+    if keep.size == 0:
+        return slice(0, 0), np.zeros(0, np.int64)
+    rows = slice(int(keep[0]), int(keep[-1]) + 1)
+    if abs(theta) + alpha >= 0.5 * math.pi - 1e-6:
+        return rows, np.arange(n_cols)
+    beta = math.asin(min(1.0, math.sin(alpha) / math.cos(abs(theta))))
+    step = 2.0 * math.pi / n_cols
+    phi = math.atan2(d[1], d[0])
+    j0 = int(math.floor((phi - beta) / step)) - 1
+    j1 = int(math.ceil((phi + beta) / step)) + 1
+    if j1 - j0 + 1 >= n_cols:
+        return rows, np.arange(n_cols)
+    return rows, np.arange(j0, j1 + 1) % n_cols
+
+
 def render_spinning(scene, R, t, col_tab, row_tab, depth_min, depth_max, noise_k=0.0, rng=None):
-    """Range image of a spinning sensor (sensor frame z up)."""
+    """Range image of a spinning sensor (sensor frame z up).  Each primitive is
+    intersected only with the rays of its angular window; primitives wholly
+    beyond depth_max are skipped (they could only produce invalid ranges)."""
     ca, sa = col_tab[0::2].astype(float), col_tab[1::2].astype(float)
     ce, se = row_tab[0::2].astype(float), row_tab[1::2].astype(float)
     cam = np.stack([ce[:, None] * ca[None, :], ce[:, None] * sa[None, :],
                     np.broadcast_to(se[:, None], (se.size, ca.size))], axis=-1)
-    dirs = cam @ np.asarray(R).T
-    rho = _cast(scene, np.asarray(t, float), dirs)
+    R = np.asarray(R, float)
+    t = np.asarray(t, float)
+    dirs = cam @ R.T
+    el = np.arctan2(se, ce)
+    rho = _cast(Scene(scene.ground), t, dirs)
+    bodies = [(0.5 * (lo + hi), 0.5 * float(np.linalg.norm(hi - lo)),
+               Scene(False, np.array([[lo, hi]]))) for lo, hi in scene.boxes]
+    bodies += [(sp[:3], float(sp[3]), Scene(False, np.zeros((0, 2, 3)), sp[None, :]))
+               for sp in scene.spheres]
+    for c, rad, body in bodies:
+        if np.linalg.norm(np.asarray(c) - t) - rad > depth_max:
+            continue
+        rows, cols = _angular_window(c, rad, R, t, el, ca.size)
+        if rows is None:
+            rho = np.minimum(rho, _cast(body, t, dirs))
+            continue
+        if cols.size == 0:
+            continue
+        sub = _cast(body, t, dirs[rows][:, cols])
+        rho[rows, cols] = np.minimum(rho[rows][:, cols], sub)
     if noise_k > 0.0:
         with np.errstate(invalid="ignore"):
             rho = rho + rng.standard_normal(rho.shape) * (noise_k * rho * rho)
@@ -378,3 +441,100 @@ def smooth_trajectory(rng, n, speed=2.0, rate=30.0, extent=(40.0, 40.0), z=(1.0,
             p[2] = min(max(p[2], z[0]), z[1])
             vz = -vz
     return np.array(out_p), np.array(out_yaw)
+
+
+def yaw_rotation(yaw):
+    """Sensor-to-world rotation of a level spinning sensor (z up) whose
+    azimuth 0 points along heading `yaw`."""
+    c, s = math.cos(yaw), math.sin(yaw)
+    return np.array([[c, -s, 0.0], [s, c, 0.0], [0.0, 0.0, 1.0]])
+
+
+# Sequences of frames flown through one seeded world along smooth random
+# walks (2 m/s, 30 Hz).  "served": 640x480 pinhole frames with the medium
+# frame's noise and holes in a 40 x 40 x 10 m world of 800 boxes + 200
+# spheres, grid 200x200x100 at 0.05 m, vox_inf 2.  "large-pinhole" /
+# "large-spinning": a 30 x 30 x 8 m world of 1500 boxes + 500 spheres seen by
+# a 1280x720 pinhole camera or a 128 x 2048 spinning range sensor (vertical
+# fov 45 deg), 0.3-12 m, grid 400x400x200 at 0.025 m, vox_inf 3.
+SEQUENCES = {
+    "served": dict(extent=(40.0, 40.0), height=(0.0, 10.0), boxes=800, spheres=200,
+                   sensor="pinhole", W=640, H=480, fov=(90.0, 60.0), rng=(0.3, 8.0),
+                   noise=0.005, drop=0.05, dims=(200, 200, 100), vox=0.05, inf=2),
+    "large-pinhole": dict(extent=(30.0, 30.0), height=(0.0, 8.0), boxes=1500, spheres=500,
+                          sensor="pinhole", W=1280, H=720, fov=(90.0, 60.0), rng=(0.3, 12.0),
+                          noise=0.005, drop=0.05, dims=(400, 400, 200), vox=0.025, inf=3),
+    "large-spinning": dict(extent=(30.0, 30.0), height=(0.0, 8.0), boxes=1500, spheres=500,
+                           sensor="spinning", W=2048, H=128, vfov=45.0, rng=(0.3, 12.0),
+                           noise=0.005, drop=0.0, dims=(400, 400, 200), vox=0.025, inf=3),
+}
+
+
+@dataclass
+class Trajectory:
+    """One robot's path through a seeded world, and how its frames are taken."""
+    name: str
+    spec: dict
+    scene: Scene
+    positions: np.ndarray        # [n, 3]
+    yaws: np.ndarray             # [n]
+    seed: int
+
+
+def make_trajectory(name, robot=0, n_frames=300, seed=None):
+    """A world (shared by every robot of a sequence) and robot `robot`'s walk
+    through it; primitives are kept 0.5 m clear of that walk."""
+    spec = SEQUENCES[name]
+    if seed is None:
+        seed = SEED_BASE + 5000 + 100 * list(SEQUENCES).index(name)
+    walk_rng = np.random.default_rng([seed, robot])
+    pos, yaw = smooth_trajectory(walk_rng, n_frames, extent=spec["extent"])
+    scene = world_scene(np.random.default_rng([seed, 1 << 20]), spec["extent"], spec["boxes"],
+                        spec["spheres"], height=spec["height"], avoid=pos, keep_out=0.5)
+    return Trajectory(name, spec, scene, pos, yaw, seed)
+
+
+def trajectory_frame(traj, i, robot=0):
+    """Frame `i` of a trajectory: the rendered image, the pose and the grid
+    centred on the camera."""
+    spec = traj.spec
+    rng = np.random.default_rng([traj.seed, robot, i + 1])
+    pos = traj.positions[i]
+    dims = spec["dims"]
+    vs = float(np.float32(spec["vox"]))
+    if spec["sensor"] == "pinhole":
+        intr = pinhole_intrinsics(spec["W"], spec["H"], *spec["fov"], *spec["rng"])
+        R = level_camera(traj.yaws[i])
+        depth = render_pinhole(traj.scene, R, pos, intr, spec["noise"], rng)
+        if spec["drop"] > 0:
+            depth = drop_blocks(depth, rng, spec["drop"])
+        return Frame(depth=depth, R=R.astype(np.float32), t=pos.astype(np.float32), intr=intr,
+                     dims=dims, vox_size=vs, vox_inf=spec["inf"],
+                     origin=centred_origin(pos, dims, vs))
+    col, row = spinning_tables(spec["W"], spec["H"], spec["vfov"])
+    R = yaw_rotation(traj.yaws[i])
+    img = render_spinning(traj.scene, R, pos, col, row, *spec["rng"], spec["noise"], rng)
+    intr = dict(width=spec["W"], height=spec["H"], vfov=math.radians(spec["vfov"]),
+                depth_min=spec["rng"][0], depth_max=spec["rng"][1])
+    return Frame(depth=img, R=R.astype(np.float32), t=pos.astype(np.float32), intr=intr,
+                 dims=dims, vox_size=vs, vox_inf=spec["inf"],
+                 origin=centred_origin(pos, dims, vs), kind="spinning", col_tab=col, row_tab=row)
+
+
+def batched_frame(rng, max_side=None):
+    """One frame of a batch of independent frames: resolution drawn from
+    {320x240, 640x480, 848x480, 1280x720}, range 0.3 m to U[4, 10] m, a
+    uniformly random 6-DoF pose, the medium frame's scene model, and its own
+    grid (gx = gy in 100..256, gz in 100..128, voxel U[0.05, 0.1] m, vox_inf
+    in {1, 2, 3}) centred on the camera.  `max_side` caps the grid sides (for
+    quick tests)."""
+    W, H = [(320, 240), (640, 480), (848, 480), (1280, 720)][int(rng.integers(0, 4))]
+    dmax = float(rng.uniform(4.0, 10.0))
+    gxy = int(rng.integers(100, 257))
+    gz = int(rng.integers(100, 129))
+    if max_side is not None:
+        gxy, gz = min(gxy, max_side), min(gz, max_side)
+    vox = float(rng.uniform(0.05, 0.1))
+    r = int(rng.integers(1, 4))
+    return random_pose_frame(rng, W, H, (90.0, 60.0), (0.3, dmax), (gxy, gxy, gz), vox, r,
+                             200, 50)

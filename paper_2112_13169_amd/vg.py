@@ -17,8 +17,8 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "vg.h")
 VG_OK, VG_ERR_ARG, VG_ERR_HIP, VG_ERR_BUDGET, VG_ERR_STATE = 0, -1, -2, -3, -4
 VG_UNKNOWN, VG_FREE, VG_OCCUPIED = 0, 1, 2
 VG_PINHOLE, VG_SPINNING = 0, 1
-PROFILE_EVENTS = 5   # events per frame of vg_set_profile_events
-PROFILE_STAGES = ("seed", "dilate", "rays", "resolve")
+PROFILE_EVENTS = 10  # events per set of vg_set_profile_events: (start, stop) per stage
+PROFILE_STAGES = ("seed", "dilate", "rays", "resolve", "shift")
 
 
 class VgError(RuntimeError):
@@ -209,7 +209,8 @@ def vg_write_grid(g, src, stream=None):
 
 def vg_set_profile_events(g, events):
     """events: list of torch.cuda.Event (enable_timing=True) or None (not
-    recorded), 5 per set; [] turns recording off.  Each event is recorded once
+    recorded), PROFILE_EVENTS per set: the (start, stop) pair of each stage of
+    PROFILE_STAGES in turn; [] turns recording off.  Each event is recorded once
     on the current device before its handle is passed on."""
     n = len(events)
     assert n % PROFILE_EVENTS == 0

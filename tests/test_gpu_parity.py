@@ -60,6 +60,15 @@ class GpuGrid:
         host = np.full((H, W + pitch_pad), np.nan, np.float32)
         host[:, :W] = fr.depth
         dev = torch.from_numpy(host).cuda()[:, :W]
+        if fr.kind == "spinning":
+            tabs = (torch.from_numpy(fr.col_tab).cuda(), torch.from_numpy(fr.row_tab).cuda())
+            sensor = vg.spinning_sensor(W, H, *tabs, fr.intr["vfov"], fr.intr["depth_min"],
+                                        fr.intr["depth_max"])
+            vg.vg_integrate_frame(self.h, dev, sensor, vg.make_pose(fr.R, fr.t))
+            return oracle.integrate_spinning(
+                self.ref, self.origin(), self.vox_size, self.vox_inf, fr.depth, fr.col_tab,
+                fr.row_tab, fr.intr["vfov"], fr.intr["depth_min"], fr.intr["depth_max"],
+                np.asarray(fr.R, np.float32).reshape(-1), np.asarray(fr.t, np.float32))
         vg.vg_integrate_frame(self.h, dev, vg.pinhole_sensor(fr.intr), vg.make_pose(fr.R, fr.t))
         ms, st = oracle.integrate_pinhole(self.ref, self.origin(), self.vox_size, self.vox_inf,
                                           fr.depth, fr.intr, fr.R, fr.t)
@@ -104,6 +113,50 @@ def test_plain_medium_full_size():
     g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf)
     g.integrate(fr)
     g.check("plain-medium 0")
+    g.close()
+
+
+def test_large_pinhole_full_size():
+    """1280x720 at 0.3-12 m into 400x400x200 at 0.025 m with vox_inf 3 (32 M
+    voxels, 533 355 rays), full grid compared."""
+    fr = scenes.make_frame("large-pinhole", 0)
+    _say("large-pinhole frame 0")
+    g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf)
+    _, st = g.integrate(fr)
+    assert st["rays"] == _fan_rays(fr) == 533355
+    g.check("large-pinhole 0")
+    g.close()
+
+
+@pytest.mark.parametrize("name,frames", [("large-pinhole", (0, 1, 2)),
+                                         ("large-spinning", (0, 1))])
+def test_large_sequences_with_shifts(name, frames):
+    """Consecutive frames of a 2 m/s trajectory through a 2000-primitive world,
+    the 400x400x200 grid re-centred on the sensor before each frame."""
+    traj = scenes.make_trajectory(name, n_frames=max(frames) + 1)
+    first = scenes.trajectory_frame(traj, frames[0])
+    g = GpuGrid(first.dims, first.vox_size, first.origin, first.vox_inf)
+    for i in frames:
+        fr = first if i == frames[0] else scenes.trajectory_frame(traj, i)
+        d = oracle.center_offset(fr.dims, fr.vox_size, g.origin(), fr.t)
+        assert d == vg.vg_center_offset(g.h, fr.t)
+        _say(f"{name} frame {i} shift {d}")
+        g.shift(d)
+        g.integrate(fr)
+        g.check(f"{name} frame {i}")
+    g.close()
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_batched_recipe_frames(seed):
+    """Independent frames as a batch draws them: resolution up to 1280x720,
+    range to U[4, 10] m, random 6-DoF pose, own grid of up to 256x256x128 at
+    0.05-0.1 m, vox_inf 1-3."""
+    fr = scenes.batched_frame(np.random.default_rng([scenes.SEED_BASE + 2, seed]))
+    _say(f"batched-recipe seed {seed}: {fr.depth.shape} dims {fr.dims} r {fr.vox_inf}")
+    g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf)
+    g.integrate(fr)
+    g.check(f"batched-recipe {seed}")
     g.close()
 
 
@@ -296,3 +349,26 @@ def test_determinism_and_budget():
         vg.vg_create_grid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf, buf.loc[:-32],
                           buf.spare, buf.scratch)
     assert ei.value.status == vg.VG_ERR_BUDGET
+
+
+def test_profile_events_time_stages_without_changing_results():
+    """The measurement hook: every stage's (start, stop) pair completes with a
+    non-negative duration, the shift uses the set of the frame after it, a
+    zero shift records markers, and the grid is the same as without events."""
+    fr = scenes.make_frame("plain-small", 17)
+    g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf)
+    events = [torch.cuda.Event(enable_timing=True) for _ in range(2 * vg.PROFILE_EVENTS)]
+    vg.vg_set_profile_events(g.h, events)
+    _say("profile events")
+    for k, d in enumerate([(2, -1, 0), (0, 0, 0)]):
+        g.shift(d)
+        g.integrate(fr)
+        g.check(f"profiled frame {k}")
+    torch.cuda.synchronize()
+    vg.vg_set_profile_events(g.h, [])
+    E = vg.PROFILE_EVENTS
+    for k in range(2):
+        for j, name in enumerate(vg.PROFILE_STAGES):
+            ms = events[E * k + 2 * j].elapsed_time(events[E * k + 2 * j + 1])
+            assert 0.0 <= ms < 1000.0, (k, name, ms)
+    g.close()
