@@ -128,8 +128,8 @@ vg_status vg_create_grid(int32_t grid_size_x, int32_t grid_size_y, int32_t grid_
  * clipped to the grid) become VG_OCCUPIED; voxels the ray fan crosses before
  * its first occupied voxel become VG_FREE unless some ray crosses them after
  * a hit, in which case they become VG_UNKNOWN; every other voxel keeps its
- * value.  Returns VG_ERR_BUDGET if the fan needs more rays than the scratch
- * workspace was sized for. */
+ * value.  Returns VG_ERR_ARG if the ray fan is too large (more than 2^31
+ * ray lanes). */
 vg_status vg_integrate_frame(vg_grid *g, const float *depth, int64_t row_pitch_bytes,
                              const vg_sensor *sensor, const vg_pose *T_w_c, void *stream);
 
@@ -161,6 +161,49 @@ vg_status vg_read_grid(const vg_grid *g, uint8_t *dst, int32_t dst_is_device, vo
 
 /* Overwrite the local grid (restore a checkpoint) from src (linear layout). */
 vg_status vg_write_grid(vg_grid *g, const uint8_t *src, int32_t src_is_device, void *stream);
+
+/* One frame of a batch. */
+typedef struct vg_frame {
+    vg_grid *grid;            /* grid the frame is integrated into                 */
+    int32_t shift[3];         /* shift of `grid` applied right before the frame    */
+    int32_t is_points;        /* 0: image (sensor.kind), 1: point cloud            */
+    const float *data;        /* device: image rows, or float32[n_points][3]        */
+    int64_t row_pitch_bytes;  /* images: as for vg_integrate_frame                  */
+    int64_t n_points;         /* point clouds: as for vg_integrate_points           */
+    vg_sensor sensor;
+    vg_pose T_w_c;
+} vg_frame;
+
+/* Bytes of device workspace vg_integrate_batch needs for up to max_frames
+ * frames (at most 4096).  Host-only; 0 for invalid counts. */
+size_t vg_batch_workspace_bytes(int32_t max_frames);
+
+/* Steps 2-5 for a batch of frames, enqueued on `stream`.  The result equals,
+ * for i = 0 .. n_frames-1 in order, vg_shift_grid(frames[i].grid,
+ * frames[i].shift) followed by vg_integrate_frame (or vg_integrate_points)
+ * of frames[i] -- voxel for voxel.  Frames may target any mix of grids on the
+ * current device; frames of one grid are applied in their order.  Frames of
+ * distinct grids run together: frame i belongs to round k if k earlier
+ * frames target its grid, and each round is one launch per stage over all
+ * its frames, whatever their image sizes, sensors, poses and grid sizes.
+ *   workspace: device, 256-byte aligned, workspace_bytes >=
+ *     vg_batch_workspace_bytes(n_frames) (else VG_ERR_BUDGET).  The frame
+ *     tables are written into it through kernel arguments (no host staging
+ *     buffer, no host synchronisation), so a later call may reuse it on the
+ *     same stream at once.
+ * Every frame is checked before anything is enqueued (VG_ERR_ARG: no grid
+ * changes).  The call enqueues kernels only, so it can be captured into a
+ * HIP graph; a replay repeats the captured frames with their captured poses
+ * and stamps (the image buffers are read at replay time). */
+vg_status vg_integrate_batch(const vg_frame *frames, int32_t n_frames, void *workspace,
+                             size_t workspace_bytes, void *stream);
+
+/* Shape of the ray bundle one wavefront walks: tiles of (1 << log2_width)
+ * fan targets along the fan's width (pinhole columns, or ring columns of a
+ * spinning fan) by (64 >> log2_width) along its height; log2_width in
+ * [0, 6], default 3 (8 x 8).  Results do not depend on it (every ray is
+ * walked alone); speed does.  Host-only; applies to later frames of g. */
+vg_status vg_set_ray_tile(vg_grid *g, int32_t log2_width);
 
 /* Measurement hook.  events holds n_sets sets of 10 hipEvent_t: per set the
  * (start, stop) pairs of five stages in this order: seed pass, dilation, ray

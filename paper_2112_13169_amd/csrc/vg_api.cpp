@@ -6,6 +6,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -142,7 +144,7 @@ struct vg_grid {
     // spinning fan table currently in scratch
     int32_t hz_vd = 0;
     double hz_fov = -1.0;
-    std::vector<int32_t> hz_host;   // kept alive for the asynchronous upload
+    int32_t tile_log2w = 3;  // ray tiles of (1 << tile_log2w) x (64 >> tile_log2w) targets
     // measurement hook: sets of kStages (start, stop) pairs, one set per frame
     std::vector<StageEvents> prof;
     uint64_t prof_next = 0;
@@ -326,21 +328,71 @@ RowBox row_union(const RowBox &a, const RowBox &b)
                   std::max(a.z1, b.z1)};
 }
 
-// Common part of steps 2-4: per-frame constants, stamp, launches.
-vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_floats, int32_t W,
-                    int32_t H, const vg_sensor *sensor, const vg_pose *T, hipStream_t st)
+// Grid state a frame's plan depends on; a batch advances a copy of it frame
+// by frame and writes it back only when every frame has been planned.
+struct GridState {
+    int32_t shift[3];
+    uint32_t epoch;
+    int32_t hz_vd;
+    double hz_fov;
+    uint8_t *loc, *spare;
+};
+
+GridState state_of(const vg_grid *g)
 {
+    GridState s;
+    std::memcpy(s.shift, g->shift, sizeof s.shift);
+    s.epoch = g->epoch;
+    s.hz_vd = g->hz_vd;
+    s.hz_fov = g->hz_fov;
+    s.loc = g->loc;
+    s.spare = g->spare;
+    return s;
+}
+
+void store_state(vg_grid *g, const GridState &s)
+{
+    std::memcpy(g->shift, s.shift, sizeof s.shift);
+    g->epoch = s.epoch;
+    g->hz_vd = s.hz_vd;
+    g->hz_fov = s.hz_fov;
+    g->loc = s.loc;
+    g->spare = s.spare;
+}
+
+// Host plan of steps 2-4 for one frame: every per-frame constant and launch
+// size.  Nothing is launched and no state changes.
+struct FramePlan {
+    int kind;
     Fan fan;
-    if (!fan_for(*sensor, g->s, fan))
+    SeedParams sp;
+    RayParams rp;
+    RowBox rows;
+    bool inside;
+    bool wrap;        // the stamp planes must be cleared first (stamp wrapped)
+    bool upload_hz;   // the spinning fan table must be (re)written
+    uint32_t epoch;
+};
+
+vg_status plan_frame(const vg_grid *g, const GridState &gs, int kind, const float *data,
+                     int64_t pitch_floats, int32_t W, int32_t H, const vg_sensor *sensor,
+                     const vg_pose *T, FramePlan &p)
+{
+    p.kind = kind;
+    if (!fan_for(*sensor, g->s, p.fan))
         return VG_ERR_ARG;
     if ((W > 0 && H > 0) && !data)
         return VG_ERR_ARG;
+    const Fan &fan = p.fan;
 
     // T^v_c = T^v_w T^w_c: the grid frame is the world frame translated by
     // -origin (axes aligned), so R is unchanged and t^v = t^w_c - origin.
     float origin[3], tv[3], o[3];
     int32_t v0[3];
-    current_origin(g, origin);
+    for (int a = 0; a < 3; ++a) {
+        float off = (float)gs.shift[a] * g->s;
+        origin[a] = g->base[a] + off;
+    }
     for (int a = 0; a < 3; ++a) {
         tv[a] = T->t[a] - origin[a];
         o[a] = tv[a] / g->s;   // camera position in voxel units
@@ -348,44 +400,18 @@ vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_float
             return VG_ERR_ARG;
         v0[a] = (int32_t)std::floor(o[a]);
     }
-    // fan tiles of 8 x 8 targets, one wavefront each
+    // fan tiles of tw x th targets, one wavefront each
+    const int32_t tw = 1 << g->tile_log2w, th = 64 >> g->tile_log2w;
     const int32_t fan_a = kind == kSpinning ? 8 * fan.vd : 2 * fan.hw + 1;
     const int32_t fan_b = 2 * fan.hh + 1;
-    const int64_t tiles = (int64_t)((fan_a + 7) / 8) * ((fan_b + 7) / 8);
+    const int64_t tiles = (int64_t)((fan_a + tw - 1) / tw) * ((fan_b + th - 1) / th);
     if (tiles * 64 > (int64_t)0x7fffffff)
         return VG_ERR_ARG;
-    if (!same_device(g))
-        return VG_ERR_STATE;
 
     // Per-frame stamp 1..255; the stamp planes are cleared when it wraps.
-    hipError_t e = hipSuccess;
-    if (g->epoch == 255) {
-        e = launch_fill(g->scratch + g->lay.seed, 0, g->lay.bitx - g->lay.seed, st);
-        if (e == hipSuccess)
-            e = launch_fill(g->scratch + g->lay.traced, 0, g->lay.hz - g->lay.traced, st);
-        if (e != hipSuccess)
-            return VG_ERR_HIP;
-        g->epoch = 0;
-    }
-    const uint32_t epoch = g->epoch + 1;
-
-    if (kind == kSpinning && (g->hz_vd != fan.vd || g->hz_fov != sensor->fov_y)) {
-        g->hz_host = fan.hz;
-        e = hipMemcpyAsync(g->scratch + g->lay.hz, g->hz_host.data(),
-                           g->hz_host.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
-        // The table changes only with the sensor; wait so the host copy can
-        // be replaced safely next time.
-        if (e == hipSuccess)
-            e = hipStreamSynchronize(st);
-        if (e != hipSuccess)
-            return VG_ERR_HIP;
-        g->hz_vd = fan.vd;
-        g->hz_fov = sensor->fov_y;
-    }
-
-    const StageEvents *ev = stage_events(g);
-    StageEvents none;
-    auto stage = [&](int k) -> const StageEvents & { return ev ? ev[k] : none; };
+    p.wrap = gs.epoch == 255;
+    p.epoch = p.wrap ? 1 : gs.epoch + 1;
+    p.upload_hz = kind == kSpinning && (gs.hz_vd != fan.vd || gs.hz_fov != sensor->fov_y);
 
     Planes pl;
     std::memcpy(pl.n, g->n, sizeof pl.n);
@@ -399,9 +425,9 @@ vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_float
     pl.occ = reinterpret_cast<uint32_t *>(g->scratch + g->lay.occ);
     pl.traced = g->scratch + g->lay.traced;
     seed_box(g, kind, *sensor, *T, tv, pl.lo, pl.hi);
-    pl.epoch = epoch;
+    pl.epoch = p.epoch;
 
-    SeedParams sp;
+    SeedParams &sp = p.sp;
     sp.pl = pl;
     std::memcpy(sp.R, T->R, sizeof sp.R);
     std::memcpy(sp.tv, tv, sizeof sp.tv);
@@ -420,7 +446,7 @@ vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_float
     sp.col_tab = sensor->col_tab;
     sp.row_tab = sensor->row_tab;
 
-    RayParams rp;
+    RayParams &rp = p.rp;
     std::memcpy(rp.R, T->R, sizeof rp.R);
     std::memcpy(rp.wf.o, o, sizeof rp.wf.o);
     std::memcpy(rp.wf.v0, v0, sizeof rp.wf.v0);
@@ -432,15 +458,16 @@ vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_float
     rp.hh = fan.hh;
     rp.na = fan_a;
     rp.nb = fan_b;
-    rp.tiles_a = (fan_a + 7) / 8;
+    rp.tile_log2w = g->tile_log2w;
+    rp.tiles_a = (fan_a + tw - 1) / tw;
     rp.tiles = (int32_t)tiles;
     rp.hz = reinterpret_cast<const int32_t *>(g->scratch + g->lay.hz);
-    rp.loc = g->loc;
+    rp.loc = gs.loc;
     rp.occ = pl.occ;
     rp.traced = pl.traced;
-    rp.epoch = epoch;
-    const bool inside = v0[0] >= 0 && v0[0] < g->n[0] && v0[1] >= 0 && v0[1] < g->n[1] &&
-                        v0[2] >= 0 && v0[2] < g->n[2];
+    rp.epoch = p.epoch;
+    p.inside = v0[0] >= 0 && v0[0] < g->n[0] && v0[1] >= 0 && v0[1] < g->n[1] && v0[2] >= 0 &&
+               v0[2] < g->n[2];
 
     // rows holding occupied voxels (seed box minus padding, widened by the
     // inflation) or traced stamps (the fan's reach)
@@ -448,21 +475,108 @@ vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_float
     if (pl.lo[0] <= pl.hi[0])
         seed_rows = RowBox{std::max(pl.lo[1] - 2 * pl.r, 0), std::min(pl.hi[1], g->n[1] - 1),
                            std::max(pl.lo[2] - 2 * pl.r, 0), std::min(pl.hi[2], g->n[2] - 1)};
-    const RowBox rows = row_union(seed_rows, fan_rows(g, kind, fan, *T, o));
+    p.rows = row_union(seed_rows, fan_rows(g, kind, fan, *T, o));
+    return VG_OK;
+}
 
+// The grid state after a planned frame.
+void advance(GridState &gs, const FramePlan &p, const vg_sensor *sensor)
+{
+    gs.epoch = p.epoch;
+    if (p.upload_hz) {
+        gs.hz_vd = p.fan.vd;
+        gs.hz_fov = sensor->fov_y;
+    }
+}
+
+// Work done before a planned frame's stages: the stamp planes cleared on a
+// wrap, the spinning fan table written.
+hipError_t prepare_frame(const vg_grid *g, const FramePlan &p, hipStream_t st)
+{
+    hipError_t e = hipSuccess;
+    if (p.wrap) {
+        e = launch_fill(g->scratch + g->lay.seed, 0, g->lay.bitx - g->lay.seed, st);
+        if (e == hipSuccess)
+            e = launch_fill(g->scratch + g->lay.traced, 0, g->lay.hz - g->lay.traced, st);
+    }
+    if (e == hipSuccess && p.upload_hz)
+        e = launch_upload(reinterpret_cast<uint32_t *>(g->scratch + g->lay.hz),
+                          reinterpret_cast<const uint32_t *>(p.fan.hz.data()), p.fan.hz.size(),
+                          st);
+    return e;
+}
+
+// Batch frame tables: per round, kBatchStages block prefixes of m + 1
+// entries (16-byte aligned), then m frame descriptors.
+constexpr int32_t kMaxBatch = 4096;
+
+size_t batch_starts_bytes(int32_t m)
+{
+    return ((size_t)kBatchStages * (m + 1) * sizeof(int32_t) + 15) / 16 * 16;
+}
+
+size_t batch_table_bytes(int32_t m)
+{
+    return (batch_starts_bytes(m) + (size_t)m * sizeof(FrameDesc) + 15) / 16 * 16;
+}
+
+// Blocks of 256 lanes each batch stage launches for a planned frame.
+void batch_blocks(const vg_grid *g, const FramePlan &p, bool moved, int64_t blocks[kBatchStages])
+{
+    auto per = [](int64_t lanes) { return (lanes + 255) / 256; };
+    const Planes &pl = p.sp.pl;
+    const int64_t wx = pl.wx;
+    blocks[kBatchShift] = moved ? per((int64_t)(g->lay.gxp / 16) * g->n[1] * g->n[2]) : 0;
+    if (p.kind == kPoints)
+        blocks[kBatchSeed] = per(p.sp.W);
+    else
+        blocks[kBatchSeed] = (p.sp.W > 0 && p.sp.H > 0)
+                                 ? (int64_t)((p.sp.W + 63) / 64) * ((p.sp.H + 3) / 4)
+                                 : 0;
+    const bool any = pl.lo[0] <= pl.hi[0] && pl.lo[1] <= pl.hi[1] && pl.lo[2] <= pl.hi[2];
+    blocks[kBatchDilateX] =
+        any ? per(wx * (pl.hi[1] - pl.lo[1] + 1) * (int64_t)(pl.hi[2] - pl.lo[2] + 1)) : 0;
+    blocks[kBatchDilateYZ] = per(wx * g->n[1] * (int64_t)g->n[2]);
+    blocks[kBatchRays] = ((int64_t)p.rp.tiles + 3) / 4;
+    const RowBox &b = p.rows;
+    blocks[kBatchResolve] = (b.y0 <= b.y1 && b.z0 <= b.z1)
+                                ? per(2 * wx * (b.y1 - b.y0 + 1) * (int64_t)(b.z1 - b.z0 + 1))
+                                : 0;
+}
+
+// Steps 2-4 of one frame, one launch per stage.
+vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_floats, int32_t W,
+                    int32_t H, const vg_sensor *sensor, const vg_pose *T, hipStream_t st)
+{
+    GridState gs = state_of(g);
+    FramePlan p;
+    vg_status rc = plan_frame(g, gs, kind, data, pitch_floats, W, H, sensor, T, p);
+    if (rc != VG_OK)
+        return rc;
+    if (!same_device(g))
+        return VG_ERR_STATE;
+    hipError_t e = prepare_frame(g, p, st);
+    if (e == hipSuccess && p.wrap)
+        g->epoch = 0;   // planes cleared: no stale stamp can match
+    if (e != hipSuccess)
+        return VG_ERR_HIP;
+
+    const StageEvents *ev = stage_events(g);
+    StageEvents none;
+    auto stage = [&](int k) -> const StageEvents & { return ev ? ev[k] : none; };
+    e = launch_seeds(p.sp, st, stage(kStageSeed));
     if (e == hipSuccess)
-        e = launch_seeds(sp, st, stage(kStageSeed));
+        e = launch_dilate(p.sp.pl, st, stage(kStageDilate));
     if (e == hipSuccess)
-        e = launch_dilate(pl, st, stage(kStageDilate));
+        e = launch_rays(p.rp, p.inside, st, stage(kStageRays));
     if (e == hipSuccess)
-        e = launch_rays(rp, inside, st, stage(kStageRays));
-    if (e == hipSuccess)
-        e = launch_resolve(pl, g->loc, rows, st, stage(kStageResolve));
+        e = launch_resolve(p.sp.pl, g->loc, p.rows, st, stage(kStageResolve));
     if (ev)
         ++g->prof_next;
     if (e != hipSuccess)
         return VG_ERR_HIP;
-    g->epoch = epoch;
+    advance(gs, p, sensor);
+    store_state(g, gs);
     return VG_OK;
 }
 
@@ -667,6 +781,177 @@ vg_status vg_set_profile_events(vg_grid *g, void *const *events, int32_t n_sets)
                                 static_cast<hipEvent_t>(events[2 * i + 1])});
     g->prof.swap(v);
     g->prof_next = 0;
+    return VG_OK;
+}
+
+vg_status vg_set_ray_tile(vg_grid *g, int32_t log2_width)
+{
+    if (!g || log2_width < 0 || log2_width > 6)
+        return VG_ERR_ARG;
+    g->tile_log2w = log2_width;
+    return VG_OK;
+}
+
+size_t vg_batch_workspace_bytes(int32_t max_frames)
+{
+    if (max_frames < 0 || max_frames > kMaxBatch)
+        return 0;
+    // a round of m frames needs at most m times a one-frame round
+    return align_up((size_t)max_frames * batch_table_bytes(1) + kAlign);
+}
+
+vg_status vg_integrate_batch(const vg_frame *frames, int32_t n_frames, void *workspace,
+                             size_t workspace_bytes, void *stream)
+{
+    if (n_frames < 0 || n_frames > kMaxBatch || (n_frames > 0 && !frames))
+        return VG_ERR_ARG;
+    if (n_frames == 0)
+        return VG_OK;
+    if (!workspace || ((uintptr_t)workspace % kAlign) != 0)
+        return VG_ERR_ARG;
+    if (workspace_bytes < vg_batch_workspace_bytes(n_frames))
+        return VG_ERR_BUDGET;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+
+    // Plan every frame against the state its grid will have by then.
+    std::vector<vg_grid *> grids;
+    std::vector<GridState> states;
+    std::vector<int32_t> grid_rounds;
+    std::vector<FramePlan> plans((size_t)n_frames);
+    std::vector<int32_t> grid_of((size_t)n_frames), round_of((size_t)n_frames);
+    std::vector<const uint8_t *> shift_src((size_t)n_frames);
+    for (int32_t i = 0; i < n_frames; ++i) {
+        const vg_frame &f = frames[i];
+        vg_grid *g = f.grid;
+        if (!g || !valid_sensor(&f.sensor) || !finite_pose(&f.T_w_c))
+            return VG_ERR_ARG;
+        int kind;
+        int32_t W, H;
+        int64_t pitch;
+        if (f.is_points) {
+            if (f.sensor.kind != VG_PINHOLE || f.n_points < 0 || f.n_points > 0x7fffffff)
+                return VG_ERR_ARG;
+            kind = kPoints;
+            W = (int32_t)f.n_points;
+            H = 1;
+            pitch = 0;
+        } else {
+            if (f.row_pitch_bytes % 4 != 0 || f.row_pitch_bytes < 4 * (int64_t)f.sensor.width)
+                return VG_ERR_ARG;
+            kind = f.sensor.kind == VG_SPINNING ? kSpinning : kPinhole;
+            W = f.sensor.width;
+            H = f.sensor.height;
+            pitch = f.row_pitch_bytes / 4;
+        }
+        size_t k = 0;
+        while (k < grids.size() && grids[k] != g)
+            ++k;
+        if (k == grids.size()) {
+            grids.push_back(g);
+            states.push_back(state_of(g));
+            grid_rounds.push_back(0);
+        }
+        GridState &gs = states[k];
+        bool moved = false;
+        for (int a = 0; a < 3; ++a) {
+            int64_t s = (int64_t)gs.shift[a] + f.shift[a];
+            if (s > (1 << 24) || s < -(1 << 24))
+                return VG_ERR_ARG;
+            moved = moved || f.shift[a] != 0;
+        }
+        shift_src[i] = nullptr;
+        if (moved) {
+            for (int a = 0; a < 3; ++a)
+                gs.shift[a] += f.shift[a];
+            shift_src[i] = gs.loc;
+            std::swap(gs.loc, gs.spare);
+        }
+        vg_status rc = plan_frame(g, gs, kind, f.data, pitch, W, H, &f.sensor, &f.T_w_c, plans[i]);
+        if (rc != VG_OK)
+            return rc;
+        advance(gs, plans[i], &f.sensor);
+        grid_of[i] = (int32_t)k;
+        round_of[i] = grid_rounds[k]++;
+    }
+    for (vg_grid *g : grids)
+        if (!same_device(g))
+            return VG_ERR_STATE;
+
+    // Frame tables, one per round, packed into the workspace.
+    int32_t rounds = 0;
+    for (int32_t r : grid_rounds)
+        rounds = std::max(rounds, r);
+    std::vector<std::vector<int32_t>> members((size_t)rounds);
+    for (int32_t i = 0; i < n_frames; ++i)
+        members[(size_t)round_of[i]].push_back(i);
+    std::vector<size_t> table_at((size_t)rounds);
+    size_t used = 0;
+    for (int32_t r = 0; r < rounds; ++r) {
+        table_at[(size_t)r] = used;
+        used += batch_table_bytes((int32_t)members[(size_t)r].size());
+    }
+    if (used > workspace_bytes)
+        return VG_ERR_BUDGET;
+    std::vector<uint32_t> host(used / 4, 0u);
+    std::vector<std::array<int32_t, kBatchStages>> totals((size_t)rounds);
+    for (int32_t r = 0; r < rounds; ++r) {
+        const std::vector<int32_t> &mem = members[(size_t)r];
+        const int32_t m = (int32_t)mem.size();
+        uint8_t *base = reinterpret_cast<uint8_t *>(host.data()) + table_at[(size_t)r];
+        int32_t *start = reinterpret_cast<int32_t *>(base);
+        FrameDesc *fd = reinterpret_cast<FrameDesc *>(base + batch_starts_bytes(m));
+        std::array<int64_t, kBatchStages> acc{};
+        for (int32_t j = 0; j < m; ++j) {
+            const int32_t i = mem[(size_t)j];
+            const FramePlan &p = plans[(size_t)i];
+            const vg_grid *g = grids[(size_t)grid_of[i]];
+            int64_t blocks[kBatchStages];
+            batch_blocks(g, p, shift_src[i] != nullptr, blocks);
+            FrameDesc d;
+            std::memset(&d, 0, sizeof d);
+            d.sp = p.sp;
+            d.rp = p.rp;
+            d.loc = p.rp.loc;
+            d.shift_src = shift_src[i];
+            d.rows = p.rows;
+            for (int a = 0; a < 3; ++a)
+                d.shift[a] = shift_src[i] ? frames[i].shift[a] : 0;
+            d.inside = p.inside ? 1 : 0;
+            d.seed_bx = p.kind == kPoints ? 0 : std::max((p.sp.W + 63) / 64, 1);
+            std::memcpy(&fd[j], &d, sizeof d);
+            for (int s = 0; s < kBatchStages; ++s) {
+                start[s * (m + 1) + j] = (int32_t)acc[s];
+                acc[s] += blocks[s];
+                if (acc[s] > 0x7fffffff)
+                    return VG_ERR_ARG;
+            }
+        }
+        for (int s = 0; s < kBatchStages; ++s) {
+            start[s * (m + 1) + m] = (int32_t)acc[s];
+            totals[(size_t)r][s] = (int32_t)acc[s];
+        }
+    }
+
+    // Upload the tables, then per round: per-frame preparation and one
+    // launch per stage.
+    uint8_t *ws = static_cast<uint8_t *>(workspace);
+    hipError_t e = launch_upload(reinterpret_cast<uint32_t *>(ws), host.data(), host.size(), st);
+    for (int32_t r = 0; r < rounds && e == hipSuccess; ++r) {
+        const std::vector<int32_t> &mem = members[(size_t)r];
+        const int32_t m = (int32_t)mem.size();
+        for (int32_t i : mem)
+            if (e == hipSuccess)
+                e = prepare_frame(grids[(size_t)grid_of[i]], plans[(size_t)i], st);
+        const int32_t *start = reinterpret_cast<const int32_t *>(ws + table_at[(size_t)r]);
+        const FrameDesc *fd =
+            reinterpret_cast<const FrameDesc *>(ws + table_at[(size_t)r] + batch_starts_bytes(m));
+        for (int s = 0; s < kBatchStages && e == hipSuccess; ++s)
+            e = launch_batch_stage(s, fd, start + s * (m + 1), m, totals[(size_t)r][s], st);
+    }
+    if (e != hipSuccess)
+        return VG_ERR_HIP;
+    for (size_t k = 0; k < grids.size(); ++k)
+        store_state(grids[k], states[k]);
     return VG_OK;
 }
 

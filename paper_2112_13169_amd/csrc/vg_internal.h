@@ -70,20 +70,47 @@ struct SeedParams {
     const float *row_tab; // spinning: cos/sin elevation per row
 };
 
-// Step 3: the bundled ray fan.  One wavefront owns an 8 x 8 tile of fan
-// targets (tile_a along a / column, tile_b along b / z).
+// Step 3: the bundled ray fan.  One wavefront owns a tile of 64 fan targets,
+// (1 << tile_log2w) along a (pinhole column / ring column) by
+// (64 >> tile_log2w) along b (pinhole row / height).
 struct RayParams {
     float R[9];
     WalkFrame wf;     // camera position / voxel, grid size and pitch
     int32_t kind;     // kPinhole (also points) or kSpinning
     int32_t vd, hw, hh;   // pinhole fan; spinning: hh = largest half height
     int32_t na, nb;       // fan extent along a and b
+    int32_t tile_log2w;   // 0..6
     int32_t tiles_a, tiles;
     const int32_t *hz;    // spinning: half height per column
     uint8_t *loc;
     const uint32_t *occ;
     uint8_t *traced;
     uint32_t epoch;
+};
+
+// One frame of a batch round, as the batch kernels read it from device memory.
+struct FrameDesc {
+    SeedParams sp;              // transform, image and the frame's planes
+    RayParams rp;               // the ray fan
+    uint8_t *loc;               // the grid's current buffer (after the frame's shift)
+    const uint8_t *shift_src;   // the buffer the shift reads (if the frame shifts)
+    RowBox rows;                // rows of the resolve pass
+    int32_t shift[3];           // grid shift applied before the frame
+    int32_t inside;             // the camera voxel lies in the grid
+    int32_t seed_bx;            // image seed blocks along x (points: 0)
+};
+
+// Batch stages, in launch order within a round.
+enum { kBatchShift, kBatchSeed, kBatchDilateX, kBatchDilateYZ, kBatchRays, kBatchResolve,
+       kBatchStages };
+
+// Bytes to copy into device memory, carried as a kernel argument (so that a
+// batch needs no host staging buffer that must outlive the call).
+constexpr int kUploadWords = 1016;
+struct UploadBlob {
+    uint32_t *dst;
+    uint32_t words;
+    uint32_t w[kUploadWords];
 };
 
 // Optional timing of one stage: `start` takes the start time of the stage's
@@ -108,6 +135,13 @@ hipError_t launch_shift(const uint8_t *src, uint8_t *dst, const int32_t n[3],
                         const int32_t d[3], hipStream_t st, const StageEvents &ev = {});
 // Records the events of a stage that launches no kernel.
 hipError_t record_empty_stage(const StageEvents &ev, hipStream_t st);
+
+// Batch: copy host words to device memory through kernel arguments.
+hipError_t launch_upload(uint32_t *dst, const uint32_t *src, size_t words, hipStream_t st);
+// Batch: one launch of stage `stage` (kBatch*) over the n frames of a round;
+// fd and start (n + 1 block prefixes) live in device memory; blocks = start[n].
+hipError_t launch_batch_stage(int stage, const FrameDesc *fd, const int32_t *start, int32_t n,
+                              int32_t blocks, hipStream_t st);
 // Linear (pitch gx) <-> device layout (pitch gxp) copies of a whole grid.
 hipError_t copy_grid(uint8_t *dst, int64_t dst_pitch, const uint8_t *src, int64_t src_pitch,
                      const int32_t n[3], hipMemcpyKind kind, hipStream_t st);

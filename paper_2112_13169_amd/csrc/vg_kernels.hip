@@ -9,8 +9,8 @@
 //   k_dilate_x    Alg. 1 lines 6-9, separably: seeds -> bits dilated by
 //   k_dilate_yz   vox_inf along x, then along y and z.  The union of the
 //                 (2 vox_inf + 1)^3 cubes is exactly this separable dilation.
-//   k_rays        Alg. 2: one wavefront per 8x8 tile of fan targets, one lane
-//                 per ray.  Before its first occupied voxel a ray marks voxels
+//   k_rays        Alg. 2: one wavefront per tile of 64 fan targets (8 x 8 by
+//                 default), one lane per ray.  Before its first occupied voxel a ray marks voxels
 //                 free in the local grid; after it, it stamps them "unknown and
 //                 traced" in a separate plane.  Occupancy words are fetched for
 //                 8 walk steps at a time so that the loads overlap.
@@ -134,13 +134,18 @@ __global__ __launch_bounds__(kBlock) void k_fill(uint8_t *dst, uint8_t value, si
     }
 }
 
-// Alg. 1 lines 2-5.  Images: block = 64 x 4 pixels, one wavefront per image
-// row segment (coalesced row reads).  Points: 256 points per block.
-__global__ __launch_bounds__(kBlock) void k_seed(SeedParams p)
+// ------------------------------------------------------------ stage bodies
+// Each stage is a device function of (parameters, work index); the one-frame
+// kernels take their parameters as kernel arguments, the batch kernels read
+// them from a frame table in device memory.
+
+// Alg. 1 lines 2-5.  Images: block = 64 x 4 pixels (bx, by), one wavefront
+// per image row segment (coalesced row reads).  Points: 256 points per block.
+__device__ __forceinline__ void seed_body(const SeedParams &p, int32_t bx, int32_t by)
 {
     float pc[3];
     if (p.kind == kPoints) {
-        int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+        int64_t i = (int64_t)bx * kBlock + threadIdx.x;
         if (i >= p.W)
             return;
         const float *q = p.img + 3 * i;
@@ -151,8 +156,8 @@ __global__ __launch_bounds__(kBlock) void k_seed(SeedParams p)
         pc[1] = y;
         pc[2] = z;
     } else {
-        int32_t u = blockIdx.x * 64 + (threadIdx.x & 63);
-        int32_t v = blockIdx.y * 4 + (threadIdx.x >> 6);
+        int32_t u = bx * 64 + (threadIdx.x & 63);
+        int32_t v = by * 4 + (threadIdx.x >> 6);
         if (u >= p.W || v >= p.H)
             return;
         float d = p.img[(int64_t)v * p.pitch + u];
@@ -192,12 +197,11 @@ __global__ __launch_bounds__(kBlock) void k_seed(SeedParams p)
 // Seeds -> bits dilated along x.  One lane per 32-voxel word of a padded row
 // inside the seed box; output voxel x is set iff a seed lies at padded
 // x .. x + 2r of the same padded row.
-__global__ __launch_bounds__(kBlock) void k_dilate_x(Planes pl)
+__device__ __forceinline__ void dilate_x_body(const Planes &pl, int64_t gid)
 {
-    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int32_t ny = pl.hi[1] - pl.lo[1] + 1;
     const int32_t nz = pl.hi[2] - pl.lo[2] + 1;
-    if (gid >= (int64_t)pl.wx * ny * nz)
+    if (pl.lo[0] > pl.hi[0] || ny <= 0 || nz <= 0 || gid >= (int64_t)pl.wx * ny * nz)
         return;
     const int32_t w = (int32_t)(gid % pl.wx);
     const int64_t row = gid / pl.wx;
@@ -230,9 +234,8 @@ __global__ __launch_bounds__(kBlock) void k_dilate_x(Planes pl)
 
 // x-dilated rows -> occupied bit plane: OR over the (2r+1) x (2r+1) padded
 // rows y .. y+2r, z .. z+2r.  Every word of the plane is written.
-__global__ __launch_bounds__(kBlock) void k_dilate_yz(Planes pl)
+__device__ __forceinline__ void dilate_yz_body(const Planes &pl, int64_t gid)
 {
-    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (gid >= (int64_t)pl.wx * pl.n[1] * pl.n[2])
         return;
     const int32_t w = (int32_t)(gid % pl.wx);
@@ -242,22 +245,25 @@ __global__ __launch_bounds__(kBlock) void k_dilate_yz(Planes pl)
     const int32_t y0 = max(y, pl.lo[1]), y1 = min(y + 2 * pl.r, pl.hi[1]);
     const int32_t z0 = max(z, pl.lo[2]), z1 = min(z + 2 * pl.r, pl.hi[2]);
     uint32_t out = 0;
-    for (int32_t zz = z0; zz <= z1; ++zz) {
-        const uint32_t *src = pl.bitx + (int64_t)pl.wx * ((int64_t)pl.py * zz) + w;
-        for (int32_t yy = y0; yy <= y1; ++yy)
-            out |= src[(int64_t)pl.wx * yy];
+    if (pl.lo[0] <= pl.hi[0]) {
+        for (int32_t zz = z0; zz <= z1; ++zz) {
+            const uint32_t *src = pl.bitx + (int64_t)pl.wx * ((int64_t)pl.py * zz) + w;
+            for (int32_t yy = y0; yy <= y1; ++yy)
+                out |= src[(int64_t)pl.wx * yy];
+        }
     }
     pl.occ[gid] = out;
 }
 
-// Alg. 2 for every ray of the fan.
+// Alg. 2 for the 64 rays of fan tile `tile` (one wavefront).
 template <bool kGeneral>
-__global__ __launch_bounds__(kBlock) void k_rays(RayParams p)
+__device__ __forceinline__ void rays_body(const RayParams &p, int32_t tile)
 {
     const int lane = threadIdx.x & 63;
-    const int32_t tile = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int32_t lw = p.tile_log2w;
     const int32_t ta = tile % p.tiles_a, tb = tile / p.tiles_a;
-    const int32_t ia = ta * 8 + (lane & 7), ib = tb * 8 + (lane >> 3);
+    const int32_t ia = (ta << lw) + (lane & ((1 << lw) - 1));
+    const int32_t ib = tb * (64 >> lw) + (lane >> lw);
     int32_t tx, ty, tz, m2;
     if (tile >= p.tiles || !fan_target(p, ia, ib, tx, ty, tz, m2))
         return;
@@ -272,19 +278,20 @@ __global__ __launch_bounds__(kBlock) void k_rays(RayParams p)
     walk_ray<kGeneral>(w, m2, p.occ, p.loc, p.traced, (uint8_t)p.epoch);
 }
 
-// Alg. 3 for the prioritised marks.  One lane per 16 voxels of a grid row:
-// occupied bit -> occupied; else traced stamp -> unknown; else unchanged.
-__global__ __launch_bounds__(kBlock) void k_resolve(Planes pl, uint8_t *loc, int32_t y0,
-                                                    int32_t ny, int32_t z0, int32_t nz)
+// Alg. 3 for the prioritised marks.  One lane per 16 voxels of a grid row of
+// the row box: occupied bit -> occupied; else traced stamp -> unknown; else
+// unchanged.
+__device__ __forceinline__ void resolve_body(const Planes &pl, uint8_t *loc, const RowBox &rows,
+                                             int64_t gid)
 {
+    const int32_t ny = rows.y1 - rows.y0 + 1, nz = rows.z1 - rows.z0 + 1;
     const int32_t chunks = pl.wx * 2;   // 16-voxel chunks per row
-    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (gid >= (int64_t)chunks * ny * nz)
+    if (ny <= 0 || nz <= 0 || gid >= (int64_t)chunks * ny * nz)
         return;
     const int32_t k = (int32_t)(gid % chunks);
     const int64_t row = gid / chunks;
-    const int32_t y = y0 + (int32_t)(row % ny);
-    const int32_t z = z0 + (int32_t)(row / ny);
+    const int32_t y = rows.y0 + (int32_t)(row % ny);
+    const int32_t z = rows.z0 + (int32_t)(row / ny);
     const int64_t base = 32 * (int64_t)pl.wx * (y + (int64_t)pl.n[1] * z) + 16 * k;
     const uint32_t occ16 = (pl.occ[base >> 5] >> (base & 16)) & 0xFFFFu;
     const uint4 tr = *reinterpret_cast<const uint4 *>(pl.traced + base);
@@ -306,24 +313,27 @@ __global__ __launch_bounds__(kBlock) void k_resolve(Planes pl, uint8_t *loc, int
 }
 
 // Sec. IV-E: dst[x,y,z] = src[x+dx, y+dy, z+dz] inside, else unknown.  One
-// lane per 16 voxels of a device-layout row (padding bytes become unknown).
-// Rows whose source row is outside the grid are cleared without loads; the
-// common case reads five aligned dwords and realigns them with v_alignbyte.
-__global__ __launch_bounds__(kBlock) void k_shift(const uint8_t *src, uint8_t *dst, int32_t nx,
-                                                  int32_t ny, int32_t nz, int32_t pitch,
-                                                  int32_t dx, int32_t dy, int32_t dz)
+// lane per 16 voxels of a device-layout row, consecutive lanes along the row
+// and then on to the next rows (padding bytes become unknown).  Rows whose
+// source row is outside the grid are cleared without loads; the common case
+// reads five aligned dwords and realigns them with v_alignbyte.
+__device__ __forceinline__ void shift_body(const uint8_t *src, uint8_t *dst, int32_t nx,
+                                           int32_t ny, int32_t nz, int32_t pitch, int32_t dx,
+                                           int32_t dy, int32_t dz, int32_t gid)
 {
-    const int32_t x0 = 16 * (int32_t)(blockIdx.x * kBlock + threadIdx.x);
-    const int32_t y = blockIdx.y, z = blockIdx.z;
-    if (x0 >= pitch)
+    const int32_t cpr = pitch >> 4;   // 16-voxel chunks per row
+    if (gid >= cpr * ny * nz)
         return;
+    const int32_t row = gid / cpr;
+    const int32_t x0 = 16 * (gid - row * cpr);
+    const int32_t y = row % ny, z = row / ny;
     const int64_t sy = (int64_t)y + dy, sz = (int64_t)z + dz;
     uint32_t out[4] = {0u, 0u, 0u, 0u};
     if (sy >= 0 && sy < ny && sz >= 0 && sz < nz) {
-        const uint8_t *row = src + pitch * (sy + (int64_t)ny * sz);
+        const uint8_t *srow = src + pitch * (sy + (int64_t)ny * sz);
         const int64_t s0 = (int64_t)x0 + dx;
         if (x0 + 16 <= nx && s0 >= 0 && s0 + 16 <= nx && (s0 & ~3ll) + 20 <= pitch) {
-            const uint32_t *w = reinterpret_cast<const uint32_t *>(row + (s0 & ~3ll));
+            const uint32_t *w = reinterpret_cast<const uint32_t *>(srow + (s0 & ~3ll));
             const uint32_t sh = (uint32_t)(s0 & 3);
             uint32_t v[5];
 #pragma unroll
@@ -337,12 +347,133 @@ __global__ __launch_bounds__(kBlock) void k_shift(const uint8_t *src, uint8_t *d
             for (int j = 0; j < 16; ++j) {
                 const int64_t x = (int64_t)x0 + j, sx = x + dx;
                 if (x < nx && sx >= 0 && sx < nx)
-                    out[j >> 2] |= (uint32_t)row[sx] << (8 * (j & 3));
+                    out[j >> 2] |= (uint32_t)srow[sx] << (8 * (j & 3));
             }
         }
     }
-    *reinterpret_cast<uint4 *>(dst + pitch * (y + (int64_t)ny * z) + x0) =
+    *reinterpret_cast<uint4 *>(dst + (int64_t)pitch * row + x0) =
         make_uint4(out[0], out[1], out[2], out[3]);
+}
+
+// ------------------------------------------------------- one-frame kernels
+
+__global__ __launch_bounds__(kBlock) void k_seed(SeedParams p)
+{
+    seed_body(p, blockIdx.x, blockIdx.y);
+}
+
+__global__ __launch_bounds__(kBlock) void k_dilate_x(Planes pl)
+{
+    dilate_x_body(pl, (int64_t)blockIdx.x * kBlock + threadIdx.x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_dilate_yz(Planes pl)
+{
+    dilate_yz_body(pl, (int64_t)blockIdx.x * kBlock + threadIdx.x);
+}
+
+template <bool kGeneral>
+__global__ __launch_bounds__(kBlock) void k_rays(RayParams p)
+{
+    rays_body<kGeneral>(p, blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6));
+}
+
+__global__ __launch_bounds__(kBlock) void k_resolve(Planes pl, uint8_t *loc, RowBox rows)
+{
+    resolve_body(pl, loc, rows, (int64_t)blockIdx.x * kBlock + threadIdx.x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_shift(const uint8_t *src, uint8_t *dst, int32_t nx,
+                                                  int32_t ny, int32_t nz, int32_t pitch,
+                                                  int32_t dx, int32_t dy, int32_t dz)
+{
+    shift_body(src, dst, nx, ny, nz, pitch, dx, dy, dz,
+               (int32_t)(blockIdx.x * kBlock + threadIdx.x));
+}
+
+// ----------------------------------------------------------- batch kernels
+// One launch per stage for every frame of a batch round.  start[0..n] is the
+// stage's block prefix over the round's frames; a block finds its frame by a
+// (wavefront-uniform) binary search and works on that frame's local block.
+
+__device__ __forceinline__ int32_t frame_of(const int32_t *__restrict__ start, int32_t n,
+                                            int32_t block, int32_t &local)
+{
+    int32_t lo = 0, hi = n - 1;   // start[lo] <= block < start[hi + 1]
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= block)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    lo = __builtin_amdgcn_readfirstlane(lo);
+    local = block - start[lo];
+    return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void k_upload(UploadBlob b)
+{
+    for (uint32_t i = threadIdx.x; i < b.words; i += kBlock)
+        b.dst[i] = b.w[i];
+}
+
+__global__ __launch_bounds__(kBlock) void kb_shift(const FrameDesc *__restrict__ fd,
+                                                   const int32_t *__restrict__ start, int32_t n)
+{
+    int32_t local;
+    const FrameDesc &f = fd[frame_of(start, n, blockIdx.x, local)];
+    const Planes &pl = f.sp.pl;
+    shift_body(f.shift_src, f.loc, pl.n[0], pl.n[1], pl.n[2], 32 * pl.wx, f.shift[0], f.shift[1],
+               f.shift[2], local * kBlock + (int32_t)threadIdx.x);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_seed(const FrameDesc *__restrict__ fd,
+                                                  const int32_t *__restrict__ start, int32_t n)
+{
+    int32_t local;
+    const FrameDesc &f = fd[frame_of(start, n, blockIdx.x, local)];
+    if (f.seed_bx > 0)
+        seed_body(f.sp, local % f.seed_bx, local / f.seed_bx);
+    else
+        seed_body(f.sp, local, 0);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_dilate_x(const FrameDesc *__restrict__ fd,
+                                                      const int32_t *__restrict__ start, int32_t n)
+{
+    int32_t local;
+    const FrameDesc &f = fd[frame_of(start, n, blockIdx.x, local)];
+    dilate_x_body(f.sp.pl, (int64_t)local * kBlock + threadIdx.x);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_dilate_yz(const FrameDesc *__restrict__ fd,
+                                                       const int32_t *__restrict__ start,
+                                                       int32_t n)
+{
+    int32_t local;
+    const FrameDesc &f = fd[frame_of(start, n, blockIdx.x, local)];
+    dilate_yz_body(f.sp.pl, (int64_t)local * kBlock + threadIdx.x);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_rays(const FrameDesc *__restrict__ fd,
+                                                  const int32_t *__restrict__ start, int32_t n)
+{
+    int32_t local;
+    const FrameDesc &f = fd[frame_of(start, n, blockIdx.x, local)];
+    const int32_t tile = local * (kBlock / 64) + (threadIdx.x >> 6);
+    if (f.inside)
+        rays_body<false>(f.rp, tile);
+    else
+        rays_body<true>(f.rp, tile);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_resolve(const FrameDesc *__restrict__ fd,
+                                                     const int32_t *__restrict__ start, int32_t n)
+{
+    int32_t local;
+    const FrameDesc &f = fd[frame_of(start, n, blockIdx.x, local)];
+    resolve_body(f.sp.pl, f.loc, f.rows, (int64_t)local * kBlock + threadIdx.x);
 }
 
 uint32_t blocks_for(int64_t threads) { return (uint32_t)((threads + kBlock - 1) / kBlock); }
@@ -426,7 +557,7 @@ hipError_t launch_resolve(const Planes &pl, uint8_t *loc, const RowBox &rows, hi
     const int32_t ny = rows.y1 - rows.y0 + 1, nz = rows.z1 - rows.z0 + 1;
     int64_t n = (int64_t)pl.wx * 2 * ny * nz;
     hipExtLaunchKernelGGL(k_resolve, dim3(blocks_for(n)), dim3(kBlock), 0, st, ev.start, ev.stop,
-                          0, pl, loc, rows.y0, ny, rows.z0, nz);
+                          0, pl, loc, rows);
     return hipGetLastError();
 }
 
@@ -434,9 +565,55 @@ hipError_t launch_shift(const uint8_t *src, uint8_t *dst, const int32_t n[3], co
                         hipStream_t st, const StageEvents &ev)
 {
     const int32_t pitch = grid_pitch(n[0]);
-    dim3 grid((uint32_t)((pitch / 16 + kBlock - 1) / kBlock), (uint32_t)n[1], (uint32_t)n[2]);
-    hipExtLaunchKernelGGL(k_shift, grid, dim3(kBlock), 0, st, ev.start, ev.stop, 0, src, dst,
-                          n[0], n[1], n[2], pitch, d[0], d[1], d[2]);
+    const int64_t lanes = (int64_t)(pitch / 16) * n[1] * n[2];
+    hipExtLaunchKernelGGL(k_shift, dim3(blocks_for(lanes)), dim3(kBlock), 0, st, ev.start, ev.stop,
+                          0, src, dst, n[0], n[1], n[2], pitch, d[0], d[1], d[2]);
+    return hipGetLastError();
+}
+
+hipError_t launch_upload(uint32_t *dst, const uint32_t *src, size_t words, hipStream_t st)
+{
+    UploadBlob b;
+    for (size_t at = 0; at < words; at += kUploadWords) {
+        b.dst = dst + at;
+        b.words = (uint32_t)std::min<size_t>(kUploadWords, words - at);
+        std::copy(src + at, src + at + b.words, b.w);
+        hipLaunchKernelGGL(k_upload, dim3(1), dim3(kBlock), 0, st, b);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_batch_stage(int stage, const FrameDesc *fd, const int32_t *start, int32_t n,
+                              int32_t blocks, hipStream_t st)
+{
+    if (blocks <= 0 || n <= 0)
+        return hipSuccess;
+    const dim3 g((uint32_t)blocks), b(kBlock);
+    switch (stage) {
+    case kBatchShift:
+        hipLaunchKernelGGL(kb_shift, g, b, 0, st, fd, start, n);
+        break;
+    case kBatchSeed:
+        hipLaunchKernelGGL(kb_seed, g, b, 0, st, fd, start, n);
+        break;
+    case kBatchDilateX:
+        hipLaunchKernelGGL(kb_dilate_x, g, b, 0, st, fd, start, n);
+        break;
+    case kBatchDilateYZ:
+        hipLaunchKernelGGL(kb_dilate_yz, g, b, 0, st, fd, start, n);
+        break;
+    case kBatchRays:
+        hipLaunchKernelGGL(kb_rays, g, b, 0, st, fd, start, n);
+        break;
+    case kBatchResolve:
+        hipLaunchKernelGGL(kb_resolve, g, b, 0, st, fd, start, n);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

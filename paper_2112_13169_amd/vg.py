@@ -42,6 +42,14 @@ class vg_sensor(ctypes.Structure):
     ]
 
 
+class vg_frame(ctypes.Structure):
+    _fields_ = [
+        ("grid", ctypes.c_void_p), ("shift", ctypes.c_int32 * 3), ("is_points", ctypes.c_int32),
+        ("data", ctypes.c_void_p), ("row_pitch_bytes", ctypes.c_int64),
+        ("n_points", ctypes.c_int64), ("sensor", vg_sensor), ("T_w_c", vg_pose),
+    ]
+
+
 _lib = None
 
 
@@ -72,12 +80,16 @@ def lib():
         L.vg_write_grid.argtypes = [P, P, i32, P]
         L.vg_destroy_grid.argtypes = [P]
         L.vg_set_profile_events.argtypes = [P, P, i32]
+        L.vg_batch_workspace_bytes.argtypes = [i32]
+        L.vg_batch_workspace_bytes.restype = ctypes.c_size_t
+        L.vg_integrate_batch.argtypes = [ctypes.POINTER(vg_frame), i32, P, ctypes.c_size_t, P]
+        L.vg_set_ray_tile.argtypes = [P, i32]
         L.vg_status_str.argtypes = [i32]
         L.vg_status_str.restype = ctypes.c_char_p
         for name in ("vg_fan_sizes", "vg_create_grid", "vg_integrate_frame",
                      "vg_integrate_points", "vg_shift_grid", "vg_center_offset",
                      "vg_grid_origin", "vg_read_grid", "vg_write_grid", "vg_destroy_grid",
-                     "vg_set_profile_events"):
+                     "vg_set_profile_events", "vg_integrate_batch", "vg_set_ray_tile"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -224,6 +236,55 @@ def vg_set_profile_events(g, events):
         arr[i] = e.cuda_event
     _check(lib().vg_set_profile_events(g, arr if n else None, n // PROFILE_EVENTS),
            "vg_set_profile_events")
+
+
+def frame_image(g, image, sensor, pose, shift=(0, 0, 0)):
+    """vg_frame of a depth / range image (float32 device tensor [height, width],
+    rows may be strided).  Keep `image` alive until the batch has run."""
+    assert image.dtype.itemsize == 4 and image.dim() == 2 and image.stride(1) == 1
+    f = vg_frame()
+    f.grid = g.value if isinstance(g, ctypes.c_void_p) else g
+    f.shift[:] = [int(v) for v in shift]
+    f.is_points = 0
+    f.data = image.data_ptr()
+    f.row_pitch_bytes = image.stride(0) * 4
+    f.n_points = 0
+    f.sensor = sensor
+    f.T_w_c = pose
+    return f
+
+
+def frame_points(g, points, sensor, pose, shift=(0, 0, 0)):
+    """vg_frame of a point cloud (float32 device tensor [n, 3])."""
+    assert points.dtype.itemsize == 4 and points.is_contiguous()
+    f = vg_frame()
+    f.grid = g.value if isinstance(g, ctypes.c_void_p) else g
+    f.shift[:] = [int(v) for v in shift]
+    f.is_points = 1
+    f.data = points.data_ptr()
+    f.row_pitch_bytes = 0
+    f.n_points = points.numel() // 3
+    f.sensor = sensor
+    f.T_w_c = pose
+    return f
+
+
+def vg_batch_workspace_bytes(max_frames):
+    return int(lib().vg_batch_workspace_bytes(int(max_frames)))
+
+
+def vg_integrate_batch(frames, workspace, stream=None):
+    """frames: list of vg_frame; workspace: uint8 device tensor of at least
+    vg_batch_workspace_bytes(len(frames)) elements (256-byte aligned)."""
+    n = len(frames)
+    arr = (vg_frame * max(n, 1))(*frames)
+    _check(lib().vg_integrate_batch(arr, n, _ptr(workspace),
+                                    workspace.numel() * workspace.element_size(),
+                                    _stream(stream)), "vg_integrate_batch")
+
+
+def vg_set_ray_tile(g, log2_width):
+    _check(lib().vg_set_ray_tile(g, int(log2_width)), "vg_set_ray_tile")
 
 
 def vg_destroy_grid(g):

@@ -1,0 +1,273 @@
+"""GPU parity of batched integration (vg_integrate_batch): a batch equals the
+frames applied one by one (shift, then integrate) -- checked against the CPU
+oracle voxel for voxel, and at full batch sizes against the one-frame path on
+the same GPU."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2112_13169_amd import scenes
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2112_13169_amd import vg
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+class Twin:
+    """A device grid and its oracle twin."""
+
+    def __init__(self, dims, vox_size, origin, vox_inf):
+        self.dims = tuple(dims)
+        self.buf = vg.GridBuffers(dims, vox_inf)
+        self.h = vg.vg_create_grid(dims, vox_size, origin, vox_inf, self.buf.loc, self.buf.spare,
+                                   self.buf.scratch)
+        self.s = np.float32(vox_size)
+        self.r = vox_inf
+        self.base = np.asarray(origin, np.float32)
+        self.shift_total = np.zeros(3, np.int32)
+        gx, gy, gz = dims
+        self.ref = np.zeros((gz, gy, gx), np.uint8)
+
+    def origin(self):
+        return oracle.origin(self.base, self.shift_total, self.s)
+
+    def read(self):
+        out = torch.empty(self.ref.size, dtype=torch.uint8, device="cuda")
+        vg.vg_read_grid(self.h, out)
+        torch.cuda.synchronize()
+        return out.cpu().numpy().reshape(self.ref.shape)
+
+    def oracle_frame(self, fr, shift=(0, 0, 0)):
+        self.ref = oracle.shift(self.ref, shift)
+        self.shift_total += np.asarray(shift, np.int32)
+        if fr.kind == "spinning":
+            oracle.integrate_spinning(self.ref, self.origin(), self.s, self.r, fr.depth, fr.col_tab,
+                                      fr.row_tab, fr.intr["vfov"], fr.intr["depth_min"],
+                                      fr.intr["depth_max"], np.asarray(fr.R, np.float32).reshape(-1),
+                                      np.asarray(fr.t, np.float32))
+        elif fr.kind == "points":
+            oracle.integrate_points(self.ref, self.origin(), self.s, self.r, fr.points,
+                                    fr.intr["fov_x"], fr.intr["fov_y"], fr.intr["depth_max"],
+                                    fr.R, fr.t)
+        else:
+            oracle.integrate_pinhole(self.ref, self.origin(), self.s, self.r, fr.depth, fr.intr,
+                                     fr.R, fr.t)
+
+    def check(self, what):
+        got = self.read()
+        if not np.array_equal(got, self.ref):
+            bad = np.argwhere(got != self.ref)
+            z, y, x = bad[0]
+            raise AssertionError(f"{what}: {len(bad)} voxels differ; first (x={x},y={y},z={z}) "
+                                 f"gpu={got[z, y, x]} oracle={self.ref[z, y, x]}")
+
+    def close(self):
+        vg.vg_destroy_grid(self.h)
+
+
+class DevFrame:
+    """Device copies of a frame's inputs and its vg_frame descriptor."""
+
+    def __init__(self, twin, fr, shift=(0, 0, 0)):
+        self.fr = fr
+        pose = vg.make_pose(fr.R, fr.t)
+        if fr.kind == "spinning":
+            self.tabs = (torch.from_numpy(fr.col_tab).cuda(), torch.from_numpy(fr.row_tab).cuda())
+            H, W = fr.depth.shape
+            sensor = vg.spinning_sensor(W, H, *self.tabs, fr.intr["vfov"], fr.intr["depth_min"],
+                                        fr.intr["depth_max"])
+            self.data = torch.from_numpy(fr.depth).cuda()
+            self.desc = vg.frame_image(twin.h, self.data, sensor, pose, shift)
+        elif fr.kind == "points":
+            self.data = torch.from_numpy(np.ascontiguousarray(fr.points, np.float32)).cuda()
+            self.desc = vg.frame_points(twin.h, self.data, vg.pinhole_sensor(fr.intr), pose, shift)
+        else:
+            self.data = torch.from_numpy(fr.depth).cuda()
+            self.desc = vg.frame_image(twin.h, self.data, vg.pinhole_sensor(fr.intr), pose, shift)
+
+
+def _points_frame(fr):
+    H, W = fr.depth.shape
+    ku = ((np.arange(W) - fr.intr["cx"]) / fr.intr["fx"]).astype(np.float32)
+    kv = ((np.arange(H) - fr.intr["cy"]) / fr.intr["fy"]).astype(np.float32)
+    pts = np.stack([fr.depth * ku[None, :], fr.depth * kv[:, None], fr.depth], -1).reshape(-1, 3)
+    fr.points = np.ascontiguousarray(pts[::3])
+    fr.kind = "points"
+    return fr
+
+
+def _spin_frame(seed, W=512, H=32, vfov=45.0, dims=(96, 96, 48), s=0.1, r=1):
+    rng = np.random.default_rng(seed)
+    col, row = scenes.spinning_tables(W, H, vfov)
+    pos = np.array([0.3, -0.2, 1.2])
+    R = scenes.random_rotation(rng)
+    scene = scenes.world_scene(rng, (12.0, 12.0), 60, 20, height=(0.0, 3.0), avoid=pos[None, :],
+                               keep_out=0.6)
+    img = scenes.render_spinning(scene, R, pos, col, row, 0.3, 4.0, 0.005, rng)
+    intr = dict(width=W, height=H, vfov=math.radians(vfov), depth_min=0.3, depth_max=4.0)
+    s = float(np.float32(s))
+    return scenes.Frame(depth=img, R=R.astype(np.float32), t=pos.astype(np.float32), intr=intr,
+                        dims=dims, vox_size=s, vox_inf=r, origin=scenes.centred_origin(pos, dims, s),
+                        kind="spinning", col_tab=col, row_tab=row)
+
+
+def _workspace(n):
+    return torch.empty(vg.vg_batch_workspace_bytes(n), dtype=torch.uint8, device="cuda")
+
+
+def test_mixed_batch_matches_oracle():
+    """Pinhole, spinning and point-cloud frames on grids of different sizes and
+    vox_inf; two grids get several frames (with shifts between them), so the
+    batch runs in rounds."""
+    frames = [scenes.make_frame("plain-small", 30 + i) for i in range(3)]
+    frames.append(_points_frame(scenes.make_frame("plain-small", 33)))
+    frames.append(_spin_frame(5))
+    twins = [Twin(f.dims, f.vox_size, f.origin, f.vox_inf) for f in frames]
+    # a second and third frame for grid 0, a second for the spinning grid
+    extra = [(0, scenes.make_frame("plain-small", 40), (2, -1, 0)),
+             (4, _spin_frame(6), (0, 0, 1)),
+             (0, scenes.make_frame("plain-small", 41), (-3, 0, 2))]
+    plan = [(k, f, (0, 0, 0)) for k, f in enumerate(frames)] + extra
+    for k, fr, _ in extra:   # the extra frames look from near their grid's camera
+        fr.t = (frames[k].t + np.float32([0.2, -0.1, 0.05])).astype(np.float32)
+    dev = [DevFrame(twins[k], fr, d) for k, fr, d in plan]
+    ws = _workspace(len(dev))
+    _say(f"mixed batch of {len(dev)} frames")
+    vg.vg_integrate_batch([d.desc for d in dev], ws)
+    for k, fr, d in plan:
+        twins[k].oracle_frame(fr, d)
+    for k, t in enumerate(twins):
+        t.check(f"grid {k}")
+        assert np.array_equal(t.shift_total, np.array(
+            [sum(d[a] for kk, _, d in plan if kk == k) for a in range(3)]))
+    for t in twins:
+        t.close()
+
+
+def test_sequence_batch_with_shifts_matches_oracle():
+    """Eight consecutive frames of one trajectory as one batch (order kept
+    across the re-centring shifts)."""
+    traj = scenes.make_trajectory("served", robot=2, n_frames=8)
+    frs = [scenes.trajectory_frame(traj, i, robot=2) for i in range(8)]
+    dims = (96, 96, 48)
+    for f in frs:
+        f.dims = dims
+    t = Twin(dims, frs[0].vox_size, scenes.centred_origin(frs[0].t, dims, frs[0].vox_size),
+             frs[0].vox_inf)
+    shifts, origin_shift = [], np.zeros(3, np.int32)
+    for f in frs:
+        org = oracle.origin(t.base, origin_shift, t.s)
+        d = oracle.center_offset(dims, t.s, org, f.t)
+        shifts.append(d)
+        origin_shift = origin_shift + np.asarray(d, np.int32)
+    dev = [DevFrame(t, f, d) for f, d in zip(frs, shifts)]
+    _say(f"sequence batch shifts {shifts}")
+    vg.vg_integrate_batch([d.desc for d in dev], _workspace(8))
+    for f, d in zip(frs, shifts):
+        t.oracle_frame(f, d)
+    t.check("sequence batch")
+    assert np.allclose(vg.vg_grid_origin(t.h), t.origin())
+    t.close()
+
+
+def test_full_size_batch_of_64_matches_one_frame_path():
+    """64 independent frames as the batch recipe draws them (up to 1280x720,
+    grids up to 256x256x128, vox_inf 1-3): every grid equals the one-frame
+    path's; three sampled frames are also checked against the oracle."""
+    rng = np.random.default_rng([scenes.SEED_BASE + 2, 64])
+    frs = [scenes.batched_frame(rng) for _ in range(64)]
+    a = [Twin(f.dims, f.vox_size, f.origin, f.vox_inf) for f in frs]
+    b = [Twin(f.dims, f.vox_size, f.origin, f.vox_inf) for f in frs]
+    dev = [DevFrame(t, f) for t, f in zip(a, frs)]
+    _say("batch of 64")
+    vg.vg_integrate_batch([d.desc for d in dev], _workspace(64))
+    for t, d in zip(b, dev):
+        vg.vg_integrate_frame(t.h, d.data, vg.pinhole_sensor(d.fr.intr),
+                              vg.make_pose(d.fr.R, d.fr.t))
+    torch.cuda.synchronize()
+    for k in range(64):
+        ga, gb = a[k].read(), b[k].read()
+        assert np.array_equal(ga, gb), f"frame {k}: batch differs from the one-frame path"
+    for k in (0, 17, 63):
+        a[k].oracle_frame(frs[k])
+        a[k].check(f"batch-64 frame {k}")
+    for t in a + b:
+        t.close()
+
+
+def test_graph_captured_batch_replays():
+    """The batch call captured into a HIP graph: every replay, with eager work
+    and synchronisation between replays, leaves the grids as the eager call."""
+    frs = [scenes.make_frame("plain-small", 50 + i) for i in range(4)]
+    eager = [Twin(f.dims, f.vox_size, f.origin, f.vox_inf) for f in frs]
+    graphed = [Twin(f.dims, f.vox_size, f.origin, f.vox_inf) for f in frs]
+    dev_e = [DevFrame(t, f, (1, 0, 0)) for t, f in zip(eager, frs)]
+    dev_g = [DevFrame(t, f, (1, 0, 0)) for t, f in zip(graphed, frs)]
+    ws_e, ws_g = _workspace(4), _workspace(4)
+    vg.vg_integrate_batch([d.desc for d in dev_e], ws_e)
+    torch.cuda.synchronize()
+    want = [t.read() for t in eager]
+    _say("graph capture")
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        vg.vg_integrate_batch([d.desc for d in dev_g], ws_g)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        graph.replay()
+        torch.cuda.synchronize()
+        junk = torch.randn(1 << 20, device="cuda").sum()   # eager work between replays
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        for k, t in enumerate(graphed):
+            assert np.array_equal(t.read(), want[k]), f"replay {rep} grid {k}"
+    for t in eager + graphed:
+        t.close()
+
+
+@pytest.mark.parametrize("log2w", range(7))
+def test_ray_tile_shapes_give_the_same_grid(log2w):
+    fr = scenes.make_frame("plain-small", 60)
+    t = Twin(fr.dims, fr.vox_size, fr.origin, fr.vox_inf)
+    vg.vg_set_ray_tile(t.h, log2w)
+    d = DevFrame(t, fr)
+    _say(f"ray tile 2^{log2w}")
+    vg.vg_integrate_frame(t.h, d.data, vg.pinhole_sensor(fr.intr), vg.make_pose(fr.R, fr.t))
+    t.oracle_frame(fr)
+    t.check(f"tile {log2w}")
+    t.close()
+
+
+def test_empty_seed_box_after_seeded_frame():
+    """A frame whose measurement range misses the grid (its seed box is empty)
+    after a frame that did seed it: no occupancy of the earlier frame may
+    survive into the later one."""
+    kw = dict(size=(80, 60), yaw=0.0, position=(0.0, 0.0, 1.0))   # looking along +x
+    fr = scenes.make_frame("plain-small", 61, **kw)
+    dims = (20, 20, 20)
+    s = fr.vox_size
+    fwd = fr.R[:, 2].astype(np.float64)
+    origin = (fr.t + 0.5 * fwd - np.array(dims) * s / 2).astype(np.float32)   # cube 0.5 m ahead
+    t = Twin(dims, s, origin, 1)
+    near = scenes.make_frame("plain-small", 61, **kw)
+    near.depth[:] = np.float32(1.0)                         # a wall 1 m ahead: inside the cube
+    far = scenes.make_frame("plain-small", 61, **kw)
+    far.intr = dict(far.intr, depth_min=3.5)               # only points beyond the cube count
+    _say("empty seed box")
+    for f in (near, far):
+        d = DevFrame(t, f)
+        vg.vg_integrate_frame(t.h, d.data, vg.pinhole_sensor(f.intr), vg.make_pose(f.R, f.t))
+        t.oracle_frame(f)
+        t.check(f"depth_min {f.intr['depth_min']}")
+    t.close()

@@ -115,3 +115,27 @@ def test_null_handle_calls_are_argument_errors():
     assert L.vg_destroy_grid(None) == vg.VG_ERR_ARG
     assert vg.vg_status_str(vg.VG_ERR_BUDGET) == "scratch workspace too small"
     assert vg.vg_status_str(12345) == "unknown status"
+
+
+def test_batch_argument_errors_before_any_device_work():
+    L = vg.lib()
+    P = ctypes.c_void_p
+    ws = P(0x400000)
+    need = vg.vg_batch_workspace_bytes(2)
+    assert need > 0 and vg.vg_batch_workspace_bytes(2) < vg.vg_batch_workspace_bytes(3)
+    assert vg.vg_batch_workspace_bytes(-1) == 0 and vg.vg_batch_workspace_bytes(4097) == 0
+    frames = (vg.vg_frame * 2)()
+    assert L.vg_integrate_batch(frames, 0, None, 0, None) == vg.VG_OK       # nothing to do
+    assert L.vg_integrate_batch(frames, -1, ws, need, None) == vg.VG_ERR_ARG
+    assert L.vg_integrate_batch(None, 2, ws, need, None) == vg.VG_ERR_ARG
+    assert L.vg_integrate_batch(frames, 2, None, need, None) == vg.VG_ERR_ARG
+    assert L.vg_integrate_batch(frames, 2, P(0x400010), need, None) == vg.VG_ERR_ARG
+    assert L.vg_integrate_batch(frames, 2, ws, need - 1, None) == vg.VG_ERR_BUDGET
+    # a frame without a grid is an argument error (checked before any launch)
+    assert L.vg_integrate_batch(frames, 2, ws, need, None) == vg.VG_ERR_ARG
+    assert ctypes.sizeof(vg.vg_frame) == 184
+
+
+def test_ray_tile_argument_range():
+    L = vg.lib()
+    assert L.vg_set_ray_tile(None, 3) == vg.VG_ERR_ARG
