@@ -102,6 +102,90 @@ def batch_recipe_frames(n, key=64, workers=8):
         return pool.map(_batch_frame, [(key, k) for k in range(n)])
 
 
+_FLEET = {}
+
+
+def _fleet_frame(arg):
+    from paper_2112_13169_amd import scenes
+    n_robots, n_frames, r, k = arg
+    key = (n_robots, n_frames)
+    if key not in _FLEET:
+        _FLEET[key] = scenes.make_fleet("served", range(n_robots), n_frames)
+    return scenes.trajectory_frame(_FLEET[key][r], k, robot=r)
+
+
+def served_frames(n_robots, n_frames, workers=8):
+    """frames[r][k]: robot r's k-th frame of the served fleet, rendered in
+    worker processes before the GPU is touched."""
+    import multiprocessing as mp
+    if n_robots <= 0 or n_frames <= 0:
+        return {}
+    args = [(n_robots, n_frames, r, k) for r in range(n_robots) for k in range(n_frames)]
+    with mp.get_context("fork").Pool(max(1, min(workers, os.cpu_count() or 1))) as pool:
+        flat = pool.map(_fleet_frame, args, chunksize=8)
+    return {r: flat[r * n_frames:(r + 1) * n_frames] for r in range(n_robots)}
+
+
+def run_served(frames, torch, vg, serve, rate_hz=30.0):
+    """Continuous-batching server over the fleet's frames: real-time Poisson
+    arrivals with room for every grid, the same with a budget of three
+    quarters of the grids (evictions), and every frame at once (capacity)."""
+    n_robots = len(frames)
+    n_frames = len(frames[0])
+    f0 = frames[0][0]
+    sensor = vg.pinhole_sensor(f0.intr)
+    backend = serve.GpuBackend(torch, vg, frames, sensor, streams=2, max_batch=64)
+    gbytes = backend.grid_bytes(f0.dims, f0.vox_inf)
+    fbytes = f0.depth.nbytes
+    fixed = 2 * backend.workspace_bytes(64)
+    out = {}
+    for name, grids, speed in [("realtime", n_robots, 1.0),
+                               ("realtime, tight budget", (3 * n_robots) // 4, 1.0),
+                               ("all at once", n_robots, float("inf"))]:
+        robots = [serve.Robot(r, f0.dims, f0.vox_size, frames[r][0].origin, f0.vox_inf)
+                  for r in range(n_robots)]
+        budget = fixed + grids * gbytes + 128 * fbytes
+        srv = serve.Server(backend, robots, fbytes, budget, max_batch=64, streams=2)
+        arrivals = serve.poisson_arrivals(n_robots, n_frames, rate_hz,
+                                          np.random.default_rng([2112131694, n_robots]))
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        done = srv.run(arrivals, speed=speed)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        entry = {"frames": len(done), "wall_s": round(wall, 4),
+                 "frames_per_s": round(len(done) / wall, 1),
+                 "latency": serve.latency_summary(done),
+                 "batches": srv.stats.batches,
+                 "mean_batch": round(float(np.mean(srv.stats.batch_sizes)), 2),
+                 "max_batch": int(max(srv.stats.batch_sizes)),
+                 "evictions": srv.stats.evictions, "restores": srv.stats.restores,
+                 "budget_MB": round(budget / 2 ** 20, 1),
+                 "peak_MB": round(srv.stats.peak_bytes / 2 ** 20, 1)}
+        if name == "realtime, tight budget":
+            # two robots' served grids against the same frames alone
+            same = True
+            for r in (0, n_robots - 1):
+                b = vg.GridBuffers(f0.dims, f0.vox_inf)
+                h = vg.vg_create_grid(f0.dims, f0.vox_size, frames[r][0].origin, f0.vox_inf,
+                                      b.loc, b.spare, b.scratch)
+                for f in frames[r]:
+                    vg.vg_shift_grid(h, *vg.vg_center_offset(h, f.t))
+                    vg.vg_integrate_frame(h, torch.from_numpy(f.depth).cuda(), sensor,
+                                          vg.make_pose(f.R, f.t))
+                alone = torch.empty(int(np.prod(f0.dims)), dtype=torch.uint8, device="cuda")
+                vg.vg_read_grid(h, alone)
+                torch.cuda.synchronize()
+                same = same and bool(np.array_equal(backend.read(srv.robots[r]),
+                                                    alone.cpu().numpy()))
+                vg.vg_destroy_grid(h)
+            entry["bit_exact_vs_alone"] = same
+        for rb in srv.robots.values():
+            vg.vg_destroy_grid(rb.handle)
+        out[name] = entry
+    return out
+
+
 def run_batched(frames, K, warmup, torch, vg, oracle, autotune, sample_oracle=()):
     """Batched vs plain on the same frames, each frame with its own grid: one
     vg_integrate_batch call per step against len(frames) vg_integrate_frame
@@ -209,6 +293,9 @@ def main():
     ap.add_argument("--batch", type=int, default=64,
                     help="frames per batch of the batch recipe (0 skips the batched runs)")
     ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--serve-robots", type=int, default=16,
+                    help="robots of the served runs (0 skips them)")
+    ap.add_argument("--serve-frames", type=int, default=60, help="frames per robot")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -224,8 +311,14 @@ def main():
         print(f"# generated {len(recipe)} batch-recipe frames in {time.time() - t0:.1f}s",
               file=sys.stderr, flush=True)
 
+    t0 = time.time()
+    fleet = served_frames(args.serve_robots, args.serve_frames)
+    if fleet:
+        print(f"# generated {args.serve_robots}x{args.serve_frames} served frames in "
+              f"{time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+
     import torch
-    from paper_2112_13169_amd import autotune, scenes, vg
+    from paper_2112_13169_amd import autotune, scenes, serve, vg
 
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU visible"}))
@@ -471,6 +564,15 @@ def main():
                               sample_oracle=(0, len(recipe) - 1))),
         }
         print(f"# batched runs in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    if fleet:
+        t0 = time.time()
+        out["served"] = dict(
+            workload=f"{args.serve_robots} robots x {args.serve_frames} frames (2 m/s walks at "
+                     "30 Hz through a 40x40x10 m world of 800 boxes + 200 spheres), 640x480 "
+                     "frames as the medium workload, each robot's 200x200x100 grid at 0.05 m "
+                     "re-centred every frame; Poisson arrivals at 30 Hz per robot",
+            **run_served(fleet, torch, vg, serve))
+        print(f"# served runs in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     print(json.dumps(out))
 
 

@@ -120,6 +120,17 @@ vg_status vg_create_grid(int32_t grid_size_x, int32_t grid_size_y, int32_t grid_
                          uint8_t *loc_grid, uint8_t *loc_spare, size_t grid_bytes,
                          void *scratch, size_t scratch_bytes, void *stream, vg_grid **out);
 
+/* Bind new device buffers to an existing grid (same sizes as for
+ * vg_create_grid), keeping its host state: sizes, vox_size, origin and the
+ * accumulated integer shift, vox_inf.  The new scratch is cleared here; the
+ * content of loc_grid is the caller's (restore it with vg_write_grid).  This
+ * lets a caller release a grid's device memory while it is idle (after
+ * vg_read_grid) and resume it later with results identical to never having
+ * released it.  All work on the old buffers must have been enqueued on
+ * `stream` or completed. */
+vg_status vg_rebind_grid(vg_grid *g, uint8_t *loc_grid, uint8_t *loc_spare, size_t grid_bytes,
+                         void *scratch, size_t scratch_bytes, void *stream);
+
 /* Steps 2-4 (Alg. 1, 2, 3) for one frame, enqueued on `stream`:
  *   depth: device, sensor->height rows of sensor->width float32, rows
  *     row_pitch_bytes apart (>= 4*width, multiple of 4).

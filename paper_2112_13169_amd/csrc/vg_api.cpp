@@ -671,6 +671,32 @@ vg_status vg_create_grid(int32_t gx, int32_t gy, int32_t gz, float vox_size,
     return VG_OK;
 }
 
+vg_status vg_rebind_grid(vg_grid *g, uint8_t *loc_grid, uint8_t *loc_spare, size_t grid_bytes,
+                         void *scratch, size_t scratch_bytes, void *stream)
+{
+    if (!g)
+        return VG_ERR_ARG;
+    if (!loc_grid || !loc_spare || loc_grid == loc_spare || !scratch ||
+        ((uintptr_t)scratch % kAlign) != 0 || ((uintptr_t)loc_grid % 16) != 0 ||
+        ((uintptr_t)loc_spare % 16) != 0)
+        return VG_ERR_ARG;
+    if (scratch_bytes < g->lay.fixed || grid_bytes < vg_grid_bytes(g->n[0], g->n[1], g->n[2]))
+        return VG_ERR_BUDGET;
+    if (!same_device(g))
+        return VG_ERR_STATE;
+    // fresh stamp planes: no stamp of an earlier frame is left to match
+    if (launch_fill(scratch, 0, g->lay.fixed, static_cast<hipStream_t>(stream)) != hipSuccess)
+        return VG_ERR_HIP;
+    g->loc = loc_grid;
+    g->spare = loc_spare;
+    g->scratch = static_cast<uint8_t *>(scratch);
+    g->scratch_bytes = scratch_bytes;
+    g->epoch = 0;
+    g->hz_vd = 0;
+    g->hz_fov = -1.0;
+    return VG_OK;
+}
+
 vg_status vg_integrate_frame(vg_grid *g, const float *depth, int64_t row_pitch_bytes,
                              const vg_sensor *sensor, const vg_pose *T_w_c, void *stream)
 {

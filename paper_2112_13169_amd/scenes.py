@@ -482,16 +482,25 @@ class Trajectory:
 
 
 def make_trajectory(name, robot=0, n_frames=300, seed=None):
-    """A world (shared by every robot of a sequence) and robot `robot`'s walk
-    through it; primitives are kept 0.5 m clear of that walk."""
+    """A world and robot `robot`'s walk through it; primitives are kept 0.5 m
+    clear of that walk."""
+    return make_fleet(name, [robot], n_frames, seed)[0]
+
+
+def make_fleet(name, robots, n_frames=300, seed=None):
+    """One world shared by several robots (primitives kept 0.5 m clear of
+    every walk) and each robot's walk through it."""
     spec = SEQUENCES[name]
     if seed is None:
         seed = SEED_BASE + 5000 + 100 * list(SEQUENCES).index(name)
-    walk_rng = np.random.default_rng([seed, robot])
-    pos, yaw = smooth_trajectory(walk_rng, n_frames, extent=spec["extent"])
+    walks = []
+    for robot in robots:
+        walk_rng = np.random.default_rng([seed, robot])
+        walks.append(smooth_trajectory(walk_rng, n_frames, extent=spec["extent"]))
+    avoid = np.concatenate([p for p, _ in walks])
     scene = world_scene(np.random.default_rng([seed, 1 << 20]), spec["extent"], spec["boxes"],
-                        spec["spheres"], height=spec["height"], avoid=pos, keep_out=0.5)
-    return Trajectory(name, spec, scene, pos, yaw, seed)
+                        spec["spheres"], height=spec["height"], avoid=avoid, keep_out=0.5)
+    return [Trajectory(name, spec, scene, p, y, seed) for p, y in walks]
 
 
 def trajectory_frame(traj, i, robot=0):

@@ -84,12 +84,14 @@ def lib():
         L.vg_batch_workspace_bytes.restype = ctypes.c_size_t
         L.vg_integrate_batch.argtypes = [ctypes.POINTER(vg_frame), i32, P, ctypes.c_size_t, P]
         L.vg_set_ray_tile.argtypes = [P, i32]
+        L.vg_rebind_grid.argtypes = [P, P, P, ctypes.c_size_t, P, ctypes.c_size_t, P]
         L.vg_status_str.argtypes = [i32]
         L.vg_status_str.restype = ctypes.c_char_p
         for name in ("vg_fan_sizes", "vg_create_grid", "vg_integrate_frame",
                      "vg_integrate_points", "vg_shift_grid", "vg_center_offset",
                      "vg_grid_origin", "vg_read_grid", "vg_write_grid", "vg_destroy_grid",
-                     "vg_set_profile_events", "vg_integrate_batch", "vg_set_ray_tile"):
+                     "vg_set_profile_events", "vg_integrate_batch", "vg_set_ray_tile",
+                     "vg_rebind_grid"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -176,6 +178,14 @@ def vg_create_grid(dims, vox_size, origin_w, vox_inf, loc, spare, scratch, strea
                                 nb, _ptr(scratch), scratch.numel() * scratch.element_size(),
                                 _stream(stream), ctypes.byref(h)), "vg_create_grid")
     return h
+
+
+def vg_rebind_grid(g, loc, spare, scratch, stream=None):
+    """Bind new device buffers (as for vg_create_grid) to an existing grid."""
+    nb = min(loc.numel(), spare.numel())
+    _check(lib().vg_rebind_grid(g, _ptr(loc), _ptr(spare), nb, _ptr(scratch),
+                                scratch.numel() * scratch.element_size(), _stream(stream)),
+           "vg_rebind_grid")
 
 
 def vg_integrate_frame(g, depth, sensor, pose, stream=None):
