@@ -112,7 +112,7 @@ size_t vg_scratch_bytes(int32_t grid_size_x, int32_t grid_size_y, int32_t grid_s
  *     aligned; it is cleared here and owned by the grid until destroyed.
  *   origin_w: world position (m) of the grid corner (voxel (0,0,0)'s minimum
  *     corner); vox_size > 0 m; vox_inf in [0, 16] voxels of inflation.
- *   Dimensions in [1, 65535] with vg_grid_bytes(...) < 2^31.
+ *   Dimensions in [1, 65535] with vg_grid_bytes(...) < 2^30.
  * Returns VG_ERR_BUDGET if grid_bytes or scratch_bytes is too small.
  * On success *out receives the handle. */
 vg_status vg_create_grid(int32_t grid_size_x, int32_t grid_size_y, int32_t grid_size_z,

@@ -29,11 +29,12 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 //   seed      seed stamps on the grid padded by vox_inf, rows of seed_pitch bytes
 //   bitx      seeds dilated along x, one 32-bit word per 32 voxels of a padded row
 //   occ       occupied voxels of the frame, one bit per device-layout voxel
-//   traced    "unknown and traced" stamps, one byte per device-layout voxel
+//   marks     free stamps, then "unknown and traced" stamps, one byte per
+//             device-layout voxel each
 //   hz        spinning fan: half height per ring column
 struct Layout {
     int32_t gxp, wx, py, pz, seed_pitch;
-    size_t seed, bitx, occ, traced, hz, fixed;
+    size_t seed, bitx, occ, marks, hz, fixed;
 };
 
 Layout layout_for(int32_t gx, int32_t gy, int32_t gz, int32_t r)
@@ -47,8 +48,8 @@ Layout layout_for(int32_t gx, int32_t gy, int32_t gz, int32_t r)
     l.seed = 0;
     l.bitx = l.seed + align_up((size_t)l.seed_pitch * l.py * l.pz);
     l.occ = l.bitx + align_up((size_t)4 * l.wx * l.py * l.pz);
-    l.traced = l.occ + align_up((size_t)4 * l.wx * gy * gz);
-    l.hz = l.traced + align_up((size_t)l.gxp * gy * gz);
+    l.marks = l.occ + align_up((size_t)4 * l.wx * gy * gz);
+    l.hz = l.marks + align_up((size_t)2 * l.gxp * gy * gz);
     l.fixed = l.hz + kHzBytes;
     return l;
 }
@@ -423,7 +424,8 @@ vg_status plan_frame(const vg_grid *g, const GridState &gs, int kind, const floa
     pl.seed = g->scratch + g->lay.seed;
     pl.bitx = reinterpret_cast<uint32_t *>(g->scratch + g->lay.bitx);
     pl.occ = reinterpret_cast<uint32_t *>(g->scratch + g->lay.occ);
-    pl.traced = g->scratch + g->lay.traced;
+    pl.marks = g->scratch + g->lay.marks;
+    pl.nbytes = (uint32_t)((size_t)g->lay.gxp * g->n[1] * g->n[2]);
     seed_box(g, kind, *sensor, *T, tv, pl.lo, pl.hi);
     pl.epoch = p.epoch;
 
@@ -462,9 +464,10 @@ vg_status plan_frame(const vg_grid *g, const GridState &gs, int kind, const floa
     rp.tiles_a = (fan_a + tw - 1) / tw;
     rp.tiles = (int32_t)tiles;
     rp.hz = reinterpret_cast<const int32_t *>(g->scratch + g->lay.hz);
-    rp.loc = gs.loc;
     rp.occ = pl.occ;
-    rp.traced = pl.traced;
+    rp.occ_bytes = pl.nbytes / 8;
+    rp.marks = pl.marks;
+    rp.nbytes = pl.nbytes;
     rp.epoch = p.epoch;
     p.inside = v0[0] >= 0 && v0[0] < g->n[0] && v0[1] >= 0 && v0[1] < g->n[1] && v0[2] >= 0 &&
                v0[2] < g->n[2];
@@ -497,7 +500,7 @@ hipError_t prepare_frame(const vg_grid *g, const FramePlan &p, hipStream_t st)
     if (p.wrap) {
         e = launch_fill(g->scratch + g->lay.seed, 0, g->lay.bitx - g->lay.seed, st);
         if (e == hipSuccess)
-            e = launch_fill(g->scratch + g->lay.traced, 0, g->lay.hz - g->lay.traced, st);
+            e = launch_fill(g->scratch + g->lay.marks, 0, g->lay.hz - g->lay.marks, st);
     }
     if (e == hipSuccess && p.upload_hz)
         e = launch_upload(reinterpret_cast<uint32_t *>(g->scratch + g->lay.hz),
@@ -602,7 +605,8 @@ size_t vg_grid_bytes(int32_t gx, int32_t gy, int32_t gz)
 {
     if (gx < 1 || gy < 1 || gz < 1 || gx > 65535 || gy > 65535 || gz > 65535)
         return 0;
-    if ((int64_t)grid_pitch(gx) * gy * gz >= ((int64_t)1 << 31))
+    // below 2^30: the two mark planes (2x) stay inside 31-bit buffer offsets
+    if ((int64_t)grid_pitch(gx) * gy * gz >= ((int64_t)1 << 30))
         return 0;
     return (size_t)grid_pitch(gx) * gy * gz;
 }
@@ -846,6 +850,7 @@ vg_status vg_integrate_batch(const vg_frame *frames, int32_t n_frames, void *wor
     std::vector<FramePlan> plans((size_t)n_frames);
     std::vector<int32_t> grid_of((size_t)n_frames), round_of((size_t)n_frames);
     std::vector<const uint8_t *> shift_src((size_t)n_frames);
+    std::vector<uint8_t *> frame_loc((size_t)n_frames);   // grid buffer the frame merges into
     for (int32_t i = 0; i < n_frames; ++i) {
         const vg_frame &f = frames[i];
         vg_grid *g = f.grid;
@@ -892,6 +897,7 @@ vg_status vg_integrate_batch(const vg_frame *frames, int32_t n_frames, void *wor
             shift_src[i] = gs.loc;
             std::swap(gs.loc, gs.spare);
         }
+        frame_loc[i] = gs.loc;
         vg_status rc = plan_frame(g, gs, kind, f.data, pitch, W, H, &f.sensor, &f.T_w_c, plans[i]);
         if (rc != VG_OK)
             return rc;
@@ -937,7 +943,7 @@ vg_status vg_integrate_batch(const vg_frame *frames, int32_t n_frames, void *wor
             std::memset(&d, 0, sizeof d);
             d.sp = p.sp;
             d.rp = p.rp;
-            d.loc = p.rp.loc;
+            d.loc = frame_loc[i];
             d.shift_src = shift_src[i];
             d.rows = p.rows;
             for (int a = 0; a < 3; ++a)

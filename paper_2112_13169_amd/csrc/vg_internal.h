@@ -49,7 +49,9 @@ struct Planes {
     uint8_t *seed;       // seed stamps, [pz][py][seed_pitch]
     uint32_t *bitx;      // seeds dilated along x, [pz][py][wx] words
     uint32_t *occ;       // occupied voxels of the frame, bit i = grid index i
-    uint8_t *traced;     // "unknown and traced" stamps, one byte per grid index
+    uint8_t *marks;      // free stamps [0, nbytes), "unknown and traced" stamps
+                         // [nbytes, 2 nbytes), one byte per grid index each
+    uint32_t nbytes;     // bytes of the device-layout grid
     int32_t lo[3], hi[3];  // padded box that holds every seed (lo > hi: none)
     uint32_t epoch;      // stamp of this frame (1..255)
 };
@@ -82,9 +84,10 @@ struct RayParams {
     int32_t tile_log2w;   // 0..6
     int32_t tiles_a, tiles;
     const int32_t *hz;    // spinning: half height per column
-    uint8_t *loc;
     const uint32_t *occ;
-    uint8_t *traced;
+    uint32_t occ_bytes;
+    uint8_t *marks;       // as Planes::marks
+    uint32_t nbytes;
     uint32_t epoch;
 };
 
@@ -128,7 +131,7 @@ hipError_t launch_dilate(const Planes &pl, hipStream_t st, const StageEvents &ev
 // The walk of every fan ray.  camera_inside: the camera voxel lies in the grid.
 hipError_t launch_rays(const RayParams &p, bool camera_inside, hipStream_t st,
                        const StageEvents &ev = {});
-// Traced stamps and occupied bits -> the local grid, over the given rows.
+// Marks and occupied bits -> the local grid, over the given rows.
 hipError_t launch_resolve(const Planes &pl, uint8_t *loc, const RowBox &rows, hipStream_t st,
                           const StageEvents &ev = {});
 hipError_t launch_shift(const uint8_t *src, uint8_t *dst, const int32_t n[3],

@@ -10,15 +10,14 @@
 //   k_dilate_yz   vox_inf along x, then along y and z.  The union of the
 //                 (2 vox_inf + 1)^3 cubes is exactly this separable dilation.
 //   k_rays        Alg. 2: one wavefront per tile of 64 fan targets (8 x 8 by
-//                 default), one lane per ray.  Before its first occupied voxel a ray marks voxels
-//                 free in the local grid; after it, it stamps them "unknown and
-//                 traced" in a separate plane.  Occupancy words are fetched for
-//                 8 walk steps at a time so that the loads overlap.
-//   k_resolve     Alg. 3 for the marks that need priority: traced stamps become
-//                 unknown, then the frame's occupied voxels become occupied.
-// The free marks need no merge pass: free lands only on voxels no traced stamp
-// or occupied bit overrides later.  All voxel stores are idempotent byte
-// stores; no atomics on voxels.
+//                 default), one lane per ray.  Each step stamps its voxel in
+//                 one of two per-frame mark planes: "free" before the ray's
+//                 first occupied voxel, "unknown and traced" from it on.
+//                 Occupancy words are fetched for 8 walk steps at a time so
+//                 that the loads overlap.
+//   k_resolve     Alg. 3: occupied bits, then traced stamps, then free stamps
+//                 decide each voxel of the local grid the frame reaches.
+// All stores are idempotent byte stores; no atomics.
 //
 // Floating point: contraction is off (also on the command line) so every fp32
 // operation rounds exactly as written; fp32 division is the correctly rounded
@@ -275,12 +274,12 @@ __device__ __forceinline__ void rays_body(const RayParams &p, int32_t tile)
         return;
     Walk w;
     walk_setup(w, p.wf, dir);
-    walk_ray<kGeneral>(w, m2, p.occ, p.loc, p.traced, (uint8_t)p.epoch);
+    walk_ray<kGeneral>(w, m2, walk_mem(p.occ, p.occ_bytes, p.marks, p.nbytes, p.epoch & 0xFFu));
 }
 
-// Alg. 3 for the prioritised marks.  One lane per 16 voxels of a grid row of
-// the row box: occupied bit -> occupied; else traced stamp -> unknown; else
-// unchanged.
+// Alg. 3: the frame's marks merged into the local grid.  One lane per 16
+// voxels of a grid row of the row box: occupied bit -> occupied; else a
+// traced stamp -> unknown; else a free stamp -> free; else unchanged.
 __device__ __forceinline__ void resolve_body(const Planes &pl, uint8_t *loc, const RowBox &rows,
                                              int64_t gid)
 {
@@ -294,11 +293,14 @@ __device__ __forceinline__ void resolve_body(const Planes &pl, uint8_t *loc, con
     const int32_t z = rows.z0 + (int32_t)(row / ny);
     const int64_t base = 32 * (int64_t)pl.wx * (y + (int64_t)pl.n[1] * z) + 16 * k;
     const uint32_t occ16 = (pl.occ[base >> 5] >> (base & 16)) & 0xFFFFu;
-    const uint4 tr = *reinterpret_cast<const uint4 *>(pl.traced + base);
+    const uint4 fr = *reinterpret_cast<const uint4 *>(pl.marks + base);
+    const uint4 tr = *reinterpret_cast<const uint4 *>(pl.marks + pl.nbytes + base);
     const uint32_t rep = (pl.epoch & 0xFFu) * 0x01010101u;
     const uint32_t tr16 = byte_eq_mask(tr.x, rep) | (byte_eq_mask(tr.y, rep) << 4) |
                           (byte_eq_mask(tr.z, rep) << 8) | (byte_eq_mask(tr.w, rep) << 12);
-    if ((occ16 | tr16) == 0)
+    const uint32_t fr16 = byte_eq_mask(fr.x, rep) | (byte_eq_mask(fr.y, rep) << 4) |
+                          (byte_eq_mask(fr.z, rep) << 8) | (byte_eq_mask(fr.w, rep) << 12);
+    if ((occ16 | tr16 | fr16) == 0)
         return;
     uint4 v = *reinterpret_cast<const uint4 *>(loc + base);
     uint32_t *vw = reinterpret_cast<uint32_t *>(&v);
@@ -307,7 +309,10 @@ __device__ __forceinline__ void resolve_body(const Planes &pl, uint8_t *loc, con
         // spread 4 mask bits to 4 byte masks
         uint32_t om = (((occ16 >> (4 * j)) & 0xFu) * 0x00204081u & 0x01010101u) * 0xFFu;
         uint32_t tm = (((tr16 >> (4 * j)) & 0xFu) * 0x00204081u & 0x01010101u) * 0xFFu;
-        vw[j] = (vw[j] & ~(om | tm)) | (0x02020202u & om);
+        uint32_t fm = (((fr16 >> (4 * j)) & 0xFu) * 0x00204081u & 0x01010101u) * 0xFFu;
+        tm &= ~om;
+        fm &= ~(om | tm);
+        vw[j] = (vw[j] & ~(om | tm | fm)) | (0x02020202u & om) | (0x01010101u & fm);
     }
     *reinterpret_cast<uint4 *>(loc + base) = v;
 }

@@ -73,6 +73,8 @@ def test_scratch_and_grid_bytes():
     assert vg.vg_grid_bytes(200, 200, 100) == 224 * 200 * 100
     assert vg.vg_scratch_bytes(0, 1, 1, 1) == 0
     assert vg.vg_grid_bytes(2048, 2048, 1024) == 0               # >= 2^31 bytes
+    assert vg.vg_grid_bytes(1024, 1024, 1024) == 0               # = 2^30: the limit
+    assert vg.vg_grid_bytes(1024, 1024, 1023) == 1024 * 1024 * 1023
     assert vg.vg_scratch_bytes(8, 8, 8, 17) == 0                 # vox_inf above 16
 
 

@@ -26,10 +26,13 @@ int main(int argc, char **argv)
     rng_state += argc > 2 ? (uint64_t)atoll(argv[2]) : 0;
     long long bad = 0, voxels = 0, steps = 0;
     for (int trial = 0; trial < trials; ++trial) {
+        // every third trial: a large grid and long rays, so that most chunks
+        // take the path without per-step tests
+        const bool big = trial % 3 == 1;
         WalkFrame f;
-        f.n[0] = 1 + rnd() % 48;
-        f.n[1] = 1 + rnd() % 40;
-        f.n[2] = 1 + rnd() % 24;
+        f.n[0] = 1 + rnd() % (big ? 200 : 48);
+        f.n[1] = 1 + rnd() % (big ? 160 : 40);
+        f.n[2] = 1 + rnd() % (big ? 120 : 24);
         f.gxp = 32 * ((f.n[0] + 31) / 32);
         const int nx = f.n[0], ny = f.n[1], nz = f.n[2];
         const bool outside = trial % 4 == 3;
@@ -45,9 +48,9 @@ int main(int argc, char **argv)
         }
         const bool inside = f.v0[0] >= 0 && f.v0[0] < nx && f.v0[1] >= 0 && f.v0[1] < ny &&
                             f.v0[2] >= 0 && f.v0[2] < nz;
-        std::vector<uint32_t> occ((size_t)f.gxp / 32 * ny * nz + 1, 0);
+        std::vector<uint32_t> occ((size_t)f.gxp / 32 * ny * nz, 0);
         std::vector<uint8_t> ms((size_t)nx * ny * nz, 0);
-        const uint32_t density = 8 + rnd() % 120;
+        const uint32_t density = big ? 200 + rnd() % 4000 : 8 + rnd() % 120;
         for (int z = 0; z < nz; ++z)
             for (int y = 0; y < ny; ++y)
                 for (int x = 0; x < nx; ++x)
@@ -63,8 +66,9 @@ int main(int argc, char **argv)
             if (trial % 11 == 0 && a == trial % 3)
                 dir[a] = 0.0f;
         }
-        const int32_t m2 = 1 + (int32_t)(rnd() % 4000);
-        std::vector<uint8_t> loc((size_t)f.gxp * ny * nz, 0), tr((size_t)f.gxp * ny * nz, 0);
+        const int32_t m2 = 1 + (int32_t)(rnd() % (big ? 60000 : 4000));
+        const uint32_t n = (uint32_t)((size_t)f.gxp * ny * nz);
+        std::vector<uint8_t> marks(2 * (size_t)n, 0);
         const uint8_t stamp = 1 + rnd() % 255;
 
         bool dead = false;
@@ -73,10 +77,11 @@ int main(int argc, char **argv)
         if (!dead) {
             Walk w;
             walk_setup(w, f, dir);
+            const WalkMem m = walk_mem(occ.data(), (uint32_t)(4 * occ.size()), marks.data(), n, stamp);
             if (inside)
-                walk_ray<false>(w, m2, occ.data(), loc.data(), tr.data(), stamp);
+                walk_ray<false>(w, m2, m);
             else
-                walk_ray<true>(w, m2, occ.data(), loc.data(), tr.data(), stamp);
+                walk_ray<true>(w, m2, m);
         }
         std::vector<uint8_t> ref = ms;
         steps += og_trace_ray(f.o, dir, m2, nx, ny, nz, ref.data(), nullptr, nullptr, 0);
@@ -85,10 +90,10 @@ int main(int argc, char **argv)
                 for (int x = 0; x < nx; ++x) {
                     size_t i = x + (size_t)nx * (y + (size_t)ny * z);
                     size_t j = x + (size_t)f.gxp * (y + (size_t)ny * z);
-                    int got = ms[i] == OG_OCCUPIED ? OG_OCCUPIED
-                              : tr[j] == stamp     ? OG_TRACED
-                              : loc[j] == 1        ? OG_FREE
-                                                   : OG_UNKNOWN;
+                    int got = ms[i] == OG_OCCUPIED       ? OG_OCCUPIED
+                              : marks[n + j] == stamp    ? OG_TRACED
+                              : marks[j] == stamp        ? OG_FREE
+                                                         : OG_UNKNOWN;
                     if (got != ref[i]) {
                         if (bad < 5)
                             fprintf(stderr, "trial %d voxel (%d,%d,%d): oracle %d walk %d\n", trial,
