@@ -162,6 +162,12 @@ vg_status vg_shift_grid(vg_grid *g, int32_t dx, int32_t dy, int32_t dz, void *st
  * delta = floor((t_w_c - origin_w) / vox_size) - grid_size / 2.  Host-only. */
 vg_status vg_center_offset(const vg_grid *g, const float t_w_c[3], int32_t delta_out[3]);
 
+/* vg_center_offset as it will be once shifts totalling pending[3] voxels
+ * have been applied (NULL: none) -- the offsets of consecutive frames of one
+ * grid in a batch.  Host-only. */
+vg_status vg_center_offset_after(const vg_grid *g, const int32_t pending[3], const float t_w_c[3],
+                                 int32_t delta_out[3]);
+
 /* Current grid origin in the world frame (host-only). */
 vg_status vg_grid_origin(const vg_grid *g, float origin_w_out[3]);
 

@@ -754,12 +754,19 @@ vg_status vg_shift_grid(vg_grid *g, int32_t dx, int32_t dy, int32_t dz, void *st
     return VG_OK;
 }
 
-vg_status vg_center_offset(const vg_grid *g, const float t_w_c[3], int32_t delta_out[3])
+vg_status vg_center_offset_after(const vg_grid *g, const int32_t pending[3], const float t_w_c[3],
+                                 int32_t delta_out[3])
 {
     if (!g || !t_w_c || !delta_out)
         return VG_ERR_ARG;
     float origin[3];
-    current_origin(g, origin);
+    for (int a = 0; a < 3; ++a) {
+        const int64_t s = (int64_t)g->shift[a] + (pending ? pending[a] : 0);
+        if (s > (1 << 24) || s < -(1 << 24))
+            return VG_ERR_ARG;
+        float off = (float)s * g->s;
+        origin[a] = g->base[a] + off;
+    }
     int32_t d[3];
     for (int a = 0; a < 3; ++a) {
         if (!std::isfinite(t_w_c[a]))
@@ -773,6 +780,11 @@ vg_status vg_center_offset(const vg_grid *g, const float t_w_c[3], int32_t delta
     for (int a = 0; a < 3; ++a)
         delta_out[a] = d[a];
     return VG_OK;
+}
+
+vg_status vg_center_offset(const vg_grid *g, const float t_w_c[3], int32_t delta_out[3])
+{
+    return vg_center_offset_after(g, nullptr, t_w_c, delta_out);
 }
 
 vg_status vg_grid_origin(const vg_grid *g, float origin_w_out[3])

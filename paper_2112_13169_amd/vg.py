@@ -75,6 +75,7 @@ def lib():
         L.vg_integrate_points.argtypes = [P, P, i64, sp, pp, P]
         L.vg_shift_grid.argtypes = [P, i32, i32, i32, P]
         L.vg_center_offset.argtypes = [P, P, P]
+        L.vg_center_offset_after.argtypes = [P, P, P, P]
         L.vg_grid_origin.argtypes = [P, P]
         L.vg_read_grid.argtypes = [P, P, i32, P]
         L.vg_write_grid.argtypes = [P, P, i32, P]
@@ -91,7 +92,7 @@ def lib():
                      "vg_integrate_points", "vg_shift_grid", "vg_center_offset",
                      "vg_grid_origin", "vg_read_grid", "vg_write_grid", "vg_destroy_grid",
                      "vg_set_profile_events", "vg_integrate_batch", "vg_set_ray_tile",
-                     "vg_rebind_grid"):
+                     "vg_rebind_grid", "vg_center_offset_after"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -212,6 +213,26 @@ def vg_center_offset(g, t_w_c):
     d = (ctypes.c_int32 * 3)()
     _check(lib().vg_center_offset(g, t, d), "vg_center_offset")
     return tuple(d)
+
+
+def vg_center_offset_after(g, pending, t_w_c):
+    p = (ctypes.c_int32 * 3)(*[int(v) for v in pending])
+    t = (ctypes.c_float * 3)(*[float(v) for v in np.asarray(t_w_c, np.float32)])
+    d = (ctypes.c_int32 * 3)()
+    _check(lib().vg_center_offset_after(g, p, t, d), "vg_center_offset_after")
+    return tuple(d)
+
+
+def sequence_shifts(g, positions):
+    """Re-centring shifts of consecutive frames of one grid (camera positions
+    in order), as they will be when applied one after another."""
+    pending = np.zeros(3, np.int64)
+    out = []
+    for t in positions:
+        d = vg_center_offset_after(g, pending, t)
+        out.append(d)
+        pending += np.asarray(d, np.int64)
+    return out
 
 
 def vg_grid_origin(g):

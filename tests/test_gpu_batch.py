@@ -170,6 +170,8 @@ def test_sequence_batch_with_shifts_matches_oracle():
         d = oracle.center_offset(dims, t.s, org, f.t)
         shifts.append(d)
         origin_shift = origin_shift + np.asarray(d, np.int32)
+    assert [tuple(d) for d in vg.sequence_shifts(t.h, [f.t for f in frs])] == \
+        [tuple(d) for d in shifts]
     dev = [DevFrame(t, f, d) for f, d in zip(frs, shifts)]
     _say(f"sequence batch shifts {shifts}")
     vg.vg_integrate_batch([d.desc for d in dev], _workspace(8))
