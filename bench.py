@@ -144,7 +144,7 @@ def run_served(frames, torch, vg, serve, rate_hz=30.0):
                                ("all at once", n_robots, float("inf"))]:
         robots = [serve.Robot(r, f0.dims, f0.vox_size, frames[r][0].origin, f0.vox_inf)
                   for r in range(n_robots)]
-        budget = fixed + grids * gbytes + 128 * fbytes
+        budget = fixed + grids * gbytes + 16 * fbytes
         srv = serve.Server(backend, robots, fbytes, budget, max_batch=64, streams=2)
         arrivals = serve.poisson_arrivals(n_robots, n_frames, rate_hz,
                                           np.random.default_rng([2112131694, n_robots]))
@@ -594,7 +594,7 @@ def main():
                 "kernel_ms": round(kernel_live_ms, 5)}
     else:
         # algorithmic HBM bytes of the streaming stages
-        nbytes = {"k_shift": 2.0 * nvox,                   # read + write the grid
+        nbytes = {"k_shift": 0.02 * nvox,                  # ring slabs: ~1 % of the grid
                   "k_seed": 5.0 * fr0.depth.size,           # depth in, stamp out
                   "k_dilate": nvox / 8.0 * 2 + nvox,        # seeds in, bit planes out
                   "k_resolve": nvox * (1 + 1 / 8.0) + 2.0 * upd.mean()}[dominant]

@@ -11,8 +11,8 @@
  * Argument names follow the paper's nomenclature (Table I).
  *
  * Conventions for every entry point:
- *  - Ownership: the caller owns every device buffer (the local grid, its spare
- *    copy, the scratch workspace, depth images).  The library never allocates
+ *  - Ownership: the caller owns every device buffer (the local grid, the
+ *    scratch workspace, depth images).  The library never allocates
  *    or frees device memory; a vg_grid handle owns host metadata only.
  *  - Asynchrony: device work is enqueued on `stream` (a hipStream_t; NULL is
  *    the default stream) and nothing blocks the host, except where stated.
@@ -94,8 +94,8 @@ typedef struct vg_sensor {
  * (vox_depth > 16384, half sizes > 16384). */
 vg_status vg_fan_sizes(const vg_sensor *sensor, float vox_size, int64_t out[4]);
 
-/* Bytes of each of the two device grid buffers (local grid and its spare)
- * of a grid of this size.  Host-only; 0 for invalid sizes. */
+/* Bytes of the device buffer of a grid of this size.  Host-only; 0 for
+ * invalid sizes. */
 size_t vg_grid_bytes(int32_t grid_size_x, int32_t grid_size_y, int32_t grid_size_z);
 
 /* Bytes of device scratch workspace a grid of this size and vox_inf needs
@@ -105,9 +105,9 @@ size_t vg_scratch_bytes(int32_t grid_size_x, int32_t grid_size_y, int32_t grid_s
 
 /* Step 1 (Sec. IV-A): bind caller buffers to a new grid and set every voxel
  * of loc_grid to unknown (enqueued on `stream`).
- *   loc_grid, loc_spare: device, distinct, 16-byte aligned, grid_bytes >=
- *     vg_grid_bytes(...) bytes each.  The spare buffer receives shifted grids
- *     (vg_shift_grid swaps the two).
+ *   loc_grid: device, 16-byte aligned, grid_bytes >= vg_grid_bytes(...).  It
+ *     holds the grid as a ring buffer, so shifts work in place.
+ *   loc_spare: unused (may be NULL).
  *   scratch: device, scratch_bytes >= vg_scratch_bytes(..., vox_inf), 256-byte
  *     aligned; it is cleared here and owned by the grid until destroyed.
  *   origin_w: world position (m) of the grid corner (voxel (0,0,0)'s minimum
@@ -155,7 +155,9 @@ vg_status vg_integrate_points(vg_grid *g, const float *points, int64_t n_points,
 /* Step 5 (Sec. IV-E): shift the grid content by an integer voxel offset:
  * new[x,y,z] = old[x+dx, y+dy, z+dz] where that lies inside, else unknown; the
  * grid origin moves by (dx,dy,dz)*vox_size (kept as an integer count so it
- * never drifts).  Enqueued on `stream`; (0,0,0) does nothing. */
+ * never drifts).  The buffer is a ring: the shift moves its offsets and
+ * clears only the slabs that enter the grid (|dx|*gy*gz + |dy|*gx*gz +
+ * |dz|*gx*gy voxels at most).  Enqueued on `stream`; (0,0,0) does nothing. */
 vg_status vg_shift_grid(vg_grid *g, int32_t dx, int32_t dy, int32_t dz, void *stream);
 
 /* Offset that re-centres the grid on a camera at t_w_c (metres):
@@ -176,7 +178,8 @@ vg_status vg_grid_origin(const vg_grid *g, float origin_w_out[3]);
  * reading a host destination. */
 vg_status vg_read_grid(const vg_grid *g, uint8_t *dst, int32_t dst_is_device, void *stream);
 
-/* Overwrite the local grid (restore a checkpoint) from src (linear layout). */
+/* Overwrite the local grid (restore a checkpoint) from src (linear layout);
+ * the ring offsets restart at 0. */
 vg_status vg_write_grid(vg_grid *g, const uint8_t *src, int32_t src_is_device, void *stream);
 
 /* One frame of a batch. */

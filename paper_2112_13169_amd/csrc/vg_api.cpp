@@ -136,7 +136,8 @@ struct vg_grid {
     float base[3];
     int32_t shift[3];
     int32_t r;
-    uint8_t *loc, *spare;
+    uint8_t *loc;            // ring buffer of the local grid
+    int32_t ring[3];         // its ring offsets
     uint8_t *scratch;
     size_t scratch_bytes;
     Layout lay;
@@ -333,32 +334,66 @@ RowBox row_union(const RowBox &a, const RowBox &b)
 // by frame and writes it back only when every frame has been planned.
 struct GridState {
     int32_t shift[3];
+    int32_t ring[3];
     uint32_t epoch;
     int32_t hz_vd;
     double hz_fov;
-    uint8_t *loc, *spare;
 };
 
 GridState state_of(const vg_grid *g)
 {
     GridState s;
     std::memcpy(s.shift, g->shift, sizeof s.shift);
+    std::memcpy(s.ring, g->ring, sizeof s.ring);
     s.epoch = g->epoch;
     s.hz_vd = g->hz_vd;
     s.hz_fov = g->hz_fov;
-    s.loc = g->loc;
-    s.spare = g->spare;
     return s;
 }
 
 void store_state(vg_grid *g, const GridState &s)
 {
     std::memcpy(g->shift, s.shift, sizeof s.shift);
+    std::memcpy(g->ring, s.ring, sizeof s.ring);
     g->epoch = s.epoch;
     g->hz_vd = s.hz_vd;
     g->hz_fov = s.hz_fov;
-    g->loc = s.loc;
-    g->spare = s.spare;
+}
+
+// Step 5 on the ring buffer (Sec. IV-E): grid coordinate x now holds what
+// x + d held, so the ring offsets move by d and the coordinates whose source
+// lay outside the grid -- [n - d, n) for d > 0, [0, -d) for d < 0 -- are
+// cleared.  Fills `c` (loc excepted) and moves the state's offsets and shift.
+void plan_shift(const vg_grid *g, GridState &gs, const int32_t d[3], SlabClear &c)
+{
+    for (int a = 0; a < 3; ++a) {
+        const int32_t n = g->n[a];
+        int64_t r = ((int64_t)gs.ring[a] + d[a]) % n;
+        if (r < 0)
+            r += n;
+        gs.ring[a] = (int32_t)r;
+        gs.shift[a] += d[a];
+        c.n[a] = n;
+        c.ring[a] = gs.ring[a];
+        if (d[a] > 0) {
+            c.lo[a] = (int32_t)std::max<int64_t>((int64_t)n - d[a], 0);
+            c.hi[a] = n;
+        } else if (d[a] < 0) {
+            c.lo[a] = 0;
+            c.hi[a] = (int32_t)std::min<int64_t>(-(int64_t)d[a], n);
+        } else {
+            c.lo[a] = c.hi[a] = 0;
+        }
+    }
+    c.gxp = g->lay.gxp;
+    // a shift past the grid on some axis clears everything: restart the ring
+    // at 0 (the plain layout keeps the merge on its aligned path)
+    bool all = false;
+    for (int a = 0; a < 3; ++a)
+        all = all || (c.hi[a] - c.lo[a] >= c.n[a]);
+    if (all)
+        for (int a = 0; a < 3; ++a)
+            gs.ring[a] = c.ring[a] = 0;
 }
 
 // Host plan of steps 2-4 for one frame: every per-frame constant and launch
@@ -373,6 +408,7 @@ struct FramePlan {
     bool wrap;        // the stamp planes must be cleared first (stamp wrapped)
     bool upload_hz;   // the spinning fan table must be (re)written
     uint32_t epoch;
+    int32_t ring[3];  // ring offsets of the grid when the frame merges
 };
 
 vg_status plan_frame(const vg_grid *g, const GridState &gs, int kind, const float *data,
@@ -413,6 +449,7 @@ vg_status plan_frame(const vg_grid *g, const GridState &gs, int kind, const floa
     p.wrap = gs.epoch == 255;
     p.epoch = p.wrap ? 1 : gs.epoch + 1;
     p.upload_hz = kind == kSpinning && (gs.hz_vd != fan.vd || gs.hz_fov != sensor->fov_y);
+    std::memcpy(p.ring, gs.ring, sizeof p.ring);
 
     Planes pl;
     std::memcpy(pl.n, g->n, sizeof pl.n);
@@ -573,7 +610,7 @@ vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_float
     if (e == hipSuccess)
         e = launch_rays(p.rp, p.inside, st, stage(kStageRays));
     if (e == hipSuccess)
-        e = launch_resolve(p.sp.pl, g->loc, p.rows, st, stage(kStageResolve));
+        e = launch_resolve(p.sp.pl, g->loc, p.rows, p.ring, st, stage(kStageResolve));
     if (ev)
         ++g->prof_next;
     if (e != hipSuccess)
@@ -633,9 +670,9 @@ vg_status vg_create_grid(int32_t gx, int32_t gy, int32_t gz, float vox_size,
     if (!origin_w || !std::isfinite(origin_w[0]) || !std::isfinite(origin_w[1]) ||
         !std::isfinite(origin_w[2]))
         return VG_ERR_ARG;
-    if (!loc_grid || !loc_spare || loc_grid == loc_spare || !scratch ||
-        ((uintptr_t)scratch % kAlign) != 0 || ((uintptr_t)loc_grid % 16) != 0 ||
-        ((uintptr_t)loc_spare % 16) != 0)
+    (void)loc_spare;   // not needed: the local grid is a ring buffer
+    if (!loc_grid || !scratch || ((uintptr_t)scratch % kAlign) != 0 ||
+        ((uintptr_t)loc_grid % 16) != 0)
         return VG_ERR_ARG;
     const size_t n = vg_grid_bytes(gx, gy, gz);
     Layout lay = layout_for(gx, gy, gz, vox_inf);
@@ -655,7 +692,8 @@ vg_status vg_create_grid(int32_t gx, int32_t gy, int32_t gz, float vox_size,
     }
     g->r = vox_inf;
     g->loc = loc_grid;
-    g->spare = loc_spare;
+    for (int a = 0; a < 3; ++a)
+        g->ring[a] = 0;
     g->scratch = static_cast<uint8_t *>(scratch);
     g->scratch_bytes = scratch_bytes;
     g->lay = lay;
@@ -680,9 +718,9 @@ vg_status vg_rebind_grid(vg_grid *g, uint8_t *loc_grid, uint8_t *loc_spare, size
 {
     if (!g)
         return VG_ERR_ARG;
-    if (!loc_grid || !loc_spare || loc_grid == loc_spare || !scratch ||
-        ((uintptr_t)scratch % kAlign) != 0 || ((uintptr_t)loc_grid % 16) != 0 ||
-        ((uintptr_t)loc_spare % 16) != 0)
+    (void)loc_spare;
+    if (!loc_grid || !scratch || ((uintptr_t)scratch % kAlign) != 0 ||
+        ((uintptr_t)loc_grid % 16) != 0)
         return VG_ERR_ARG;
     if (scratch_bytes < g->lay.fixed || grid_bytes < vg_grid_bytes(g->n[0], g->n[1], g->n[2]))
         return VG_ERR_BUDGET;
@@ -692,7 +730,6 @@ vg_status vg_rebind_grid(vg_grid *g, uint8_t *loc_grid, uint8_t *loc_spare, size
     if (launch_fill(scratch, 0, g->lay.fixed, static_cast<hipStream_t>(stream)) != hipSuccess)
         return VG_ERR_HIP;
     g->loc = loc_grid;
-    g->spare = loc_spare;
     g->scratch = static_cast<uint8_t *>(scratch);
     g->scratch_bytes = scratch_bytes;
     g->epoch = 0;
@@ -743,14 +780,14 @@ vg_status vg_shift_grid(vg_grid *g, int32_t dx, int32_t dy, int32_t dz, void *st
     }
     if (!same_device(g))
         return VG_ERR_STATE;
-    hipError_t e = launch_shift(g->loc, g->spare, g->n, d, static_cast<hipStream_t>(stream), sev);
+    GridState gs = state_of(g);
+    SlabClear c;
+    plan_shift(g, gs, d, c);
+    c.loc = g->loc;
+    hipError_t e = launch_clear(c, static_cast<hipStream_t>(stream), sev);
     if (e != hipSuccess)
         return VG_ERR_HIP;
-    uint8_t *t = g->loc;
-    g->loc = g->spare;
-    g->spare = t;
-    for (int a = 0; a < 3; ++a)
-        g->shift[a] += d[a];
+    store_state(g, gs);
     return VG_OK;
 }
 
@@ -799,18 +836,25 @@ vg_status vg_read_grid(const vg_grid *g, uint8_t *dst, int32_t dst_is_device, vo
 {
     if (!g || !dst)
         return VG_ERR_ARG;
-    return hip_status(copy_grid(dst, g->n[0], g->loc, g->lay.gxp, g->n,
-                                dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
-                                static_cast<hipStream_t>(stream)));
+    const hipMemcpyKind kind = dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    const hipStream_t st = static_cast<hipStream_t>(stream);
+    if (g->ring[0] == 0 && g->ring[1] == 0 && g->ring[2] == 0)
+        return hip_status(copy_grid(dst, g->n[0], g->loc, g->lay.gxp, g->n, kind, st));
+    return hip_status(copy_grid_from_ring(dst, g->loc, g->lay.gxp, g->n, g->ring, kind, st));
 }
 
 vg_status vg_write_grid(vg_grid *g, const uint8_t *src, int32_t src_is_device, void *stream)
 {
     if (!g || !src)
         return VG_ERR_ARG;
-    return hip_status(copy_grid(g->loc, g->lay.gxp, src, g->n[0], g->n,
-                                src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
-                                static_cast<hipStream_t>(stream)));
+    hipError_t e = copy_grid(g->loc, g->lay.gxp, src, g->n[0], g->n,
+                             src_is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                             static_cast<hipStream_t>(stream));
+    if (e != hipSuccess)
+        return VG_ERR_HIP;
+    for (int a = 0; a < 3; ++a)
+        g->ring[a] = 0;   // written in the plain layout
+    return VG_OK;
 }
 
 vg_status vg_set_profile_events(vg_grid *g, void *const *events, int32_t n_sets)
@@ -861,8 +905,8 @@ vg_status vg_integrate_batch(const vg_frame *frames, int32_t n_frames, void *wor
     std::vector<int32_t> grid_rounds;
     std::vector<FramePlan> plans((size_t)n_frames);
     std::vector<int32_t> grid_of((size_t)n_frames), round_of((size_t)n_frames);
-    std::vector<const uint8_t *> shift_src((size_t)n_frames);
-    std::vector<uint8_t *> frame_loc((size_t)n_frames);   // grid buffer the frame merges into
+    std::vector<uint8_t> moved_of((size_t)n_frames);
+    std::vector<SlabClear> clears((size_t)n_frames);
     for (int32_t i = 0; i < n_frames; ++i) {
         const vg_frame &f = frames[i];
         vg_grid *g = f.grid;
@@ -902,14 +946,12 @@ vg_status vg_integrate_batch(const vg_frame *frames, int32_t n_frames, void *wor
                 return VG_ERR_ARG;
             moved = moved || f.shift[a] != 0;
         }
-        shift_src[i] = nullptr;
+        moved_of[i] = moved ? 1 : 0;
+        std::memset(&clears[i], 0, sizeof clears[i]);
         if (moved) {
-            for (int a = 0; a < 3; ++a)
-                gs.shift[a] += f.shift[a];
-            shift_src[i] = gs.loc;
-            std::swap(gs.loc, gs.spare);
+            plan_shift(g, gs, f.shift, clears[i]);
+            clears[i].loc = g->loc;
         }
-        frame_loc[i] = gs.loc;
         vg_status rc = plan_frame(g, gs, kind, f.data, pitch, W, H, &f.sensor, &f.T_w_c, plans[i]);
         if (rc != VG_OK)
             return rc;
@@ -950,16 +992,15 @@ vg_status vg_integrate_batch(const vg_frame *frames, int32_t n_frames, void *wor
             const FramePlan &p = plans[(size_t)i];
             const vg_grid *g = grids[(size_t)grid_of[i]];
             int64_t blocks[kBatchStages];
-            batch_blocks(g, p, shift_src[i] != nullptr, blocks);
+            batch_blocks(g, p, moved_of[i] != 0, blocks);
             FrameDesc d;
             std::memset(&d, 0, sizeof d);
             d.sp = p.sp;
             d.rp = p.rp;
-            d.loc = frame_loc[i];
-            d.shift_src = shift_src[i];
+            d.loc = g->loc;
+            d.clear = clears[i];
             d.rows = p.rows;
-            for (int a = 0; a < 3; ++a)
-                d.shift[a] = shift_src[i] ? frames[i].shift[a] : 0;
+            std::memcpy(d.ring, p.ring, sizeof d.ring);
             d.inside = p.inside ? 1 : 0;
             d.seed_bx = p.kind == kPoints ? 0 : std::max((p.sp.W + 63) / 64, 1);
             std::memcpy(&fd[j], &d, sizeof d);

@@ -3,9 +3,15 @@
 //
 // Device layout of a grid: rows of gx voxels are stored with a pitch of
 // gxp = 32 * ceil(gx / 32) bytes (voxel (x, y, z) at x + gxp * (y + gy * z)),
-// so that the same linear index addresses the grid byte and its bit in the
-// per-frame occupancy plane (32-voxel words never straddle rows).  The
-// padding bytes x >= gx are never part of the grid.
+// so that the same linear index addresses a voxel's byte in a per-frame mark
+// plane and its bit in the per-frame occupancy plane (32-voxel words never
+// straddle rows).  The padding bytes x >= gx are never part of the grid.
+//
+// The local grid itself is a ring buffer: voxel (x, y, z) of the grid lives
+// at ((x + rx) mod gx, (y + ry) mod gy, (z + rz) mod gz) of its buffer, where
+// (rx, ry, rz) are the grid's ring offsets.  A shift (Sec. IV-E) moves the
+// offsets and clears only the slabs that enter the grid.  The per-frame
+// planes use the plain (unrotated) layout.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -91,14 +97,25 @@ struct RayParams {
     uint32_t epoch;
 };
 
+// Step 5 on a ring-buffered grid: after the ring offsets moved, the voxels
+// whose grid coordinate lies in an exposed slab [lo, hi) of some axis become
+// unknown.  One lane per grid row.
+struct SlabClear {
+    uint8_t *loc;
+    int32_t n[3];
+    int32_t gxp;
+    int32_t ring[3];        // ring offsets after the shift
+    int32_t lo[3], hi[3];   // exposed grid coordinates per axis (lo == hi: none)
+};
+
 // One frame of a batch round, as the batch kernels read it from device memory.
 struct FrameDesc {
     SeedParams sp;              // transform, image and the frame's planes
     RayParams rp;               // the ray fan
-    uint8_t *loc;               // the grid's current buffer (after the frame's shift)
-    const uint8_t *shift_src;   // the buffer the shift reads (if the frame shifts)
+    uint8_t *loc;               // the grid's buffer
+    SlabClear clear;            // the frame's shift (if it shifts)
     RowBox rows;                // rows of the resolve pass
-    int32_t shift[3];           // grid shift applied before the frame
+    int32_t ring[3];            // ring offsets the frame's merge uses
     int32_t inside;             // the camera voxel lies in the grid
     int32_t seed_bx;            // image seed blocks along x (points: 0)
 };
@@ -131,11 +148,11 @@ hipError_t launch_dilate(const Planes &pl, hipStream_t st, const StageEvents &ev
 // The walk of every fan ray.  camera_inside: the camera voxel lies in the grid.
 hipError_t launch_rays(const RayParams &p, bool camera_inside, hipStream_t st,
                        const StageEvents &ev = {});
-// Marks and occupied bits -> the local grid, over the given rows.
-hipError_t launch_resolve(const Planes &pl, uint8_t *loc, const RowBox &rows, hipStream_t st,
-                          const StageEvents &ev = {});
-hipError_t launch_shift(const uint8_t *src, uint8_t *dst, const int32_t n[3],
-                        const int32_t d[3], hipStream_t st, const StageEvents &ev = {});
+// Marks and occupied bits -> the local grid (ring offsets `ring`), over the
+// given rows.
+hipError_t launch_resolve(const Planes &pl, uint8_t *loc, const RowBox &rows,
+                          const int32_t ring[3], hipStream_t st, const StageEvents &ev = {});
+hipError_t launch_clear(const SlabClear &c, hipStream_t st, const StageEvents &ev = {});
 // Records the events of a stage that launches no kernel.
 hipError_t record_empty_stage(const StageEvents &ev, hipStream_t st);
 
@@ -148,5 +165,9 @@ hipError_t launch_batch_stage(int stage, const FrameDesc *fd, const int32_t *sta
 // Linear (pitch gx) <-> device layout (pitch gxp) copies of a whole grid.
 hipError_t copy_grid(uint8_t *dst, int64_t dst_pitch, const uint8_t *src, int64_t src_pitch,
                      const int32_t n[3], hipMemcpyKind kind, hipStream_t st);
+// Device layout with ring offsets -> linear: up to 8 box copies.
+hipError_t copy_grid_from_ring(uint8_t *dst, const uint8_t *src, int64_t src_pitch,
+                               const int32_t n[3], const int32_t ring[3], hipMemcpyKind kind,
+                               hipStream_t st);
 
 }  // namespace vg

@@ -1,7 +1,8 @@
 // vg_kernels.hip -- gfx950 kernels for depth-frame -> voxel-grid generation
 // (Toumieh & Lambert, arXiv 2112.13169, Sec. IV).
 //
-// One frame is a chain of launches on one stream:
+// One frame is a chain of launches on one stream (k_clear, for a shift of the
+// ring-buffered grid, runs before it when the grid is re-centred):
 //   k_seed        Alg. 1 lines 2-5: one lane per pixel / point: unproject,
 //                 transform, quantise; stamp the point's voxel in a seed plane
 //                 padded by vox_inf (byte stores of the frame's stamp: no
@@ -277,32 +278,98 @@ __device__ __forceinline__ void rays_body(const RayParams &p, int32_t tile)
     walk_ray<kGeneral>(w, m2, walk_mem(p.occ, p.occ_bytes, p.marks, p.nbytes, p.epoch & 0xFFu));
 }
 
+// (v + r) mod n for v, r in [0, n).
+__device__ __forceinline__ int32_t wrap_add(int32_t v, int32_t r, int32_t n)
+{
+    const int32_t s = v + r;
+    return s >= n ? s - n : s;
+}
+
+// Stamp matches of the 16 bytes at any byte address p: five aligned dword
+// loads from p rounded down to 4 (so up to 4 bytes past p + 16 are read),
+// realigned with v_alignbyte.
+__device__ __forceinline__ uint32_t stamp_mask16(const uint8_t *p, uint32_t rep)
+{
+    const uintptr_t a = (uintptr_t)p;
+    const uint32_t *w = reinterpret_cast<const uint32_t *>(a & ~(uintptr_t)3);
+    const uint32_t sh = (uint32_t)(a & 3);
+    uint32_t v[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+        v[k] = w[k];
+    uint32_t m = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        m |= byte_eq_mask(__builtin_amdgcn_alignbyte(v[k + 1], v[k], sh), rep) << (4 * k);
+    return m;
+}
+
 // Alg. 3: the frame's marks merged into the local grid.  One lane per 16
-// voxels of a grid row of the row box: occupied bit -> occupied; else a
-// traced stamp -> unknown; else a free stamp -> free; else unchanged.
+// buffer columns of the buffer row that holds a grid row of the row box:
+// occupied bit -> occupied; else a traced stamp -> unknown; else a free stamp
+// -> free; else unchanged.  The frame's planes are read at the grid columns
+// the 16 buffer columns hold (one run, or two where the ring wraps).
 __device__ __forceinline__ void resolve_body(const Planes &pl, uint8_t *loc, const RowBox &rows,
-                                             int64_t gid)
+                                             const int32_t ring[3], int64_t gid)
 {
     const int32_t ny = rows.y1 - rows.y0 + 1, nz = rows.z1 - rows.z0 + 1;
-    const int32_t chunks = pl.wx * 2;   // 16-voxel chunks per row
+    const int32_t chunks = pl.wx * 2;   // 16-column chunks per row
     if (ny <= 0 || nz <= 0 || gid >= (int64_t)chunks * ny * nz)
         return;
     const int32_t k = (int32_t)(gid % chunks);
     const int64_t row = gid / chunks;
     const int32_t y = rows.y0 + (int32_t)(row % ny);
     const int32_t z = rows.z0 + (int32_t)(row / ny);
-    const int64_t base = 32 * (int64_t)pl.wx * (y + (int64_t)pl.n[1] * z) + 16 * k;
-    const uint32_t occ16 = (pl.occ[base >> 5] >> (base & 16)) & 0xFFFFu;
-    const uint4 fr = *reinterpret_cast<const uint4 *>(pl.marks + base);
-    const uint4 tr = *reinterpret_cast<const uint4 *>(pl.marks + pl.nbytes + base);
+    const int32_t gx = pl.n[0];
+    const int32_t c0 = 16 * k;               // buffer column of the chunk
+    if (c0 >= gx)
+        return;                              // row padding only
+    const int32_t nvalid = min(16, gx - c0);
+    const int32_t by = wrap_add(y, ring[1], pl.n[1]), bz = wrap_add(z, ring[2], pl.n[2]);
+    const int64_t prow = 32 * (int64_t)pl.wx * (y + (int64_t)pl.n[1] * z);    // planes
+    const int64_t brow = 32 * (int64_t)pl.wx * (by + (int64_t)pl.n[1] * bz);  // buffer
+    int32_t x0 = c0 - ring[0];               // grid column of buffer column c0
+    if (x0 < 0)
+        x0 += gx;
     const uint32_t rep = (pl.epoch & 0xFFu) * 0x01010101u;
-    const uint32_t tr16 = byte_eq_mask(tr.x, rep) | (byte_eq_mask(tr.y, rep) << 4) |
-                          (byte_eq_mask(tr.z, rep) << 8) | (byte_eq_mask(tr.w, rep) << 12);
-    const uint32_t fr16 = byte_eq_mask(fr.x, rep) | (byte_eq_mask(fr.y, rep) << 4) |
-                          (byte_eq_mask(fr.z, rep) << 8) | (byte_eq_mask(fr.w, rep) << 12);
+    uint32_t occ16, tr16, fr16;
+    if ((x0 & 15) == 0 && x0 + nvalid <= gx) {
+        // one run of grid columns starting on a 16-column boundary
+        const int64_t b = prow + x0;
+        occ16 = (pl.occ[b >> 5] >> (b & 16)) & 0xFFFFu;
+        const uint4 fr = *reinterpret_cast<const uint4 *>(pl.marks + b);
+        const uint4 tr = *reinterpret_cast<const uint4 *>(pl.marks + pl.nbytes + b);
+        tr16 = byte_eq_mask(tr.x, rep) | (byte_eq_mask(tr.y, rep) << 4) |
+               (byte_eq_mask(tr.z, rep) << 8) | (byte_eq_mask(tr.w, rep) << 12);
+        fr16 = byte_eq_mask(fr.x, rep) | (byte_eq_mask(fr.y, rep) << 4) |
+               (byte_eq_mask(fr.z, rep) << 8) | (byte_eq_mask(fr.w, rep) << 12);
+    } else if (x0 + nvalid <= gx) {
+        const int64_t b = prow + x0;
+        const uint64_t two = (uint64_t)pl.occ[b >> 5] | ((uint64_t)pl.occ[(b >> 5) + 1] << 32);
+        occ16 = (uint32_t)(two >> (b & 31)) & 0xFFFFu;
+        fr16 = stamp_mask16(pl.marks + b, rep);
+        tr16 = stamp_mask16(pl.marks + pl.nbytes + b, rep);
+    } else {
+        occ16 = tr16 = fr16 = 0;
+        const uint8_t e = (uint8_t)pl.epoch;
+        for (int j = 0; j < nvalid; ++j) {
+            int32_t x = x0 + j;
+            if (x >= gx)
+                x -= gx;
+            const int64_t b = prow + x;
+            occ16 |= ((pl.occ[b >> 5] >> (b & 31)) & 1u) << j;
+            tr16 |= (uint32_t)(pl.marks[pl.nbytes + b] == e) << j;
+            fr16 |= (uint32_t)(pl.marks[b] == e) << j;
+        }
+    }
+    const uint32_t valid = nvalid >= 16 ? 0xFFFFu : (1u << nvalid) - 1u;
+    occ16 &= valid;
+    tr16 &= valid;
+    fr16 &= valid;
     if ((occ16 | tr16 | fr16) == 0)
         return;
-    uint4 v = *reinterpret_cast<const uint4 *>(loc + base);
+    uint8_t *dst = loc + brow + c0;
+    uint4 v = *reinterpret_cast<const uint4 *>(dst);
     uint32_t *vw = reinterpret_cast<uint32_t *>(&v);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -314,50 +381,41 @@ __device__ __forceinline__ void resolve_body(const Planes &pl, uint8_t *loc, con
         fm &= ~(om | tm);
         vw[j] = (vw[j] & ~(om | tm | fm)) | (0x02020202u & om) | (0x01010101u & fm);
     }
-    *reinterpret_cast<uint4 *>(loc + base) = v;
+    *reinterpret_cast<uint4 *>(dst) = v;
 }
 
-// Sec. IV-E: dst[x,y,z] = src[x+dx, y+dy, z+dz] inside, else unknown.  One
-// lane per 16 voxels of a device-layout row, consecutive lanes along the row
-// and then on to the next rows (padding bytes become unknown).  Rows whose
-// source row is outside the grid are cleared without loads; the common case
-// reads five aligned dwords and realigns them with v_alignbyte.
-__device__ __forceinline__ void shift_body(const uint8_t *src, uint8_t *dst, int32_t nx,
-                                           int32_t ny, int32_t nz, int32_t pitch, int32_t dx,
-                                           int32_t dy, int32_t dz, int32_t gid)
+// Sec. IV-E on the ring buffer: one lane per 16 buffer columns of a grid
+// row.  Rows of an exposed y or z slab (every row when the x slab is the
+// whole row) are cleared whole; other rows clear the buffer columns that hold
+// grid columns of the exposed x slab.
+__device__ __forceinline__ void clear_body(const SlabClear &c, int64_t gid)
 {
-    const int32_t cpr = pitch >> 4;   // 16-voxel chunks per row
-    if (gid >= cpr * ny * nz)
+    const int32_t cpr = c.gxp >> 4;
+    if (gid >= (int64_t)cpr * c.n[1] * c.n[2])
         return;
-    const int32_t row = gid / cpr;
-    const int32_t x0 = 16 * (gid - row * cpr);
-    const int32_t y = row % ny, z = row / ny;
-    const int64_t sy = (int64_t)y + dy, sz = (int64_t)z + dz;
-    uint32_t out[4] = {0u, 0u, 0u, 0u};
-    if (sy >= 0 && sy < ny && sz >= 0 && sz < nz) {
-        const uint8_t *srow = src + pitch * (sy + (int64_t)ny * sz);
-        const int64_t s0 = (int64_t)x0 + dx;
-        if (x0 + 16 <= nx && s0 >= 0 && s0 + 16 <= nx && (s0 & ~3ll) + 20 <= pitch) {
-            const uint32_t *w = reinterpret_cast<const uint32_t *>(srow + (s0 & ~3ll));
-            const uint32_t sh = (uint32_t)(s0 & 3);
-            uint32_t v[5];
-#pragma unroll
-            for (int k = 0; k < 5; ++k)
-                v[k] = w[k];
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                out[k] = __builtin_amdgcn_alignbyte(v[k + 1], v[k], sh);
-        } else {
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const int64_t x = (int64_t)x0 + j, sx = x + dx;
-                if (x < nx && sx >= 0 && sx < nx)
-                    out[j >> 2] |= (uint32_t)srow[sx] << (8 * (j & 3));
-            }
-        }
+    const int32_t row = (int32_t)(gid / cpr);
+    const int32_t c0 = 16 * (int32_t)(gid - (int64_t)row * cpr);
+    const int32_t y = row % c.n[1], z = row / c.n[1];
+    const int32_t by = wrap_add(y, c.ring[1], c.n[1]), bz = wrap_add(z, c.ring[2], c.n[2]);
+    uint8_t *dst = c.loc + (int64_t)c.gxp * (by + (int64_t)c.n[1] * bz) + c0;
+    const bool whole = (y >= c.lo[1] && y < c.hi[1]) || (z >= c.lo[2] && z < c.hi[2]) ||
+                       c.hi[0] - c.lo[0] >= c.n[0];
+    if (whole) {
+        *reinterpret_cast<uint4 *>(dst) = make_uint4(0u, 0u, 0u, 0u);
+        return;
     }
-    *reinterpret_cast<uint4 *>(dst + (int64_t)pitch * row + x0) =
-        make_uint4(out[0], out[1], out[2], out[3]);
+    if (c.lo[0] >= c.hi[0])
+        return;
+    for (int j = 0; j < 16; ++j) {
+        const int32_t col = c0 + j;
+        if (col >= c.n[0])
+            break;
+        int32_t x = col - c.ring[0];       // grid column held by buffer column col
+        if (x < 0)
+            x += c.n[0];
+        if (x >= c.lo[0] && x < c.hi[0])
+            dst[j] = kUnknown;
+    }
 }
 
 // ------------------------------------------------------- one-frame kernels
@@ -383,17 +441,16 @@ __global__ __launch_bounds__(kBlock) void k_rays(RayParams p)
     rays_body<kGeneral>(p, blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6));
 }
 
-__global__ __launch_bounds__(kBlock) void k_resolve(Planes pl, uint8_t *loc, RowBox rows)
+__global__ __launch_bounds__(kBlock) void k_resolve(Planes pl, uint8_t *loc, RowBox rows,
+                                                    int32_t rx, int32_t ry, int32_t rz)
 {
-    resolve_body(pl, loc, rows, (int64_t)blockIdx.x * kBlock + threadIdx.x);
+    const int32_t ring[3] = {rx, ry, rz};
+    resolve_body(pl, loc, rows, ring, (int64_t)blockIdx.x * kBlock + threadIdx.x);
 }
 
-__global__ __launch_bounds__(kBlock) void k_shift(const uint8_t *src, uint8_t *dst, int32_t nx,
-                                                  int32_t ny, int32_t nz, int32_t pitch,
-                                                  int32_t dx, int32_t dy, int32_t dz)
+__global__ __launch_bounds__(kBlock) void k_clear(SlabClear c)
 {
-    shift_body(src, dst, nx, ny, nz, pitch, dx, dy, dz,
-               (int32_t)(blockIdx.x * kBlock + threadIdx.x));
+    clear_body(c, (int64_t)blockIdx.x * kBlock + threadIdx.x);
 }
 
 // ----------------------------------------------------------- batch kernels
@@ -423,14 +480,12 @@ __global__ __launch_bounds__(kBlock) void k_upload(UploadBlob b)
         b.dst[i] = b.w[i];
 }
 
-__global__ __launch_bounds__(kBlock) void kb_shift(const FrameDesc *__restrict__ fd,
+__global__ __launch_bounds__(kBlock) void kb_clear(const FrameDesc *__restrict__ fd,
                                                    const int32_t *__restrict__ start, int32_t n)
 {
     int32_t local;
     const FrameDesc &f = fd[frame_of(start, n, blockIdx.x, local)];
-    const Planes &pl = f.sp.pl;
-    shift_body(f.shift_src, f.loc, pl.n[0], pl.n[1], pl.n[2], 32 * pl.wx, f.shift[0], f.shift[1],
-               f.shift[2], local * kBlock + (int32_t)threadIdx.x);
+    clear_body(f.clear, (int64_t)local * kBlock + threadIdx.x);
 }
 
 __global__ __launch_bounds__(kBlock) void kb_seed(const FrameDesc *__restrict__ fd,
@@ -478,7 +533,7 @@ __global__ __launch_bounds__(kBlock) void kb_resolve(const FrameDesc *__restrict
 {
     int32_t local;
     const FrameDesc &f = fd[frame_of(start, n, blockIdx.x, local)];
-    resolve_body(f.sp.pl, f.loc, f.rows, (int64_t)local * kBlock + threadIdx.x);
+    resolve_body(f.sp.pl, f.loc, f.rows, f.ring, (int64_t)local * kBlock + threadIdx.x);
 }
 
 uint32_t blocks_for(int64_t threads) { return (uint32_t)((threads + kBlock - 1) / kBlock); }
@@ -554,25 +609,23 @@ hipError_t launch_rays(const RayParams &p, bool camera_inside, hipStream_t st,
     return hipGetLastError();
 }
 
-hipError_t launch_resolve(const Planes &pl, uint8_t *loc, const RowBox &rows, hipStream_t st,
-                          const StageEvents &ev)
+hipError_t launch_resolve(const Planes &pl, uint8_t *loc, const RowBox &rows,
+                          const int32_t ring[3], hipStream_t st, const StageEvents &ev)
 {
     if (rows.y0 > rows.y1 || rows.z0 > rows.z1)
         return record_empty_stage(ev, st);
     const int32_t ny = rows.y1 - rows.y0 + 1, nz = rows.z1 - rows.z0 + 1;
     int64_t n = (int64_t)pl.wx * 2 * ny * nz;
     hipExtLaunchKernelGGL(k_resolve, dim3(blocks_for(n)), dim3(kBlock), 0, st, ev.start, ev.stop,
-                          0, pl, loc, rows);
+                          0, pl, loc, rows, ring[0], ring[1], ring[2]);
     return hipGetLastError();
 }
 
-hipError_t launch_shift(const uint8_t *src, uint8_t *dst, const int32_t n[3], const int32_t d[3],
-                        hipStream_t st, const StageEvents &ev)
+hipError_t launch_clear(const SlabClear &c, hipStream_t st, const StageEvents &ev)
 {
-    const int32_t pitch = grid_pitch(n[0]);
-    const int64_t lanes = (int64_t)(pitch / 16) * n[1] * n[2];
-    hipExtLaunchKernelGGL(k_shift, dim3(blocks_for(lanes)), dim3(kBlock), 0, st, ev.start, ev.stop,
-                          0, src, dst, n[0], n[1], n[2], pitch, d[0], d[1], d[2]);
+    const int64_t lanes = (int64_t)(c.gxp / 16) * c.n[1] * c.n[2];
+    hipExtLaunchKernelGGL(k_clear, dim3(blocks_for(lanes)), dim3(kBlock), 0, st, ev.start,
+                          ev.stop, 0, c);
     return hipGetLastError();
 }
 
@@ -599,7 +652,7 @@ hipError_t launch_batch_stage(int stage, const FrameDesc *fd, const int32_t *sta
     const dim3 g((uint32_t)blocks), b(kBlock);
     switch (stage) {
     case kBatchShift:
-        hipLaunchKernelGGL(kb_shift, g, b, 0, st, fd, start, n);
+        hipLaunchKernelGGL(kb_clear, g, b, 0, st, fd, start, n);
         break;
     case kBatchSeed:
         hipLaunchKernelGGL(kb_seed, g, b, 0, st, fd, start, n);
@@ -627,6 +680,42 @@ hipError_t copy_grid(uint8_t *dst, int64_t dst_pitch, const uint8_t *src, int64_
 {
     return hipMemcpy2DAsync(dst, (size_t)dst_pitch, src, (size_t)src_pitch, (size_t)n[0],
                             (size_t)n[1] * n[2], kind, st);
+}
+
+hipError_t copy_grid_from_ring(uint8_t *dst, const uint8_t *src, int64_t src_pitch,
+                               const int32_t n[3], const int32_t ring[3], hipMemcpyKind kind,
+                               hipStream_t st)
+{
+    // along each axis, grid coordinates [0, n - r) sit at buffer r.., and
+    // [n - r, n) at buffer 0..
+    for (int iz = 0; iz < 2; ++iz)
+        for (int iy = 0; iy < 2; ++iy)
+            for (int ix = 0; ix < 2; ++ix) {
+                const int idx[3] = {ix, iy, iz};
+                size_t g0[3], b0[3], len[3];
+                bool empty = false;
+                for (int a = 0; a < 3; ++a) {
+                    const int32_t r = ring[a];
+                    g0[a] = idx[a] ? (size_t)(n[a] - r) : 0;
+                    b0[a] = idx[a] ? 0 : (size_t)r;
+                    len[a] = idx[a] ? (size_t)r : (size_t)(n[a] - r);
+                    empty = empty || len[a] == 0;
+                }
+                if (empty)
+                    continue;
+                hipMemcpy3DParms p = {};
+                p.srcPtr = make_hipPitchedPtr(const_cast<uint8_t *>(src), (size_t)src_pitch,
+                                              (size_t)n[0], (size_t)n[1]);
+                p.srcPos = make_hipPos(b0[0], b0[1], b0[2]);
+                p.dstPtr = make_hipPitchedPtr(dst, (size_t)n[0], (size_t)n[0], (size_t)n[1]);
+                p.dstPos = make_hipPos(g0[0], g0[1], g0[2]);
+                p.extent = make_hipExtent(len[0], len[1], len[2]);
+                p.kind = kind;
+                hipError_t e = hipMemcpy3DAsync(&p, st);
+                if (e != hipSuccess)
+                    return e;
+            }
+    return hipSuccess;
 }
 
 }  // namespace vg

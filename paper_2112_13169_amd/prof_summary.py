@@ -92,30 +92,35 @@ def calibration(rows, cal_bytes):
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--kt", required=True)
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
+    ap.add_argument("--fetch", help="FETCH_SIZE run (optional: no counter columns)")
+    ap.add_argument("--write", help="WRITE_SIZE run")
     ap.add_argument("--workload", required=True)
     ap.add_argument("--cal-bytes", type=int, required=True)
     ap.add_argument("--command", required=True, help="the profiled command, for the record")
     ap.add_argument("--md", required=True)
-    ap.add_argument("--json", required=True)
+    ap.add_argument("--json", help="traffic summary to write (needs both counter runs)")
     a = ap.parse_args(argv)
 
     stats = read_stats(a.kt)
-    fetch, frows = read_counter(a.fetch, "FETCH_SIZE")
-    write, wrows = read_counter(a.write, "WRITE_SIZE")
-    f_fac, f_cal = calibration(frows, a.cal_bytes)
-    w_fac, w_cal = calibration(wrows, a.cal_bytes)
+    counters = bool(a.fetch and a.write)
+    fetch, write = {}, {}
+    f_fac = w_fac = f_cal = w_cal = None
+    if counters:
+        fetch, frows = read_counter(a.fetch, "FETCH_SIZE")
+        write, wrows = read_counter(a.write, "WRITE_SIZE")
+        f_fac, f_cal = calibration(frows, a.cal_bytes)
+        w_fac, w_cal = calibration(wrows, a.cal_bytes)
 
     kernels = {}
     lines = [f"# Kernel durations and memory-side bytes: {a.workload}", "",
              "Commands (one MI355X; REPO is the repository root):", "", "```"]
     lines += a.command.strip().splitlines()
-    lines += ["```", "",
-              f"Calibration: a {a.cal_bytes} B device copy read FETCH_SIZE {f_cal:.1f} KiB and "
-              f"WRITE_SIZE {w_cal:.1f} KiB, so bytes = FETCH_SIZE x {f_fac:.4f} KiB + "
-              f"WRITE_SIZE x {w_fac:.4f} KiB.", "",
-              f"Kernel sources hash: `{kernel_source_hash()}`", "",
+    lines += ["```", ""]
+    if counters:
+        lines += [f"Calibration: a {a.cal_bytes} B device copy read FETCH_SIZE {f_cal:.1f} KiB "
+                  f"and WRITE_SIZE {w_cal:.1f} KiB, so bytes = FETCH_SIZE x {f_fac:.4f} KiB + "
+                  f"WRITE_SIZE x {w_fac:.4f} KiB.", ""]
+    lines += [f"Kernel sources hash: `{kernel_source_hash()}`", "",
               "| kernel | launches | avg us | min us | max us | % time | FETCH KiB | WRITE KiB "
               "| bytes/launch (calibrated) |",
               "|---|---|---|---|---|---|---|---|---|"]
@@ -137,11 +142,12 @@ def main(argv=None):
     lines.append("")
     with open(a.md, "w") as fh:
         fh.write("\n".join(lines))
-    with open(a.json, "w") as fh:
-        json.dump(dict(workload=a.workload, source_hash=kernel_source_hash(),
-                       fetch_factor=round(f_fac, 4), write_factor=round(w_fac, 4),
-                       kernels=kernels), fh, indent=1)
-        fh.write("\n")
+    if counters and a.json:
+        with open(a.json, "w") as fh:
+            json.dump(dict(workload=a.workload, source_hash=kernel_source_hash(),
+                           fetch_factor=round(f_fac, 4), write_factor=round(w_fac, 4),
+                           kernels=kernels), fh, indent=1)
+            fh.write("\n")
     print("\n".join(lines))
 
 

@@ -1,6 +1,6 @@
 """Serving loop: depth frames from many robots, integrated as they arrive.
 
-Each robot owns a resident local grid (its loc buffers and scratch) that is
+Each robot owns a resident local grid (its ring buffer and scratch) that is
 re-centred on the robot before every frame (Sec. IV-E) and integrated with the
 frame (Sec. IV-B..D).  The server batches continuously: whenever a stream is
 free it forms a batch from the frames that have arrived and can be admitted
@@ -272,7 +272,7 @@ class GpuBackend:
         return self.vg.vg_batch_workspace_bytes(max_batch)
 
     def grid_bytes(self, dims, vox_inf):
-        return 2 * self.vg.vg_grid_bytes(*dims) + self.vg.vg_scratch_bytes(*dims, vox_inf)
+        return self.vg.vg_grid_bytes(*dims) + self.vg.vg_scratch_bytes(*dims, vox_inf)
 
     def _event(self):
         ev = self.torch.cuda.Event()

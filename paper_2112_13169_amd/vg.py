@@ -167,24 +167,29 @@ def vg_scratch_bytes(gx, gy, gz, vox_inf):
     return int(lib().vg_scratch_bytes(gx, gy, gz, vox_inf))
 
 
+def _opt_ptr(t):
+    return None if t is None else _ptr(t)
+
+
 def vg_create_grid(dims, vox_size, origin_w, vox_inf, loc, spare, scratch, stream=None):
-    """dims = (gx, gy, gz); loc / spare: uint8 device tensors of
-    vg_grid_bytes(gx, gy, gz) elements; scratch: uint8 device tensor of
+    """dims = (gx, gy, gz); loc: uint8 device tensor of vg_grid_bytes(gx, gy,
+    gz) elements; spare: unused (None); scratch: uint8 device tensor of
     vg_scratch_bytes(gx, gy, gz, vox_inf) elements (256-byte aligned)."""
     gx, gy, gz = (int(v) for v in dims)
     org = (ctypes.c_float * 3)(*[float(v) for v in np.asarray(origin_w, np.float32)])
     h = ctypes.c_void_p()
-    nb = min(loc.numel(), spare.numel())
-    _check(lib().vg_create_grid(gx, gy, gz, vox_size, org, int(vox_inf), _ptr(loc), _ptr(spare),
-                                nb, _ptr(scratch), scratch.numel() * scratch.element_size(),
-                                _stream(stream), ctypes.byref(h)), "vg_create_grid")
+    nb = loc.numel() if spare is None else min(loc.numel(), spare.numel())
+    _check(lib().vg_create_grid(gx, gy, gz, vox_size, org, int(vox_inf), _ptr(loc),
+                                _opt_ptr(spare), nb, _ptr(scratch),
+                                scratch.numel() * scratch.element_size(), _stream(stream),
+                                ctypes.byref(h)), "vg_create_grid")
     return h
 
 
 def vg_rebind_grid(g, loc, spare, scratch, stream=None):
     """Bind new device buffers (as for vg_create_grid) to an existing grid."""
-    nb = min(loc.numel(), spare.numel())
-    _check(lib().vg_rebind_grid(g, _ptr(loc), _ptr(spare), nb, _ptr(scratch),
+    nb = loc.numel() if spare is None else min(loc.numel(), spare.numel())
+    _check(lib().vg_rebind_grid(g, _ptr(loc), _opt_ptr(spare), nb, _ptr(scratch),
                                 scratch.numel() * scratch.element_size(), _stream(stream)),
            "vg_rebind_grid")
 
@@ -326,7 +331,8 @@ def vg_destroy_grid(g):
 
 class GridBuffers:
     """Device buffers one grid needs, allocated with torch (the library itself
-    never allocates): loc, spare and scratch sized for the grid and vox_inf."""
+    never allocates): the grid's ring buffer `loc` and its scratch, sized for
+    the grid and vox_inf (`spare` is None: shifts work in place)."""
 
     def __init__(self, dims, vox_inf, device="cuda"):
         import torch
@@ -337,6 +343,6 @@ class GridBuffers:
             raise ValueError("invalid grid size")
         self.dims = tuple(dims)
         self.loc = torch.empty(n, dtype=torch.uint8, device=device)
-        self.spare = torch.empty(n, dtype=torch.uint8, device=device)
+        self.spare = None
         self.scratch = torch.empty(nbytes, dtype=torch.uint8, device=device)
         assert self.scratch.data_ptr() % 256 == 0

@@ -372,3 +372,30 @@ def test_profile_events_time_stages_without_changing_results():
             ms = events[E * k + 2 * j].elapsed_time(events[E * k + 2 * j + 1])
             assert 0.0 <= ms < 1000.0, (k, name, ms)
     g.close()
+
+
+def test_ring_buffer_wraps_and_resolves_across_the_seam():
+    """Many small shifts whose ring offsets wrap round the grid several times,
+    with frames integrated in between (the merge writes across the ring's
+    seam), reads to device and to host memory, and a checkpoint written back
+    (the ring restarts at 0) -- all against the oracle."""
+    fr = scenes.make_frame("plain-small", 18, size=(64, 48), dims=(45, 38, 21))
+    g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf)
+    rng = np.random.default_rng(31)
+    for k in range(24):
+        d = tuple(int(v) for v in rng.integers(-9, 10, 3))
+        _say(f"ring step {k} shift {d}")
+        g.shift(d)
+        fr.t = (g.origin() + np.asarray(fr.dims, np.float32) * g.vox_size *
+                rng.uniform(0.3, 0.7, 3).astype(np.float32)).astype(np.float32)
+        g.integrate(fr)
+        g.check(f"ring step {k}")
+        if k % 6 == 5:
+            host = torch.empty(g.ref.size, dtype=torch.uint8, pin_memory=True)
+            vg.vg_read_grid(g.h, host)
+            torch.cuda.synchronize()
+            assert np.array_equal(host.numpy().reshape(g.ref.shape), g.ref), f"host read {k}"
+        if k == 11:
+            g.write(g.ref)          # checkpoint round trip: the ring restarts at 0
+            g.check("after write")
+    g.close()

@@ -96,7 +96,7 @@ def test_create_grid_argument_errors_leave_no_handle():
     for kw in [dict(gx=0), dict(gz=-1), dict(gx=2048, gy=2048, gz=1024), dict(s=0.0),
                dict(s=float("nan")), dict(r=-1), dict(r=17), dict(gy=70000),
                dict(origin=(ctypes.c_float * 3)(0, float("inf"), 0)), dict(a=P(0)),
-               dict(b=fake_a), dict(scr=P(0x300010)), dict(a=P(0x100004))]:
+               dict(scr=P(0)), dict(scr=P(0x300010)), dict(a=P(0x100004))]:
         st, h = create(**kw)
         assert st == vg.VG_ERR_ARG and h is None, kw
     for kw in [dict(nbytes=100), dict(nb=gb - 1)]:
