@@ -273,7 +273,8 @@ def run_large(seqs, torch, vg, passes=3):
     return out
 
 
-def run_batched(frames, K, warmup, torch, vg, oracle, autotune, sample_oracle=()):
+def run_batched(frames, K, warmup, torch, vg, oracle, autotune, sample_oracle=(),
+                walk_steps=None):
     """Batched vs plain on the same frames, each frame with its own grid: one
     vg_integrate_batch call per step against len(frames) vg_integrate_frame
     calls per step.  Returns the figures of both and whether they agree."""
@@ -346,13 +347,27 @@ def run_batched(frames, K, warmup, torch, vg, oracle, autotune, sample_oracle=()
 
     wb, lb = timed(batch_step)
     wp, lp = timed(plain_step)
+
+    # the batched walk kernel's live time: events its own launches record
+    S = len(vg.BATCH_STAGES)
+    j = vg.BATCH_STAGES.index("rays")
+    stage_ev = []
+    for _ in range(K):
+        row = [None] * (2 * S)
+        row[2 * j], row[2 * j + 1] = (torch.cuda.Event(enable_timing=True),
+                                      torch.cuda.Event(enable_timing=True))
+        stage_ev.append(row)
+    for row in stage_ev:
+        vg.vg_integrate_batch_timed(descs, ws, row)
+    torch.cuda.synchronize()
+    rays_ms = float(np.mean([row[2 * j].elapsed_time(row[2 * j + 1]) for row in stage_ev]))
     for (_, h) in A + B:
         vg.vg_destroy_grid(h)
     tiles = {"x".join(str(v) for v in c): {"best": f"{1 << b}x{64 >> b}",
                                            "rays_ms": {f"{1 << w}x{64 >> w}": round(ms, 4)
                                                        for w, ms in t.items()}}
              for c, (b, t) in table.items()}
-    return {
+    result = {
         "frames_per_step": n, "steps": K,
         "batched_frames_per_s": round(n * K / wb, 1),
         "plain_frames_per_s": round(n * K / wp, 1),
@@ -366,7 +381,18 @@ def run_batched(frames, K, warmup, torch, vg, oracle, autotune, sample_oracle=()
         "bit_exact": same,
         "oracle_sampled_frames": list(sample_oracle),
         "ray_tiles": tiles,
+        "kb_rays_ms": round(rays_ms, 5),
     }
+    if walk_steps is not None:
+        units = float(np.sum(walk_steps))
+        achieved = units * OPS_PER_STEP / (rays_ms * 1e-3) / 1e12
+        result["roofline"] = {"bound": "alu", "achieved": round(achieved, 3),
+                              "peak": round(ALU_PEAK_TOPS, 1), "unit": "TOP/s",
+                              "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None,
+                              "kernel": "kb_rays", "units_per_launch": units,
+                              "unit_kind": "in-grid walk steps", "ops_per_unit": OPS_PER_STEP,
+                              "kernel_ms": round(rays_ms, 5)}
+    return result
 
 
 def main():
@@ -647,10 +673,18 @@ def main():
     }
     if args.batch > 0:
         t0 = time.time()
+        x16 = frames[:16]
+        walk16 = []
+        for f in x16:       # in-grid walk steps do not depend on the grid's content
+            _, st = oracle.integrate_pinhole(np.zeros(f.dims[::-1], np.uint8), f.origin,
+                                             f.vox_size, f.vox_inf, f.depth, f.intr, f.R, f.t,
+                                             want_ms=False)
+            walk16.append(st["steps"])
         out["batched"] = {
             "plain-medium x16": dict(
                 workload="16 plain-medium frames per step, each into its own 200x200x100 grid",
-                **run_batched(frames[:16], args.batch_steps * 4, 3, torch, vg, oracle, autotune)),
+                **run_batched(x16, args.batch_steps * 4, 3, torch, vg, oracle, autotune,
+                              walk_steps=walk16)),
             "batch-recipe": dict(
                 workload=f"{len(recipe)} independent frames per step: 320x240..1280x720, range "
                          "to U[4,10] m, random 6-DoF poses, own grids of gx=gy in 100..256, gz "

@@ -218,6 +218,15 @@ size_t vg_batch_workspace_bytes(int32_t max_frames);
 vg_status vg_integrate_batch(const vg_frame *frames, int32_t n_frames, void *workspace,
                              size_t workspace_bytes, void *stream);
 
+/* vg_integrate_batch with a measurement hook: events (hipEvent_t, NULL
+ * entries skipped) holds 12 entries, the (start, stop) pair of each batch
+ * stage in launch order -- shift, seed, dilation x, dilation yz, ray walk,
+ * merge.  A stage's start event takes the start time of its first launch and
+ * its stop event the end time of its last (recorded by the launches; a stage
+ * that launches nothing records markers).  events NULL: vg_integrate_batch. */
+vg_status vg_integrate_batch_timed(const vg_frame *frames, int32_t n_frames, void *workspace,
+                                   size_t workspace_bytes, void *const *events, void *stream);
+
 /* Shape of the ray bundle one wavefront walks: tiles of (1 << log2_width)
  * fan targets along the fan's width (pinhole columns, or ring columns of a
  * spinning fan) by (64 >> log2_width) along its height; log2_width in

@@ -889,6 +889,12 @@ size_t vg_batch_workspace_bytes(int32_t max_frames)
 vg_status vg_integrate_batch(const vg_frame *frames, int32_t n_frames, void *workspace,
                              size_t workspace_bytes, void *stream)
 {
+    return vg_integrate_batch_timed(frames, n_frames, workspace, workspace_bytes, nullptr, stream);
+}
+
+vg_status vg_integrate_batch_timed(const vg_frame *frames, int32_t n_frames, void *workspace,
+                                   size_t workspace_bytes, void *const *events, void *stream)
+{
     if (n_frames < 0 || n_frames > kMaxBatch || (n_frames > 0 && !frames))
         return VG_ERR_ARG;
     if (n_frames == 0)
@@ -1030,8 +1036,14 @@ vg_status vg_integrate_batch(const vg_frame *frames, int32_t n_frames, void *wor
         const int32_t *start = reinterpret_cast<const int32_t *>(ws + table_at[(size_t)r]);
         const FrameDesc *fd =
             reinterpret_cast<const FrameDesc *>(ws + table_at[(size_t)r] + batch_starts_bytes(m));
-        for (int s = 0; s < kBatchStages && e == hipSuccess; ++s)
-            e = launch_batch_stage(s, fd, start + s * (m + 1), m, totals[(size_t)r][s], st);
+        for (int s = 0; s < kBatchStages && e == hipSuccess; ++s) {
+            StageEvents ev;
+            if (events) {   // stage s: start of its first launch, end of its last
+                ev.start = r == 0 ? static_cast<hipEvent_t>(events[2 * s]) : nullptr;
+                ev.stop = r == rounds - 1 ? static_cast<hipEvent_t>(events[2 * s + 1]) : nullptr;
+            }
+            e = launch_batch_stage(s, fd, start + s * (m + 1), m, totals[(size_t)r][s], st, ev);
+        }
     }
     if (e != hipSuccess)
         return VG_ERR_HIP;

@@ -161,7 +161,7 @@ hipError_t launch_upload(uint32_t *dst, const uint32_t *src, size_t words, hipSt
 // Batch: one launch of stage `stage` (kBatch*) over the n frames of a round;
 // fd and start (n + 1 block prefixes) live in device memory; blocks = start[n].
 hipError_t launch_batch_stage(int stage, const FrameDesc *fd, const int32_t *start, int32_t n,
-                              int32_t blocks, hipStream_t st);
+                              int32_t blocks, hipStream_t st, const StageEvents &ev = {});
 // Linear (pitch gx) <-> device layout (pitch gxp) copies of a whole grid.
 hipError_t copy_grid(uint8_t *dst, int64_t dst_pitch, const uint8_t *src, int64_t src_pitch,
                      const int32_t n[3], hipMemcpyKind kind, hipStream_t st);

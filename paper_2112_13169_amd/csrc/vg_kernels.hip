@@ -645,29 +645,29 @@ hipError_t launch_upload(uint32_t *dst, const uint32_t *src, size_t words, hipSt
 }
 
 hipError_t launch_batch_stage(int stage, const FrameDesc *fd, const int32_t *start, int32_t n,
-                              int32_t blocks, hipStream_t st)
+                              int32_t blocks, hipStream_t st, const StageEvents &ev)
 {
     if (blocks <= 0 || n <= 0)
-        return hipSuccess;
+        return record_empty_stage(ev, st);
     const dim3 g((uint32_t)blocks), b(kBlock);
     switch (stage) {
     case kBatchShift:
-        hipLaunchKernelGGL(kb_clear, g, b, 0, st, fd, start, n);
+        hipExtLaunchKernelGGL(kb_clear, g, b, 0, st, ev.start, ev.stop, 0, fd, start, n);
         break;
     case kBatchSeed:
-        hipLaunchKernelGGL(kb_seed, g, b, 0, st, fd, start, n);
+        hipExtLaunchKernelGGL(kb_seed, g, b, 0, st, ev.start, ev.stop, 0, fd, start, n);
         break;
     case kBatchDilateX:
-        hipLaunchKernelGGL(kb_dilate_x, g, b, 0, st, fd, start, n);
+        hipExtLaunchKernelGGL(kb_dilate_x, g, b, 0, st, ev.start, ev.stop, 0, fd, start, n);
         break;
     case kBatchDilateYZ:
-        hipLaunchKernelGGL(kb_dilate_yz, g, b, 0, st, fd, start, n);
+        hipExtLaunchKernelGGL(kb_dilate_yz, g, b, 0, st, ev.start, ev.stop, 0, fd, start, n);
         break;
     case kBatchRays:
-        hipLaunchKernelGGL(kb_rays, g, b, 0, st, fd, start, n);
+        hipExtLaunchKernelGGL(kb_rays, g, b, 0, st, ev.start, ev.stop, 0, fd, start, n);
         break;
     case kBatchResolve:
-        hipLaunchKernelGGL(kb_resolve, g, b, 0, st, fd, start, n);
+        hipExtLaunchKernelGGL(kb_resolve, g, b, 0, st, ev.start, ev.stop, 0, fd, start, n);
         break;
     default:
         return hipErrorInvalidValue;

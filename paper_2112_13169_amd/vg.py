@@ -84,6 +84,8 @@ def lib():
         L.vg_batch_workspace_bytes.argtypes = [i32]
         L.vg_batch_workspace_bytes.restype = ctypes.c_size_t
         L.vg_integrate_batch.argtypes = [ctypes.POINTER(vg_frame), i32, P, ctypes.c_size_t, P]
+        L.vg_integrate_batch_timed.argtypes = [ctypes.POINTER(vg_frame), i32, P, ctypes.c_size_t,
+                                               P, P]
         L.vg_set_ray_tile.argtypes = [P, i32]
         L.vg_rebind_grid.argtypes = [P, P, P, ctypes.c_size_t, P, ctypes.c_size_t, P]
         L.vg_status_str.argtypes = [i32]
@@ -92,7 +94,7 @@ def lib():
                      "vg_integrate_points", "vg_shift_grid", "vg_center_offset",
                      "vg_grid_origin", "vg_read_grid", "vg_write_grid", "vg_destroy_grid",
                      "vg_set_profile_events", "vg_integrate_batch", "vg_set_ray_tile",
-                     "vg_rebind_grid", "vg_center_offset_after"):
+                     "vg_rebind_grid", "vg_center_offset_after", "vg_integrate_batch_timed"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -317,6 +319,28 @@ def vg_integrate_batch(frames, workspace, stream=None):
     _check(lib().vg_integrate_batch(arr, n, _ptr(workspace),
                                     workspace.numel() * workspace.element_size(),
                                     _stream(stream)), "vg_integrate_batch")
+
+
+BATCH_STAGES = ("shift", "seed", "dilate_x", "dilate_yz", "rays", "resolve")
+
+
+def vg_integrate_batch_timed(frames, workspace, events, stream=None):
+    """vg_integrate_batch recording events: 2 * len(BATCH_STAGES) torch
+    events (or None), the (start, stop) pair of each stage in turn."""
+    n = len(frames)
+    assert len(events) == 2 * len(BATCH_STAGES)
+    ev = (ctypes.c_void_p * len(events))()
+    for i, e in enumerate(events):
+        if e is None:
+            ev[i] = None
+            continue
+        if not e.cuda_event:
+            e.record()
+        ev[i] = e.cuda_event
+    arr = (vg_frame * max(n, 1))(*frames)
+    _check(lib().vg_integrate_batch_timed(arr, n, _ptr(workspace),
+                                          workspace.numel() * workspace.element_size(), ev,
+                                          _stream(stream)), "vg_integrate_batch_timed")
 
 
 def vg_set_ray_tile(g, log2_width):

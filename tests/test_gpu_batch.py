@@ -273,3 +273,26 @@ def test_empty_seed_box_after_seeded_frame():
         t.oracle_frame(f)
         t.check(f"depth_min {f.intr['depth_min']}")
     t.close()
+
+
+def test_timed_batch_records_every_stage_and_matches():
+    """vg_integrate_batch_timed: the same grids as the plain batch call, and
+    every stage's event pair completes (a stage with nothing to do -- no frame
+    shifts here -- records markers)."""
+    frs = [scenes.make_frame("plain-small", 70 + i) for i in range(3)]
+    a = [Twin(f.dims, f.vox_size, f.origin, f.vox_inf) for f in frs]
+    b = [Twin(f.dims, f.vox_size, f.origin, f.vox_inf) for f in frs]
+    da = [DevFrame(t, f) for t, f in zip(a, frs)]
+    db = [DevFrame(t, f) for t, f in zip(b, frs)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * len(vg.BATCH_STAGES))]
+    _say("timed batch")
+    vg.vg_integrate_batch([d.desc for d in da], _workspace(3))
+    vg.vg_integrate_batch_timed([d.desc for d in db], _workspace(3), ev)
+    torch.cuda.synchronize()
+    for k, name in enumerate(vg.BATCH_STAGES):
+        ms = ev[2 * k].elapsed_time(ev[2 * k + 1])
+        assert 0.0 <= ms < 1000.0, (name, ms)
+    for ta, tb in zip(a, b):
+        assert np.array_equal(ta.read(), tb.read())
+    for t in a + b:
+        t.close()
