@@ -526,7 +526,17 @@ def main():
     # dispatches record) picks the dominant kernel; a latency pass (start of the
     # shift to end of the resolve pass); then the timed region, where only the
     # dominant kernel's dispatches record events.
+    # ray-bundle shape from the autotuner (one fan class: every frame of the
+    # pool has the same sensor and voxel size), timed on a scratch grid
+    tbuf, th = new_grid()
+    tune_table = autotune.tune(
+        [(sensor, fr0.vox_size, th,
+          lambda: vg.vg_integrate_frame(th, depth_dev[0], sensor, poses[0]))], vg, torch, reps=5)
+    tile = autotune.choose(tune_table, sensor, fr0.vox_size, vg)
+    vg.vg_destroy_grid(th)
+    del tbuf
     buf, h = new_grid()
+    vg.vg_set_ray_tile(h, tile)
     for k in range(args.warmup):
         step(h, k)
     K = args.steps
@@ -659,6 +669,7 @@ def main():
                         "shift + integrate",
             "rays": rays, "vox_depth": vd, "fan": f"{2 * hw + 1}x{2 * hh + 1}",
             "frame_pool": len(frames), "path": "plain (one frame per call)",
+            "ray_tile": f"{1 << tile}x{64 >> tile} (autotuned)",
         },
         "voxel_updates_per_s": round(float(upd.mean()) * fps, 1),
         "voxel_updates_per_frame": round(float(upd.mean()), 1),
