@@ -561,7 +561,8 @@ size_t batch_table_bytes(int32_t m)
 }
 
 // Blocks of 256 lanes each batch stage launches for a planned frame.
-void batch_blocks(const vg_grid *g, const FramePlan &p, bool moved, int64_t blocks[kBatchStages])
+void batch_blocks(const vg_grid *g, const FramePlan &p, bool moved, int tile_w,
+                  int64_t blocks[kBatchStages])
 {
     auto per = [](int64_t lanes) { return (lanes + 255) / 256; };
     const Planes &pl = p.sp.pl;
@@ -576,7 +577,8 @@ void batch_blocks(const vg_grid *g, const FramePlan &p, bool moved, int64_t bloc
     const bool any = pl.lo[0] <= pl.hi[0] && pl.lo[1] <= pl.hi[1] && pl.lo[2] <= pl.hi[2];
     blocks[kBatchDilateX] =
         any ? per(wx * (pl.hi[1] - pl.lo[1] + 1) * (int64_t)(pl.hi[2] - pl.lo[2] + 1)) : 0;
-    blocks[kBatchDilateYZ] = per(wx * g->n[1] * (int64_t)g->n[2]);
+    blocks[kBatchDilateYZ] =
+        tile_w > 0 ? dilate_tiles(pl, tile_w) : per(wx * g->n[1] * (int64_t)g->n[2]);
     blocks[kBatchRays] = ((int64_t)p.rp.tiles + 3) / 4;
     const RowBox &b = p.rows;
     blocks[kBatchResolve] = (b.y0 <= b.y1 && b.z0 <= b.z1)
@@ -986,9 +988,26 @@ vg_status vg_integrate_batch_timed(const vg_frame *frames, int32_t n_frames, voi
         return VG_ERR_BUDGET;
     std::vector<uint32_t> host(used / 4, 0u);
     std::vector<std::array<int32_t, kBatchStages>> totals((size_t)rounds);
+    // tiled y/z dilation per round: the widest slot any frame needs, if every
+    // frame of the round can use tiles (0: the untiled kernel)
+    std::vector<int> round_tile((size_t)rounds, 0);
+    std::vector<size_t> round_lds((size_t)rounds, 0);
     for (int32_t r = 0; r < rounds; ++r) {
         const std::vector<int32_t> &mem = members[(size_t)r];
         const int32_t m = (int32_t)mem.size();
+        int tw = 8;
+        for (int32_t i : mem) {
+            const int k = dilate_tile_width(plans[(size_t)i].sp.pl);
+            tw = k == 0 ? 0 : (tw == 0 ? 0 : std::max(tw, k));
+        }
+        size_t lds = 0;
+        for (int32_t i : mem)
+            if (tw > 0)
+                lds = std::max(lds, dilate_tile_lds(plans[(size_t)i].sp.pl, tw));
+        if (lds > kMaxTileLds)
+            tw = 0;
+        round_tile[(size_t)r] = tw;
+        round_lds[(size_t)r] = tw > 0 ? lds : 0;
         uint8_t *base = reinterpret_cast<uint8_t *>(host.data()) + table_at[(size_t)r];
         int32_t *start = reinterpret_cast<int32_t *>(base);
         FrameDesc *fd = reinterpret_cast<FrameDesc *>(base + batch_starts_bytes(m));
@@ -998,7 +1017,7 @@ vg_status vg_integrate_batch_timed(const vg_frame *frames, int32_t n_frames, voi
             const FramePlan &p = plans[(size_t)i];
             const vg_grid *g = grids[(size_t)grid_of[i]];
             int64_t blocks[kBatchStages];
-            batch_blocks(g, p, moved_of[i] != 0, blocks);
+            batch_blocks(g, p, moved_of[i] != 0, round_tile[(size_t)r], blocks);
             FrameDesc d;
             std::memset(&d, 0, sizeof d);
             d.sp = p.sp;
@@ -1042,7 +1061,9 @@ vg_status vg_integrate_batch_timed(const vg_frame *frames, int32_t n_frames, voi
                 ev.start = r == 0 ? static_cast<hipEvent_t>(events[2 * s]) : nullptr;
                 ev.stop = r == rounds - 1 ? static_cast<hipEvent_t>(events[2 * s + 1]) : nullptr;
             }
-            e = launch_batch_stage(s, fd, start + s * (m + 1), m, totals[(size_t)r][s], st, ev);
+            const bool yz = s == kBatchDilateYZ;
+            e = launch_batch_stage(s, fd, start + s * (m + 1), m, totals[(size_t)r][s], st, ev,
+                                   yz ? round_tile[(size_t)r] : 0, yz ? round_lds[(size_t)r] : 0);
         }
     }
     if (e != hipSuccess)

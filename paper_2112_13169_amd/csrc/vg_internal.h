@@ -120,6 +120,39 @@ struct FrameDesc {
     int32_t seed_bx;            // image seed blocks along x (points: 0)
 };
 
+// The y/z dilation runs on tiles staged through LDS when a row's words fit a
+// fixed slot width kW (8 or 16 words, so rows up to 256 / 512 voxels): a block
+// of kBlock threads is kW word lanes by kBlock / kW row slots, and a tile is
+// kBlock / kW output rows along y by kTileZ along z.  0: untiled.
+constexpr int kTileZ = 2;
+constexpr int kTileLoads = 16;   // input words per thread: iz * iy * kW <= 16 * 256
+constexpr size_t kMaxTileLds = 48 * 1024;
+
+inline int dilate_tile_width(const Planes &pl)
+{
+    const int kw = pl.wx <= 8 ? 8 : (pl.wx <= 16 ? 16 : 0);
+    if (kw == 0)
+        return 0;
+    const size_t ty = 256 / kw, iz = (size_t)kTileZ + 2 * pl.r, iy = ty + 2 * pl.r;
+    if (iz * iy * kw > (size_t)kTileLoads * 256)
+        return 0;
+    return 4 * (size_t)kw * (iz * iy + iz * ty) <= kMaxTileLds ? kw : 0;
+}
+
+// LDS bytes of one tile of slot width kw: its padded input rows plus the
+// rows dilated along y.
+inline size_t dilate_tile_lds(const Planes &pl, int kw)
+{
+    const size_t ty = 256 / kw, iz = (size_t)kTileZ + 2 * pl.r, iy = ty + 2 * pl.r;
+    return 4 * (size_t)kw * (iz * iy + iz * ty);
+}
+
+inline int64_t dilate_tiles(const Planes &pl, int kw)
+{
+    const int ty = 256 / kw;
+    return (int64_t)((pl.n[1] + ty - 1) / ty) * ((pl.n[2] + kTileZ - 1) / kTileZ);
+}
+
 // Batch stages, in launch order within a round.
 enum { kBatchShift, kBatchSeed, kBatchDilateX, kBatchDilateYZ, kBatchRays, kBatchResolve,
        kBatchStages };
@@ -160,8 +193,12 @@ hipError_t record_empty_stage(const StageEvents &ev, hipStream_t st);
 hipError_t launch_upload(uint32_t *dst, const uint32_t *src, size_t words, hipStream_t st);
 // Batch: one launch of stage `stage` (kBatch*) over the n frames of a round;
 // fd and start (n + 1 block prefixes) live in device memory; blocks = start[n].
+// tile_w > 0 (kBatchDilateYZ only): the tiled y/z dilation of that slot width
+// with `lds` bytes of LDS per block; the block prefixes then count
+// dilate_tiles(pl, tile_w) per frame.
 hipError_t launch_batch_stage(int stage, const FrameDesc *fd, const int32_t *start, int32_t n,
-                              int32_t blocks, hipStream_t st, const StageEvents &ev = {});
+                              int32_t blocks, hipStream_t st, const StageEvents &ev = {},
+                              int tile_w = 0, size_t lds = 0);
 // Linear (pitch gx) <-> device layout (pitch gxp) copies of a whole grid.
 hipError_t copy_grid(uint8_t *dst, int64_t dst_pitch, const uint8_t *src, int64_t src_pitch,
                      const int32_t n[3], hipMemcpyKind kind, hipStream_t st);

@@ -255,6 +255,67 @@ __device__ __forceinline__ void dilate_yz_body(const Planes &pl, int64_t gid)
     pl.occ[gid] = out;
 }
 
+// The same dilation for one tile (tile_y, tile_z) of kBlock / kW rows along y
+// by kTileZ along z.  Thread = (word lane w, row slot); the padded rows the
+// tile reads are loaded once into LDS (rows outside the seed box as 0), ORed
+// along y into a second LDS buffer, then along z.  No divisions: rows are
+// walked by slot, words by lane.
+template <int kW>
+__device__ __forceinline__ void dilate_yz_tile_body(const Planes &pl, int32_t tile_y,
+                                                    int32_t tile_z, uint32_t *lds)
+{
+    constexpr int32_t kTY = kBlock / kW;
+    const int32_t w = (int32_t)threadIdx.x % kW, slot = (int32_t)threadIdx.x / kW;
+    const int32_t r2 = 2 * pl.r, wx = pl.wx;
+    const int32_t iy = kTY + r2, iz = kTileZ + r2;
+    const int32_t y0 = tile_y * kTY, z0 = tile_z * kTileZ;   // first output row = padded row
+    uint32_t *in = lds;                   // [iz][iy][kW]
+    uint32_t *yd = lds + iz * iy * kW;    // [iz][kTY][kW]
+    const bool any = pl.lo[0] <= pl.hi[0];
+    const bool lane = w < wx;
+    // all loads of a thread first (at most kTileLoads, unrolled), so that they
+    // are in flight together; then the LDS stores
+    const int32_t total = iz * iy * kW;
+    uint32_t ld[kTileLoads];
+#pragma unroll
+    for (int it = 0; it < kTileLoads; ++it) {
+        const int32_t t = it * kBlock + (int32_t)threadIdx.x;
+        ld[it] = 0;
+        const int32_t row = t / kW;
+        const int32_t zz = row / iy, yy = row - zz * iy;
+        const int32_t py = y0 + yy, pz = z0 + zz;
+        if (t < total && any && lane && py >= pl.lo[1] && py <= pl.hi[1] && pz >= pl.lo[2] &&
+            pz <= pl.hi[2])
+            ld[it] = pl.bitx[(int64_t)wx * (py + (int64_t)pl.py * pz) + w];
+    }
+#pragma unroll
+    for (int it = 0; it < kTileLoads; ++it) {
+        const int32_t t = it * kBlock + (int32_t)threadIdx.x;
+        if (t < total)
+            in[t] = ld[it];
+    }
+    __syncthreads();
+    for (int32_t zz = 0; zz < iz; ++zz) {
+        uint32_t v = 0;
+        for (int32_t d = 0; d <= r2; ++d)
+            v |= in[(zz * iy + slot + d) * kW + w];
+        yd[(zz * kTY + slot) * kW + w] = v;
+    }
+    __syncthreads();
+    const int32_t gy = y0 + slot;
+    if (!lane || gy >= pl.n[1])
+        return;
+    for (int32_t z = 0; z < kTileZ; ++z) {
+        const int32_t gz = z0 + z;
+        if (gz >= pl.n[2])
+            break;
+        uint32_t v = 0;
+        for (int32_t d = 0; d <= r2; ++d)
+            v |= yd[((z + d) * kTY + slot) * kW + w];
+        pl.occ[(int64_t)wx * (gy + (int64_t)pl.n[1] * gz) + w] = v;
+    }
+}
+
 // Alg. 2 for the 64 rays of fan tile `tile` (one wavefront).
 template <bool kGeneral>
 __device__ __forceinline__ void rays_body(const RayParams &p, int32_t tile)
@@ -435,6 +496,13 @@ __global__ __launch_bounds__(kBlock) void k_dilate_yz(Planes pl)
     dilate_yz_body(pl, (int64_t)blockIdx.x * kBlock + threadIdx.x);
 }
 
+template <int kW>
+__global__ __launch_bounds__(kBlock) void k_dilate_yz_tile(Planes pl)
+{
+    extern __shared__ uint32_t lds[];
+    dilate_yz_tile_body<kW>(pl, blockIdx.x, blockIdx.y, lds);
+}
+
 template <bool kGeneral>
 __global__ __launch_bounds__(kBlock) void k_rays(RayParams p)
 {
@@ -516,6 +584,19 @@ __global__ __launch_bounds__(kBlock) void kb_dilate_yz(const FrameDesc *__restri
     dilate_yz_body(f.sp.pl, (int64_t)local * kBlock + threadIdx.x);
 }
 
+template <int kW>
+__global__ __launch_bounds__(kBlock) void kb_dilate_yz_tile(const FrameDesc *__restrict__ fd,
+                                                            const int32_t *__restrict__ start,
+                                                            int32_t n)
+{
+    extern __shared__ uint32_t lds[];
+    int32_t local;
+    const FrameDesc &f = fd[frame_of(start, n, blockIdx.x, local)];
+    constexpr int32_t kTY = kBlock / kW;
+    const int32_t tiles_y = (f.sp.pl.n[1] + kTY - 1) / kTY;
+    dilate_yz_tile_body<kW>(f.sp.pl, local % tiles_y, local / tiles_y, lds);
+}
+
 __global__ __launch_bounds__(kBlock) void kb_rays(const FrameDesc *__restrict__ fd,
                                                   const int32_t *__restrict__ start, int32_t n)
 {
@@ -587,6 +668,20 @@ hipError_t launch_dilate(const Planes &pl, hipStream_t st, const StageEvents &ev
             return e;
         start = nullptr;
     }
+    const int kw = dilate_tile_width(pl);
+    if (kw > 0) {
+        const uint32_t lds = (uint32_t)dilate_tile_lds(pl, kw);
+        const int32_t ty = kBlock / kw;
+        const dim3 tiles((uint32_t)((pl.n[1] + ty - 1) / ty),
+                         (uint32_t)((pl.n[2] + kTileZ - 1) / kTileZ));
+        if (kw == 8)
+            hipExtLaunchKernelGGL(k_dilate_yz_tile<8>, tiles, dim3(kBlock), lds, st, start,
+                                  ev.stop, 0, pl);
+        else
+            hipExtLaunchKernelGGL(k_dilate_yz_tile<16>, tiles, dim3(kBlock), lds, st, start,
+                                  ev.stop, 0, pl);
+        return hipGetLastError();
+    }
     int64_t n = (int64_t)pl.wx * pl.n[1] * pl.n[2];
     hipExtLaunchKernelGGL(k_dilate_yz, dim3(blocks_for(n)), dim3(kBlock), 0, st, start, ev.stop,
                           0, pl);
@@ -645,7 +740,8 @@ hipError_t launch_upload(uint32_t *dst, const uint32_t *src, size_t words, hipSt
 }
 
 hipError_t launch_batch_stage(int stage, const FrameDesc *fd, const int32_t *start, int32_t n,
-                              int32_t blocks, hipStream_t st, const StageEvents &ev)
+                              int32_t blocks, hipStream_t st, const StageEvents &ev, int tile_w,
+                              size_t lds)
 {
     if (blocks <= 0 || n <= 0)
         return record_empty_stage(ev, st);
@@ -661,7 +757,14 @@ hipError_t launch_batch_stage(int stage, const FrameDesc *fd, const int32_t *sta
         hipExtLaunchKernelGGL(kb_dilate_x, g, b, 0, st, ev.start, ev.stop, 0, fd, start, n);
         break;
     case kBatchDilateYZ:
-        hipExtLaunchKernelGGL(kb_dilate_yz, g, b, 0, st, ev.start, ev.stop, 0, fd, start, n);
+        if (tile_w == 8)
+            hipExtLaunchKernelGGL(kb_dilate_yz_tile<8>, g, b, (uint32_t)lds, st, ev.start,
+                                  ev.stop, 0, fd, start, n);
+        else if (tile_w == 16)
+            hipExtLaunchKernelGGL(kb_dilate_yz_tile<16>, g, b, (uint32_t)lds, st, ev.start,
+                                  ev.stop, 0, fd, start, n);
+        else
+            hipExtLaunchKernelGGL(kb_dilate_yz, g, b, 0, st, ev.start, ev.stop, 0, fd, start, n);
         break;
     case kBatchRays:
         hipExtLaunchKernelGGL(kb_rays, g, b, 0, st, ev.start, ev.stop, 0, fd, start, n);
