@@ -146,12 +146,12 @@ static void grid_translation(const float t[3], const float origin[3], float tv[3
 void og_quantize(const float R[9], const float tv[3], float vox_size, const float pc[3], float q[3])
 {
     float pv[3];
-    transform(R, tv, pc, pv);              /* Alg. 1 line 2 */
-    for (int a = 0; a < 3; ++a)            /* Alg. 1 lines 3-5, R1: floor */
+    transform(R, tv, pc, pv);              /* Alg. 1: the transform */
+    for (int a = 0; a < 3; ++a)            /* Alg. 1: quantise, R1: floor */
         q[a] = floorf(pv[a] / vox_size);
 }
 
-/* Alg. 1 lines 6-9 for one point already transformed; R2 clips the cube to the
+/* Alg. 1, inflation, for one point already transformed; R2 clips the cube to the
  * grid and drops points whose cube cannot reach it. */
 static void add_occ(int32_t gx, int32_t gy, int32_t gz, int32_t r, const float q[3], uint8_t *ms)
 {
@@ -323,7 +323,7 @@ static int64_t trace_pinhole_fan(frame_ctx *f, int32_t vd, int32_t hw, int32_t h
             tgt[0] = (float)xi;
             tgt[1] = (float)yi;
             tgt[2] = (float)vd;
-            rotate(f->R, tgt, dir);        /* Alg. 2 line 4, R11 */
+            rotate(f->R, tgt, dir);        /* Alg. 2: ray direction, R11 */
             int64_t m2 = (int64_t)xi * xi + (int64_t)yi * yi + (int64_t)vd * vd;
             walk(o, dir, m2, f->gx, f->gy, f->gz, f->ms, NULL, NULL, 0, &steps, &f->after_hit);
         }

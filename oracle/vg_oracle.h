@@ -52,7 +52,7 @@ int64_t og_spin_ray_count(int32_t vox_depth, double tan_half_vfov, int32_t *hz_o
  * origin = base + (float)shift * vox_size, per component, each op rounded. */
 void og_origin(const float base[3], const int32_t shift[3], float vox_size, float origin[3]);
 
-/* Alg. 1 lines 2-5 for one camera-frame point: p^v = R p^c + t^v (R8) and
+/* Alg. 1, transform and quantise, for one camera-frame point: p^v = R p^c + t^v (R8) and
  * q = floor(p^v / vox_size) (R1).  Writes the floored values as floats. */
 void og_quantize(const float R[9], const float tv[3], float vox_size, const float pc[3], float q[3]);
 

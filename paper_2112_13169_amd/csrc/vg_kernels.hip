@@ -3,11 +3,11 @@
 //
 // One frame is a chain of launches on one stream (k_clear, for a shift of the
 // ring-buffered grid, runs before it when the grid is re-centred):
-//   k_seed        Alg. 1 lines 2-5: one lane per pixel / point: unproject,
+//   k_seed        Alg. 1, transform and quantise: one lane per pixel / point: unproject,
 //                 transform, quantise; stamp the point's voxel in a seed plane
 //                 padded by vox_inf (byte stores of the frame's stamp: no
 //                 clearing between frames, no atomics).
-//   k_dilate_x    Alg. 1 lines 6-9, separably: seeds -> bits dilated by
+//   k_dilate_x    Alg. 1, inflation, separably: seeds -> bits dilated by
 //   k_dilate_yz   vox_inf along x, then along y and z.  The union of the
 //                 (2 vox_inf + 1)^3 cubes is exactly this separable dilation.
 //   k_rays        Alg. 2: one wavefront per tile of 64 fan targets (8 x 8 by
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_fill(uint8_t *dst, uint8_t value, si
 // kernels take their parameters as kernel arguments, the batch kernels read
 // them from a frame table in device memory.
 
-// Alg. 1 lines 2-5.  Images: block = 64 x 4 pixels (bx, by), one wavefront
+// Alg. 1, transform and quantise.  Images: block = 64 x 4 pixels (bx, by), one wavefront
 // per image row segment (coalesced row reads).  Points: 256 points per block.
 __device__ __forceinline__ void seed_body(const SeedParams &p, int32_t bx, int32_t by)
 {

@@ -26,18 +26,31 @@ import glob
 import hashlib
 import json
 import os
+import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ["csrc/vg_kernels.hip", "csrc/vg_walk.h", "csrc/vg_internal.h"]
 
 
-def kernel_source_hash():
-    """Hash of the kernel sources: counter readings taken on other sources are
-    stale."""
+def code_only(text):
+    """C/C++ source without its comments and blank space (a comment edit does
+    not change a kernel)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def kernel_source_hash(read=None):
+    """Hash of the kernel sources' code: counter readings taken on other code
+    are stale.  `read(rel)` may supply a file's text (default: this tree)."""
     h = hashlib.sha256()
     for rel in KERNEL_SOURCES:
-        with open(os.path.join(HERE, rel), "rb") as fh:
-            h.update(fh.read())
+        if read is None:
+            with open(os.path.join(HERE, rel)) as fh:
+                text = fh.read()
+        else:
+            text = read(rel)
+        h.update(code_only(text).encode())
     return h.hexdigest()[:16]
 
 
@@ -120,7 +133,7 @@ def main(argv=None):
         lines += [f"Calibration: a {a.cal_bytes} B device copy read FETCH_SIZE {f_cal:.1f} KiB "
                   f"and WRITE_SIZE {w_cal:.1f} KiB, so bytes = FETCH_SIZE x {f_fac:.4f} KiB + "
                   f"WRITE_SIZE x {w_fac:.4f} KiB.", ""]
-    lines += [f"Kernel sources hash: `{kernel_source_hash()}`", "",
+    lines += [f"Kernel sources hash (code without comments): `{kernel_source_hash()}`", "",
               "| kernel | launches | avg us | min us | max us | % time | FETCH KiB | WRITE KiB "
               "| bytes/launch (calibrated) |",
               "|---|---|---|---|---|---|---|---|---|"]
