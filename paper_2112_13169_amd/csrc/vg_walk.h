@@ -237,6 +237,12 @@ VG_HD uint32_t bit_of(uint32_t word, uint32_t i)
 #endif
 }
 
+// Index of the lowest set bit of a non-zero word.
+VG_HD int lowest_set(uint32_t v)
+{
+    return __builtin_ctz(v);
+}
+
 // The walk runs in chunks of kChunk steps, two chunks in flight: the
 // occupancy words of one chunk load while the previous chunk is resolved.
 // A step that was not taken, or whose voxel is outside the grid, has index
@@ -315,19 +321,22 @@ VG_HD bool walk_chunk(Walk &w, int32_t m2, bool alive, Chunk &c, bool load, cons
 // Returns whether the chunk held the hit.
 VG_HD bool resolve_chunk(const Chunk &c, bool before_hit, const WalkMem &m)
 {
-    int hit = kChunk;
+    // occupied bits of the chunk's voxels as a mask (words of steps not taken
+    // are 0); the hit is its lowest set bit.  Steps before `hit` are free:
+    // none once the ray has hit (hit = 0), all of them if this chunk has no
+    // occupied voxel (hit = kChunk).
+    uint32_t hits = 1u;
     if (before_hit) {
+        hits = 1u << kChunk;
 #pragma unroll
-        for (int s = kChunk - 1; s >= 0; --s)
-            if (bit_of(c.words[s], c.ids[s]))   // words of steps not taken are 0
-                hit = s;
+        for (int s = 0; s < kChunk; ++s)
+            hits |= bit_of(c.words[s], c.ids[s]) << s;
     }
+    const int hit = lowest_set(hits);
 #pragma unroll
-    for (int s = 0; s < kChunk; ++s) {
-        const bool free = before_hit && s < hit;
-        store_mark(m, c.ids[s] + (free ? 0u : m.n));
-    }
-    return hit < kChunk;
+    for (int s = 0; s < kChunk; ++s)
+        store_mark(m, c.ids[s] + (s < hit ? 0u : m.n));
+    return before_hit && hit < kChunk;
 }
 
 // Alg. 2 for one ray: walk, test occupancy before the first hit, mark free
