@@ -125,16 +125,15 @@ struct FrameDesc {
 // of kBlock threads is kW word lanes by kBlock / kW row slots, and a tile is
 // kBlock / kW output rows along y by kTileZ along z.  0: untiled.
 constexpr int kTileZ = 2;
-constexpr int kTileLoads = 16;   // input words per thread: iz * iy * kW <= 16 * 256
+constexpr int kTileMaxIz = 8;    // input z rows a tile may need: kTileZ + 2 vox_inf
 constexpr size_t kMaxTileLds = 48 * 1024;
 
 inline int dilate_tile_width(const Planes &pl)
 {
     const int kw = pl.wx <= 8 ? 8 : (pl.wx <= 16 ? 16 : 0);
-    if (kw == 0)
-        return 0;
-    const size_t ty = 256 / kw, iz = (size_t)kTileZ + 2 * pl.r, iy = ty + 2 * pl.r;
-    if (iz * iy * kw > (size_t)kTileLoads * 256)
+    const size_t ty = kw ? 256 / kw : 0, iz = (size_t)kTileZ + 2 * pl.r, iy = ty + 2 * pl.r;
+    // each thread loads at most 2 input rows of every z row: iy <= 2 ty
+    if (kw == 0 || iz > (size_t)kTileMaxIz || iy > 2 * ty)
         return 0;
     return 4 * (size_t)kw * (iz * iy + iz * ty) <= kMaxTileLds ? kw : 0;
 }

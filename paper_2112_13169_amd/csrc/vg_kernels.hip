@@ -273,26 +273,30 @@ __device__ __forceinline__ void dilate_yz_tile_body(const Planes &pl, int32_t ti
     uint32_t *yd = lds + iz * iy * kW;    // [iz][kTY][kW]
     const bool any = pl.lo[0] <= pl.hi[0];
     const bool lane = w < wx;
-    // all loads of a thread first (at most kTileLoads, unrolled), so that they
-    // are in flight together; then the LDS stores
-    const int32_t total = iz * iy * kW;
-    uint32_t ld[kTileLoads];
+    // all loads of a thread first, so that they are in flight together: the
+    // thread's word lane w of padded rows y0 + slot (+ kTY) of every input z
+    // row (at most 2 x kTileMaxIz, unrolled, no divisions); then the stores
+    uint32_t ld[2][kTileMaxIz];
 #pragma unroll
-    for (int it = 0; it < kTileLoads; ++it) {
-        const int32_t t = it * kBlock + (int32_t)threadIdx.x;
-        ld[it] = 0;
-        const int32_t row = t / kW;
-        const int32_t zz = row / iy, yy = row - zz * iy;
-        const int32_t py = y0 + yy, pz = z0 + zz;
-        if (t < total && any && lane && py >= pl.lo[1] && py <= pl.hi[1] && pz >= pl.lo[2] &&
-            pz <= pl.hi[2])
-            ld[it] = pl.bitx[(int64_t)wx * (py + (int64_t)pl.py * pz) + w];
+    for (int h = 0; h < 2; ++h) {
+        const int32_t yy = slot + h * kTY;
+        const int32_t py = y0 + yy;
+        const bool yin = any && lane && yy < iy && py >= pl.lo[1] && py <= pl.hi[1];
+#pragma unroll
+        for (int zz = 0; zz < kTileMaxIz; ++zz) {
+            const int32_t pz = z0 + zz;
+            ld[h][zz] = 0;
+            if (yin && zz < iz && pz >= pl.lo[2] && pz <= pl.hi[2])
+                ld[h][zz] = pl.bitx[(int64_t)wx * (py + (int64_t)pl.py * pz) + w];
+        }
     }
 #pragma unroll
-    for (int it = 0; it < kTileLoads; ++it) {
-        const int32_t t = it * kBlock + (int32_t)threadIdx.x;
-        if (t < total)
-            in[t] = ld[it];
+    for (int h = 0; h < 2; ++h) {
+        const int32_t yy = slot + h * kTY;
+#pragma unroll
+        for (int zz = 0; zz < kTileMaxIz; ++zz)
+            if (yy < iy && zz < iz)
+                in[(zz * iy + yy) * kW + w] = ld[h][zz];
     }
     __syncthreads();
     for (int32_t zz = 0; zz < iz; ++zz) {
