@@ -320,14 +320,32 @@ def run_batched(frames, K, warmup, torch, vg, oracle, autotune, sample_oracle=()
                                  want_ms=False)
         same = same and bool(np.array_equal(read(A[k][1], f).cpu().numpy(), ref.reshape(-1)))
 
-    # ray-bundle shapes tuned per fan class on the plain grids
+    # ray-bundle shapes tuned per fan class: for the plain grids on one frame
+    # of the class, for the batch on the batched walk launch
     samples = [(s, f.vox_size, hb, (lambda hb=hb, d=d, s=s, p=p: vg.vg_integrate_frame(hb, d, s, p)))
                for (_, hb), d, s, p, f in zip(B, dev, sensors, poses, frames)]
     table = autotune.tune(samples, vg, torch, reps=3)
-    for (_, ha), (_, hb), s, f in zip(A, B, sensors, frames):
-        w = autotune.choose(table, s, f.vox_size, vg)
-        vg.vg_set_ray_tile(ha, w)
-        vg.vg_set_ray_tile(hb, w)
+    for (_, hb), s, f in zip(B, sensors, frames):
+        vg.vg_set_ray_tile(hb, autotune.choose(table, s, f.vox_size, vg))
+
+    S = len(vg.BATCH_STAGES)
+    j = vg.BATCH_STAGES.index("rays")
+
+    def batch_rays_ms(reps=1):
+        rows = []
+        for _ in range(reps):
+            row = [None] * (2 * S)
+            row[2 * j], row[2 * j + 1] = (torch.cuda.Event(enable_timing=True),
+                                          torch.cuda.Event(enable_timing=True))
+            vg.vg_integrate_batch_timed(descs, ws, row)
+            rows.append(row)
+        torch.cuda.synchronize()
+        return float(np.mean([r[2 * j].elapsed_time(r[2 * j + 1]) for r in rows]))
+
+    classes = {}
+    for (_, ha), s, f in zip(A, sensors, frames):
+        classes.setdefault(autotune.fan_class(s, f.vox_size, vg), []).append(ha)
+    btable = autotune.tune_batch(classes, vg.vg_set_ray_tile, batch_rays_ms, reps=3)
 
     def timed(step):
         for _ in range(warmup):
@@ -349,24 +367,15 @@ def run_batched(frames, K, warmup, torch, vg, oracle, autotune, sample_oracle=()
     wp, lp = timed(plain_step)
 
     # the batched walk kernel's live time: events its own launches record
-    S = len(vg.BATCH_STAGES)
-    j = vg.BATCH_STAGES.index("rays")
-    stage_ev = []
-    for _ in range(K):
-        row = [None] * (2 * S)
-        row[2 * j], row[2 * j + 1] = (torch.cuda.Event(enable_timing=True),
-                                      torch.cuda.Event(enable_timing=True))
-        stage_ev.append(row)
-    for row in stage_ev:
-        vg.vg_integrate_batch_timed(descs, ws, row)
-    torch.cuda.synchronize()
-    rays_ms = float(np.mean([row[2 * j].elapsed_time(row[2 * j + 1]) for row in stage_ev]))
+    rays_ms = batch_rays_ms(K)
     for (_, h) in A + B:
         vg.vg_destroy_grid(h)
-    tiles = {"x".join(str(v) for v in c): {"best": f"{1 << b}x{64 >> b}",
-                                           "rays_ms": {f"{1 << w}x{64 >> w}": round(ms, 4)
-                                                       for w, ms in t.items()}}
-             for c, (b, t) in table.items()}
+
+    def tiles_of(tab):
+        return {"x".join(str(v) for v in c): {"best": f"{1 << b}x{64 >> b}",
+                                              "rays_ms": {f"{1 << w}x{64 >> w}": round(ms, 4)
+                                                          for w, ms in t.items()}}
+                for c, (b, t) in tab.items()}
     result = {
         "frames_per_step": n, "steps": K,
         "batched_frames_per_s": round(n * K / wb, 1),
@@ -380,7 +389,8 @@ def run_batched(frames, K, warmup, torch, vg, oracle, autotune, sample_oracle=()
                                   "p99": round(float(np.percentile(lp, 99)), 4)},
         "bit_exact": same,
         "oracle_sampled_frames": list(sample_oracle),
-        "ray_tiles": tiles,
+        "ray_tiles_plain": tiles_of(table),
+        "ray_tiles_batched": tiles_of(btable),
         "kb_rays_ms": round(rays_ms, 5),
     }
     if walk_steps is not None:

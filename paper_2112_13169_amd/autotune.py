@@ -70,6 +70,33 @@ def tune(samples, lib_vg, torch, reps=5):
     return table
 
 
+def tune_batch(classes, set_tile, time_rays, reps=3):
+    """Shapes for the frames of one batch, timed on the batched walk launch
+    itself: there many frames' wavefronts share the chip, so the shape that is
+    fastest for a lone frame (latency) need not be fastest in the batch
+    (throughput, cache footprint).  classes: {class: [grid handles]} of the
+    batch's frames; set_tile(handle, shape); time_rays() runs the batch and
+    returns its walk launch time (ms).  One coordinate-descent pass over the
+    classes, largest first, the others held at their current shape (8 x 8 to
+    begin with).  Returns {class: (best shape, {shape: ms})}."""
+    for hs in classes.values():
+        for h in hs:
+            set_tile(h, 3)
+    table = {}
+    for c in sorted(classes, key=lambda c: -len(classes[c])):
+        times = {}
+        for w in SHAPES:
+            for h in classes[c]:
+                set_tile(h, w)
+            time_rays()                                  # warm
+            times[w] = float(np.median([time_rays() for _ in range(reps)]))
+        best = min(times, key=times.get)
+        for h in classes[c]:
+            set_tile(h, best)
+        table[c] = (best, times)
+    return table
+
+
 def choose(table, sensor, vox_size, lib_vg, default=3):
     """Tuned shape of a (sensor, voxel size), or the default (8 x 8)."""
     hit = table.get(fan_class(sensor, vox_size, lib_vg))

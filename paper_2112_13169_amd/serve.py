@@ -262,9 +262,19 @@ class GpuBackend:
         self.aux = torch.cuda.Stream()     # grid set-up, eviction and restore
         self.ws = [torch.empty(vg.vg_batch_workspace_bytes(max_batch), dtype=torch.uint8,
                                device="cuda") for _ in range(streams)]
-        # frames in pinned host memory, so that uploads are asynchronous
+        # frames in pinned host memory, so that uploads are asynchronous, and
+        # their poses, built once
         self.host = {rid: [torch.from_numpy(np.ascontiguousarray(f.depth)).pin_memory()
                            for f in seq] for rid, seq in frames.items()}
+        self.poses = {rid: [vg.make_pose(f.R, f.t) for f in seq] for rid, seq in frames.items()}
+        # device slots of each stream's batch: a stream's next batch starts only
+        # after its previous one has completed, so the slots are reused as is
+        shapes = {f.depth.shape for seq in frames.values() for f in seq}
+        self.slots = None
+        if len(shapes) == 1:
+            shape = shapes.pop()
+            self.slots = [torch.empty((max_batch,) + tuple(shape), dtype=torch.float32,
+                                      device="cuda") for _ in range(streams)]
         self.dev = {}          # (rid, k) -> device depth of an admitted frame
         self.robots = {}
 
@@ -316,15 +326,18 @@ class GpuBackend:
             st.wait_event(e)
         with torch.cuda.stream(st):
             descs = []
-            for q in batch:
+            for j, q in enumerate(batch):
                 fr = self.frames[q.robot][q.index]
                 r = self.robots[q.robot]
-                d = torch.empty(fr.depth.shape, dtype=torch.float32, device="cuda")
+                if self.slots is not None:
+                    d = self.slots[s][j]
+                else:
+                    d = torch.empty(fr.depth.shape, dtype=torch.float32, device="cuda")
+                    self.dev[(q.robot, q.index)] = d
                 d.copy_(self.host[q.robot][q.index], non_blocking=True)
-                self.dev[(q.robot, q.index)] = d
                 shift = vg.vg_center_offset(r.handle, fr.t)
-                pose = vg.make_pose(fr.R, fr.t)
-                descs.append(vg.frame_image(r.handle, d, self.sensor, pose, shift))
+                descs.append(vg.frame_image(r.handle, d, self.sensor,
+                                            self.poses[q.robot][q.index], shift))
             vg.vg_integrate_batch(descs, self.ws[s], st)
             ev = torch.cuda.Event()
             ev.record(st)
