@@ -54,7 +54,8 @@ CAL_BYTES = 64 << 20            # calibration copy: 64 MiB read + 64 MiB written
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
-STAGE_KERNELS = {"k_dilate": ["k_dilate_x", "k_dilate_yz"],
+STAGE_KERNELS = {"k_dilate": ["k_dilate_x", "k_dilate_yz", "k_dilate_yz_tile<8>",
+                              "k_dilate_yz_tile<16>"],
                  "k_rays": ["k_rays<false>", "k_rays<true>"]}
 
 

@@ -303,7 +303,9 @@ VG_HD bool walk_chunk(Walk &w, int32_t m2, bool alive, Chunk &c, bool load, cons
             c.ids[s] = (alive && in) ? w.idx : kOob;
         }
     }
-    // a wavefront whose rays have all met their obstacle loads nothing
+    // a wavefront whose rays have all met their obstacle loads nothing.  For
+    // kOob the word's byte offset is 2^28, beyond any occupancy plane (grids
+    // hold fewer than 2^30 voxels): a step outside the grid reads 0.
     if (vg_any(load)) {
 #pragma unroll
         for (int s = 0; s < kChunk; ++s)

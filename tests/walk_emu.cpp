@@ -1,7 +1,10 @@
 // Host build of the kernel's ray walk (paper_2112_13169_amd/csrc/vg_walk.h),
 // checked ray by ray against the CPU oracle's walk.  Random grids, random
-// occupancy, random rays from inside and outside the grid.  Prints the
-// number of mismatching voxels and exits non-zero if there is any.
+// occupancy, random rays from inside and outside the grid.  The occupancy
+// buffer is followed by 64 MiB of all-ones words: steps outside the grid must
+// read nothing from it (as on the device, where a grid of up to 2^30 voxels
+// has that much occupancy plane).  Prints the number of mismatching voxels
+// and exits non-zero if there is any.
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -25,6 +28,8 @@ int main(int argc, char **argv)
     const int trials = argc > 1 ? atoi(argv[1]) : 2000;
     rng_state += argc > 2 ? (uint64_t)atoll(argv[2]) : 0;
     long long bad = 0, voxels = 0, steps = 0;
+    // grid words first, then set bits up to and past byte 2^26
+    std::vector<uint32_t> occ(((size_t)1 << 24) + 64, 0xFFFFFFFFu);
     for (int trial = 0; trial < trials; ++trial) {
         // every third trial: a large grid and long rays, so that most chunks
         // take the path without per-step tests
@@ -48,7 +53,7 @@ int main(int argc, char **argv)
         }
         const bool inside = f.v0[0] >= 0 && f.v0[0] < nx && f.v0[1] >= 0 && f.v0[1] < ny &&
                             f.v0[2] >= 0 && f.v0[2] < nz;
-        std::vector<uint32_t> occ((size_t)f.gxp / 32 * ny * nz, 0);
+        std::fill(occ.begin(), occ.begin() + (size_t)f.gxp / 32 * ny * nz, 0u);
         std::vector<uint8_t> ms((size_t)nx * ny * nz, 0);
         const uint32_t density = big ? 200 + rnd() % 4000 : 8 + rnd() % 120;
         for (int z = 0; z < nz; ++z)
