@@ -144,6 +144,18 @@ vg_status vg_rebind_grid(vg_grid *g, uint8_t *loc_grid, uint8_t *loc_spare, size
 vg_status vg_integrate_frame(vg_grid *g, const float *depth, int64_t row_pitch_bytes,
                              const vg_sensor *sensor, const vg_pose *T_w_c, void *stream);
 
+/* Step 5 then steps 2-4 (Sec. IV-E; Alg. 1, 2, 3): the same as
+ * vg_shift_grid(g, dx, dy, dz, stream) followed by vg_integrate_frame(g, ...)
+ * -- the same grid, the same errors (VG_ERR_ARG leaves the grid untouched,
+ * shift included) -- in one call.  The shift's clear of the exposed slabs
+ * runs as extra workgroups of the frame's ray-walk launch, on compute units
+ * the walk leaves idle, instead of a launch of its own.  With the
+ * measurement hook set, the frame's shift pair records markers only (the
+ * clear's time is inside the walk's pair). */
+vg_status vg_integrate_frame_shifted(vg_grid *g, const float *depth, int64_t row_pitch_bytes,
+                                     const vg_sensor *sensor, const vg_pose *T_w_c, int32_t dx,
+                                     int32_t dy, int32_t dz, void *stream);
+
 /* Same as vg_integrate_frame for a dense point cloud (the paper's stereo input
  * form, Sec. IV): `points` is device float32[n_points][3] in the camera frame;
  * an entry is a measurement iff all three coordinates are finite.  The ray fan

@@ -587,10 +587,32 @@ void batch_blocks(const vg_grid *g, const FramePlan &p, bool moved, int tile_w,
 }
 
 // Steps 2-4 of one frame, one launch per stage.
+// A shift of the grid's offset by d stays within +-2^24 voxels.
+bool shift_in_range(const vg_grid *g, const int32_t d[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        const int64_t s = (int64_t)g->shift[a] + d[a];
+        if (s > (1 << 24) || s < -(1 << 24))
+            return false;
+    }
+    return true;
+}
+
+// Steps 2-4 of one frame, after the shift d (step 5) if d is given and not
+// zero: its slab clear runs as extra workgroups of the walk launch.
 vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_floats, int32_t W,
-                    int32_t H, const vg_sensor *sensor, const vg_pose *T, hipStream_t st)
+                    int32_t H, const vg_sensor *sensor, const vg_pose *T, hipStream_t st,
+                    const int32_t *d = nullptr)
 {
     GridState gs = state_of(g);
+    SlabClear clear;
+    const bool shifted = d && (d[0] != 0 || d[1] != 0 || d[2] != 0);
+    if (shifted) {
+        if (!shift_in_range(g, d))
+            return VG_ERR_ARG;
+        plan_shift(g, gs, d, clear);
+        clear.loc = g->loc;
+    }
     FramePlan p;
     vg_status rc = plan_frame(g, gs, kind, data, pitch_floats, W, H, sensor, T, p);
     if (rc != VG_OK)
@@ -606,11 +628,14 @@ vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_float
     const StageEvents *ev = stage_events(g);
     StageEvents none;
     auto stage = [&](int k) -> const StageEvents & { return ev ? ev[k] : none; };
-    e = launch_seeds(p.sp, st, stage(kStageSeed));
+    if (d)   // the shift's own pair: markers (its clear is timed with the walk)
+        e = record_empty_stage(stage(kStageShift), st);
+    if (e == hipSuccess)
+        e = launch_seeds(p.sp, st, stage(kStageSeed));
     if (e == hipSuccess)
         e = launch_dilate(p.sp.pl, st, stage(kStageDilate));
     if (e == hipSuccess)
-        e = launch_rays(p.rp, p.inside, st, stage(kStageRays));
+        e = launch_rays(p.rp, p.inside, st, stage(kStageRays), shifted ? &clear : nullptr);
     if (e == hipSuccess)
         e = launch_resolve(p.sp.pl, g->loc, p.rows, p.ring, st, stage(kStageResolve));
     if (ev)
@@ -762,16 +787,27 @@ vg_status vg_integrate_points(vg_grid *g, const float *points, int64_t n_points,
                      static_cast<hipStream_t>(stream));
 }
 
+vg_status vg_integrate_frame_shifted(vg_grid *g, const float *depth, int64_t row_pitch_bytes,
+                                     const vg_sensor *sensor, const vg_pose *T_w_c, int32_t dx,
+                                     int32_t dy, int32_t dz, void *stream)
+{
+    if (!g || !valid_sensor(sensor) || !T_w_c || !finite_pose(T_w_c))
+        return VG_ERR_ARG;
+    if (row_pitch_bytes % 4 != 0 || row_pitch_bytes < 4 * (int64_t)sensor->width)
+        return VG_ERR_ARG;
+    const int32_t d[3] = {dx, dy, dz};
+    int kind = sensor->kind == VG_SPINNING ? kSpinning : kPinhole;
+    return integrate(g, kind, depth, row_pitch_bytes / 4, sensor->width, sensor->height, sensor,
+                     T_w_c, static_cast<hipStream_t>(stream), d);
+}
+
 vg_status vg_shift_grid(vg_grid *g, int32_t dx, int32_t dy, int32_t dz, void *stream)
 {
     if (!g)
         return VG_ERR_ARG;
     const int32_t d[3] = {dx, dy, dz};
-    for (int a = 0; a < 3; ++a) {
-        int64_t s = (int64_t)g->shift[a] + d[a];
-        if (s > (1 << 24) || s < -(1 << 24))
-            return VG_ERR_ARG;
-    }
+    if (!shift_in_range(g, d))
+        return VG_ERR_ARG;
     const StageEvents *ev = stage_events(g);
     const StageEvents none;
     const StageEvents &sev = ev ? ev[kStageShift] : none;

@@ -178,8 +178,10 @@ hipError_t launch_seeds(const SeedParams &p, hipStream_t st, const StageEvents &
 // Seeds -> occupied bit plane (dilation by vox_inf along x, then y and z).
 hipError_t launch_dilate(const Planes &pl, hipStream_t st, const StageEvents &ev = {});
 // The walk of every fan ray.  camera_inside: the camera voxel lies in the grid.
+// clear (optional): a slab clear of the local grid run by extra workgroups of
+// the same launch (it touches no memory the walk uses).
 hipError_t launch_rays(const RayParams &p, bool camera_inside, hipStream_t st,
-                       const StageEvents &ev = {});
+                       const StageEvents &ev = {}, const SlabClear *clear = nullptr);
 // Marks and occupied bits -> the local grid (ring offsets `ring`), over the
 // given rows.
 hipError_t launch_resolve(const Planes &pl, uint8_t *loc, const RowBox &rows,

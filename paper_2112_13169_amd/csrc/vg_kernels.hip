@@ -507,9 +507,15 @@ __global__ __launch_bounds__(kBlock) void k_dilate_yz_tile(Planes pl)
     dilate_yz_tile_body<kW>(pl, blockIdx.x, blockIdx.y, lds);
 }
 
+// The walk; workgroups from ray_blocks on run the slab clear c instead (the
+// walk leaves most compute units idle for its longest rays).
 template <bool kGeneral>
-__global__ __launch_bounds__(kBlock) void k_rays(RayParams p)
+__global__ __launch_bounds__(kBlock) void k_rays(RayParams p, SlabClear c, int32_t ray_blocks)
 {
+    if ((int32_t)blockIdx.x >= ray_blocks) {
+        clear_body(c, (int64_t)(blockIdx.x - ray_blocks) * kBlock + threadIdx.x);
+        return;
+    }
     rays_body<kGeneral>(p, blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6));
 }
 
@@ -693,18 +699,25 @@ hipError_t launch_dilate(const Planes &pl, hipStream_t st, const StageEvents &ev
 }
 
 hipError_t launch_rays(const RayParams &p, bool camera_inside, hipStream_t st,
-                       const StageEvents &ev)
+                       const StageEvents &ev, const SlabClear *clear)
 {
     const int waves = kBlock / 64;
-    uint32_t blocks = (uint32_t)((p.tiles + waves - 1) / waves);
+    const int64_t ray_blocks = (p.tiles + waves - 1) / waves;
+    SlabClear c{};
+    int64_t clear_blocks = 0;
+    if (clear) {
+        c = *clear;
+        clear_blocks = blocks_for((int64_t)(c.gxp / 16) * c.n[1] * c.n[2]);
+    }
+    const uint32_t blocks = (uint32_t)(ray_blocks + clear_blocks);
     if (blocks == 0)
         return record_empty_stage(ev, st);
     if (camera_inside)
         hipExtLaunchKernelGGL(k_rays<false>, dim3(blocks), dim3(kBlock), 0, st, ev.start, ev.stop,
-                              0, p);
+                              0, p, c, (int32_t)ray_blocks);
     else
         hipExtLaunchKernelGGL(k_rays<true>, dim3(blocks), dim3(kBlock), 0, st, ev.start, ev.stop,
-                              0, p);
+                              0, p, c, (int32_t)ray_blocks);
     return hipGetLastError();
 }
 

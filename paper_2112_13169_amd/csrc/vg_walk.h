@@ -16,8 +16,14 @@
 #include <cmath>
 #define VG_HD static inline
 #define VG_INF INFINITY
-#define vg_any(p) (p)   // host build: one lane per "wavefront"
-#define vg_all(p) (p)
+// Host build: one lane per "wavefront".  A test can stand in for the other
+// lanes of a wavefront with vg_host_vote: each call returns whether some
+// other lane votes the other way (so a wavefront vote can be true although
+// this lane's predicate is false, for any, or false although it is true, for
+// all).  The walk's results must not depend on it.
+inline bool (*vg_host_vote)() = nullptr;
+#define vg_any(p) ((p) || (vg_host_vote && vg_host_vote()))
+#define vg_all(p) ((p) && !(vg_host_vote && vg_host_vote()))
 #endif
 
 namespace vg {
@@ -100,7 +106,6 @@ struct WalkFrame {
 };
 
 VG_HD int32_t imax(int32_t a, int32_t b) { return a > b ? a : b; }
-VG_HD float fmin3(float a, float b, float c) { return fminf(fminf(a, b), c); }
 
 // Amanatides & Woo set-up on one axis.
 VG_HD void axis_setup(float o, int32_t v0, float d, int32_t &step, float &tmax, float &tdelta)
@@ -182,23 +187,31 @@ VG_HD int32_t sgn(float d) { return d > 0.0f ? 1 : (d < 0.0f ? -1 : 0); }
 VG_HD int32_t sel(bool c, int32_t a, int32_t b) { return c ? a : b; }
 VG_HD float self(bool c, float a, float b) { return c ? a : b; }
 
-// Move one voxel along the axis whose next boundary is nearest (ties go to
-// the later axis): its boundary parameter advances by its per-voxel
-// increment, its step count by one, the squared lattice distance by the old
-// q of that axis and the index by that axis' stride.  Returns the old q and
-// the axis' limit (a step with q >= limit leaves the grid).
+// The axis of the next step: the one whose boundary parameter is smallest,
+// ties going to the later axis -- tMx<tMy ? (tMx<tMz ? x : z) : (tMy<tMz ?
+// y : z) -- as three compares: z if tMz <= tMy and tMz <= tMx, else y if
+// tMy <= tMx, else x (the boundary parameters are never NaN).
+VG_HD void pick_axis(float tmx, float tmy, float tmz, bool &ax, bool &ay, bool &az)
+{
+    const bool zy = tmz <= tmy, zx = tmz <= tmx, yx = tmy <= tmx;
+    az = zy && zx;
+    ay = !az && yx;
+    ax = !az && !yx;
+}
+
+// Move one voxel along the axis whose next boundary is nearest: its boundary
+// parameter advances by its per-voxel increment, its step count by one, the
+// squared lattice distance by the old q of that axis and the index by that
+// axis' stride.  Returns the old q and the axis' limit (a step with q >=
+// limit leaves the grid).
 VG_HD void advance(Walk &w, int32_t &q, int32_t &lim)
 {
     const float tmx = w.tmx, tmy = w.tmy, tmz = w.tmz;
-    // tMx<tMy ? (tMx<tMz ? x : z) : (tMy<tMz ? y : z) == "z if tMz is a
-    // minimum, else y if tMy is, else x" (the boundary parameters are never NaN)
-    const float mn = fmin3(tmx, tmy, tmz);
-    const bool az = tmz == mn;
-    const bool ayr = tmy == mn;
-    q = sel(az, w.qz, sel(ayr, w.qy, w.qx));
-    lim = sel(az, w.lz, sel(ayr, w.ly, w.lx));
-    const int32_t stride = sel(az, w.sz, sel(ayr, w.sy, w.sx));
-    const bool ay = !az && ayr, ax = !az && !ayr;
+    bool ax, ay, az;
+    pick_axis(tmx, tmy, tmz, ax, ay, az);
+    q = sel(az, w.qz, sel(ay, w.qy, w.qx));
+    lim = sel(az, w.lz, sel(ay, w.ly, w.lx));
+    const int32_t stride = sel(az, w.sz, sel(ay, w.sy, w.sx));
     w.tmx = self(ax, tmx + w.tdx, tmx);
     w.tmy = self(ay, tmy + w.tdy, tmy);
     w.tmz = self(az, tmz + w.tdz, tmz);
@@ -243,14 +256,34 @@ VG_HD int lowest_set(uint32_t v)
     return __builtin_ctz(v);
 }
 
+// a * b for a, b < 2^24 and a product below 2^32 (one full-rate multiply on
+// the device).
+VG_HD uint32_t mul24(uint32_t a, uint32_t b)
+{
+#ifdef __HIPCC__
+    return __umul24(a, b);
+#else
+    return a * b;
+#endif
+}
+
 // The walk runs in chunks of kChunk steps, two chunks in flight: the
 // occupancy words of one chunk load while the previous chunk is resolved.
-// A step that was not taken, or whose voxel is outside the grid, has index
-// kOob: its load reads 0 and its mark store writes nothing (kOob is at least
-// twice any plane size, so kOob + n stays out of range too).
+//
+// Indices: a walk's index runs over the free mark plane until the ray meets
+// its first occupied voxel, over the traced plane from then on (it moves up
+// by n there), and is kOob once the walk is over (its strides become 0, so it
+// stays kOob).  A step that was not taken, or whose voxel is outside the
+// grid, has index kOob.  Loads at traced-plane indices or at kOob fall beyond
+// the occupancy plane and read 0 (the word of index i is at byte
+// (i >> 5) << 2, at least n / 8 for i >= n, and 2^28 for kOob); stores at
+// kOob or kOob + n write nothing (kOob is at least twice any plane size).  So
+// a ray after its hit needs no test for its loads or for the plane of its
+// marks.
 struct Chunk {
-    uint32_t ids[kChunk];     // device-layout index of each step's voxel, or kOob
+    uint32_t ids[kChunk];     // index of each step's voxel, or kOob
     uint32_t words[kChunk];   // occupancy word of that voxel (0 when not loaded)
+    bool loaded;              // some lane of the wavefront loaded words
 };
 
 // A live walk whose next kChunk steps can neither reach its length nor leave
@@ -272,29 +305,31 @@ VG_HD bool walk_chunk(Walk &w, int32_t m2, bool alive, Chunk &c, bool load, cons
         // No step of this chunk can end a walk, so the steps skip the tests
         // and the bookkeeping of q and the distance: the steps per axis are
         // counted in one word (10 bits each) and applied at the end.  The
-        // boundary parameters and the index move exactly as in advance().
+        // boundary parameters and the index move exactly as in advance(); a
+        // finished walk's index stays kOob.
         uint32_t cnt = 0;
 #pragma unroll
         for (int s = 0; s < kChunk; ++s) {
             const float tmx = w.tmx, tmy = w.tmy, tmz = w.tmz;
-            const float mn = fmin3(tmx, tmy, tmz);
-            const bool az = tmz == mn;
-            const bool ayr = tmy == mn;
-            const bool ay = !az && ayr, ax = !az && !ayr;
+            bool ax, ay, az;
+            pick_axis(tmx, tmy, tmz, ax, ay, az);
             w.tmx = self(ax, tmx + w.tdx, tmx);
             w.tmy = self(ay, tmy + w.tdy, tmy);
             w.tmz = self(az, tmz + w.tdz, tmz);
-            cnt += (uint32_t)sel(az, 1 << 20, sel(ayr, 1 << 10, 1));
-            w.idx += (uint32_t)sel(az, w.sz, sel(ayr, w.sy, w.sx));
-            c.ids[s] = alive ? w.idx : kOob;
+            cnt += (uint32_t)sel(az, 1 << 20, sel(ay, 1 << 10, 1));
+            w.idx += (uint32_t)sel(az, w.sz, sel(ay, w.sy, w.sx));
+            c.ids[s] = w.idx;
         }
-        // c steps on an axis whose q was q0 add q0 + (q0+2) + ... = c (q0 + c - 1)
-        const int32_t cx = (int32_t)(cnt & 1023u), cy = (int32_t)((cnt >> 10) & 1023u);
-        const int32_t cz = (int32_t)(cnt >> 20);
-        w.d2 += cx * (w.qx + cx - 1) + cy * (w.qy + cy - 1) + cz * (w.qz + cz - 1);
-        w.qx += 2 * cx;
-        w.qy += 2 * cy;
-        w.qz += 2 * cz;
+        // c steps on an axis whose q was q0 add q0 + (q0+2) + ... = c (q0 + c - 1);
+        // a live walk's distance stays below 2^31, so q and c (q0 + c - 1) fit
+        // the 24-bit multiply
+        const uint32_t cx = cnt & 1023u, cy = (cnt >> 10) & 1023u, cz = cnt >> 20;
+        w.d2 += (int32_t)(mul24(cx, (uint32_t)w.qx + cx - 1u) +
+                          mul24(cy, (uint32_t)w.qy + cy - 1u) +
+                          mul24(cz, (uint32_t)w.qz + cz - 1u));
+        w.qx += (int32_t)(2u * cx);
+        w.qy += (int32_t)(2u * cy);
+        w.qz += (int32_t)(2u * cz);
     } else {
 #pragma unroll
         for (int s = 0; s < kChunk; ++s) {
@@ -302,14 +337,17 @@ VG_HD bool walk_chunk(Walk &w, int32_t m2, bool alive, Chunk &c, bool load, cons
             alive = walk_step<kGeneral>(w, m2, alive, in);
             c.ids[s] = (alive && in) ? w.idx : kOob;
         }
+        if (!alive) {   // over: the index parks at kOob
+            w.idx = kOob;
+            w.sx = w.sy = w.sz = 0;
+        }
     }
-    // a wavefront whose rays have all met their obstacle loads nothing.  For
-    // kOob the word's byte offset is 2^28, beyond any occupancy plane (grids
-    // hold fewer than 2^30 voxels): a step outside the grid reads 0.
-    if (vg_any(load)) {
+    // a wavefront whose rays have all met their obstacle loads nothing
+    c.loaded = vg_any(load);
+    if (c.loaded) {
 #pragma unroll
         for (int s = 0; s < kChunk; ++s)
-            c.words[s] = load_occ(m, load ? (c.ids[s] >> 5) << 2 : kOob);
+            c.words[s] = load_occ(m, (c.ids[s] >> 5) << 2);
     } else {
 #pragma unroll
         for (int s = 0; s < kChunk; ++s)
@@ -318,27 +356,41 @@ VG_HD bool walk_chunk(Walk &w, int32_t m2, bool alive, Chunk &c, bool load, cons
     return alive;
 }
 
-// Marks of one chunk: free before the ray's first occupied voxel, traced from
+// Marks of chunk c: free before the ray's first occupied voxel, traced from
 // it on (the occupied voxel itself becomes occupied whatever its marks say).
-// Returns whether the chunk held the hit.
-VG_HD bool resolve_chunk(const Chunk &c, bool before_hit, const WalkMem &m)
+// The hit is the lowest occupied slot of a ray still before its hit (a ray
+// after it loaded zeros).  A lane that hits here moves to the traced plane:
+// its walk index and the indices of the chunk walked after c (`next`, whose
+// words it must no longer test) move up by n.
+VG_HD void resolve_chunk(const Chunk &c, bool &before_hit, Walk &w, Chunk &next,
+                         const WalkMem &m)
 {
-    // occupied bits of the chunk's voxels as a mask (words of steps not taken
-    // are 0); the hit is its lowest set bit.  Steps before `hit` are free:
-    // none once the ray has hit (hit = 0), all of them if this chunk has no
-    // occupied voxel (hit = kChunk).
-    uint32_t hits = 1u;
-    if (before_hit) {
-        hits = 1u << kChunk;
+    int hit = kChunk;
+    if (c.loaded) {
+        uint32_t hits = 1u << kChunk;
 #pragma unroll
         for (int s = 0; s < kChunk; ++s)
             hits |= bit_of(c.words[s], c.ids[s]) << s;
+        hit = lowest_set(hits);
     }
-    const int hit = lowest_set(hits);
+    if (vg_any(hit < kChunk)) {
 #pragma unroll
-    for (int s = 0; s < kChunk; ++s)
-        store_mark(m, c.ids[s] + (s < hit ? 0u : m.n));
-    return before_hit && hit < kChunk;
+        for (int s = 0; s < kChunk; ++s)
+            store_mark(m, c.ids[s] + (s < hit ? 0u : m.n));
+        if (hit < kChunk) {
+            before_hit = false;
+            w.idx += m.n;
+#pragma unroll
+            for (int s = 0; s < kChunk; ++s) {
+                next.ids[s] += m.n;
+                next.words[s] = 0u;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < kChunk; ++s)
+            store_mark(m, c.ids[s]);
+    }
 }
 
 // Alg. 2 for one ray: walk, test occupancy before the first hit, mark free
@@ -354,14 +406,12 @@ VG_HD void walk_ray(Walk &w, int32_t m2, const WalkMem &m)
     while (true) {
         bool more = alive;
         alive = walk_chunk<kGeneral>(w, m2, alive, b, before_hit, m);
-        if (resolve_chunk(a, before_hit, m))
-            before_hit = false;
+        resolve_chunk(a, before_hit, w, b, m);
         if (!more)
             break;
         more = alive;
         alive = walk_chunk<kGeneral>(w, m2, alive, a, before_hit, m);
-        if (resolve_chunk(b, before_hit, m))
-            before_hit = false;
+        resolve_chunk(b, before_hit, w, a, m);
         if (!more)
             break;
     }

@@ -72,6 +72,7 @@ def lib():
         L.vg_create_grid.argtypes = [i32, i32, i32, f32, P, i32, P, P, ctypes.c_size_t, P,
                                      ctypes.c_size_t, P, ctypes.POINTER(P)]
         L.vg_integrate_frame.argtypes = [P, P, i64, sp, pp, P]
+        L.vg_integrate_frame_shifted.argtypes = [P, P, i64, sp, pp, i32, i32, i32, P]
         L.vg_integrate_points.argtypes = [P, P, i64, sp, pp, P]
         L.vg_shift_grid.argtypes = [P, i32, i32, i32, P]
         L.vg_center_offset.argtypes = [P, P, P]
@@ -91,6 +92,7 @@ def lib():
         L.vg_status_str.argtypes = [i32]
         L.vg_status_str.restype = ctypes.c_char_p
         for name in ("vg_fan_sizes", "vg_create_grid", "vg_integrate_frame",
+                     "vg_integrate_frame_shifted",
                      "vg_integrate_points", "vg_shift_grid", "vg_center_offset",
                      "vg_grid_origin", "vg_read_grid", "vg_write_grid", "vg_destroy_grid",
                      "vg_set_profile_events", "vg_integrate_batch", "vg_set_ray_tile",
@@ -201,6 +203,16 @@ def vg_integrate_frame(g, depth, sensor, pose, stream=None):
     assert depth.dtype.itemsize == 4 and depth.dim() == 2 and depth.stride(1) == 1
     _check(lib().vg_integrate_frame(g, _ptr(depth), depth.stride(0) * 4, ctypes.byref(sensor),
                                     ctypes.byref(pose), _stream(stream)), "vg_integrate_frame")
+
+
+def vg_integrate_frame_shifted(g, depth, sensor, pose, shift, stream=None):
+    """vg_shift_grid(g, *shift) then vg_integrate_frame(g, depth, ...), in one
+    call (the shift's clear runs inside the frame's walk launch)."""
+    assert depth.dtype.itemsize == 4 and depth.dim() == 2 and depth.stride(1) == 1
+    dx, dy, dz = (int(v) for v in shift)
+    _check(lib().vg_integrate_frame_shifted(g, _ptr(depth), depth.stride(0) * 4,
+                                            ctypes.byref(sensor), ctypes.byref(pose), dx, dy, dz,
+                                            _stream(stream)), "vg_integrate_frame_shifted")
 
 
 def vg_integrate_points(g, points, sensor, pose, stream=None):

@@ -399,3 +399,55 @@ def test_ring_buffer_wraps_and_resolves_across_the_seam():
             g.write(g.ref)          # checkpoint round trip: the ring restarts at 0
             g.check("after write")
     g.close()
+
+
+def test_shift_fused_into_the_frame():
+    """vg_integrate_frame_shifted (the shift's clear inside the walk launch)
+    against the oracle's shift-then-integrate: small shifts whose ring offsets
+    wrap (slabs on every axis), a shift past the grid (the whole grid clears),
+    a zero shift; and an out-of-range shift is refused with the grid untouched."""
+    fr = scenes.make_frame("plain-small", 21, size=(64, 48), dims=(45, 38, 21))
+    g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf)
+    rng = np.random.default_rng(41)
+    shifts = [tuple(int(v) for v in rng.integers(-9, 10, 3)) for _ in range(10)]
+    shifts[4] = (0, 0, 0)
+    shifts[7] = (60, -3, 2)          # past the grid along x
+    for k, d in enumerate(shifts):
+        _say(f"fused shift {k} {d}")
+        g.ref = oracle.shift(g.ref, d)
+        g.shift_total += np.asarray(d, np.int32)
+        fr.t = (g.origin() + np.asarray(fr.dims, np.float32) * g.vox_size *
+                rng.uniform(0.3, 0.7, 3).astype(np.float32)).astype(np.float32)
+        dev = torch.from_numpy(fr.depth).cuda()
+        vg.vg_integrate_frame_shifted(g.h, dev, vg.pinhole_sensor(fr.intr),
+                                      vg.make_pose(fr.R, fr.t), d)
+        oracle.integrate_pinhole(g.ref, g.origin(), g.vox_size, g.vox_inf, fr.depth, fr.intr,
+                                 fr.R, fr.t, want_ms=False)
+        g.check(f"fused shift {k}")
+    before = g.read()
+    with pytest.raises(vg.VgError):
+        vg.vg_integrate_frame_shifted(g.h, torch.from_numpy(fr.depth).cuda(),
+                                      vg.pinhole_sensor(fr.intr), vg.make_pose(fr.R, fr.t),
+                                      (1 << 25, 0, 0))
+    assert np.array_equal(g.read(), before)
+    assert np.array_equal(vg.vg_grid_origin(g.h), g.origin())
+    g.close()
+
+
+def test_shift_fused_into_the_medium_frame():
+    """The benchmark's step on full-size frames: random poses, so every shift
+    clears the whole grid inside the walk launch."""
+    frames = [scenes.make_frame("plain-medium", k) for k in (2, 3)]
+    f0 = frames[0]
+    g = GpuGrid(f0.dims, f0.vox_size, f0.origin, f0.vox_inf)
+    for k, fr in enumerate(frames):
+        d = vg.vg_center_offset(g.h, fr.t)
+        _say(f"medium fused shift {d}")
+        g.ref = oracle.shift(g.ref, d)
+        g.shift_total += np.asarray(d, np.int32)
+        vg.vg_integrate_frame_shifted(g.h, torch.from_numpy(fr.depth).cuda(),
+                                      vg.pinhole_sensor(fr.intr), vg.make_pose(fr.R, fr.t), d)
+        oracle.integrate_pinhole(g.ref, g.origin(), g.vox_size, g.vox_inf, fr.depth, fr.intr,
+                                 fr.R, fr.t, want_ms=False)
+        g.check(f"medium fused {k}")
+    g.close()

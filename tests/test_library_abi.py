@@ -113,6 +113,8 @@ def test_null_handle_calls_are_argument_errors():
     assert L.vg_integrate_frame(None, None, 64, ctypes.byref(s), ctypes.byref(pose),
                                 None) == vg.VG_ERR_ARG
     assert L.vg_shift_grid(None, 1, 0, 0, None) == vg.VG_ERR_ARG
+    assert L.vg_integrate_frame_shifted(None, None, 64, ctypes.byref(s), ctypes.byref(pose),
+                                        1, 0, 0, None) == vg.VG_ERR_ARG
     assert L.vg_read_grid(None, None, 1, None) == vg.VG_ERR_ARG
     assert L.vg_destroy_grid(None) == vg.VG_ERR_ARG
     assert vg.vg_status_str(vg.VG_ERR_BUDGET) == "scratch workspace too small"

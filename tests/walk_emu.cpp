@@ -1,10 +1,11 @@
 // Host build of the kernel's ray walk (paper_2112_13169_amd/csrc/vg_walk.h),
 // checked ray by ray against the CPU oracle's walk.  Random grids, random
-// occupancy, random rays from inside and outside the grid.  The occupancy
-// buffer is followed by 64 MiB of all-ones words: steps outside the grid must
-// read nothing from it (as on the device, where a grid of up to 2^30 voxels
-// has that much occupancy plane).  Prints the number of mismatching voxels
-// and exits non-zero if there is any.
+// occupancy, random rays from inside and outside the grid.  In every other
+// trial the lane's wavefront votes at random (vg_host_vote): other lanes may
+// still need occupancy loads after this ray's hit, or force the chunk path
+// with per-step tests.  The occupancy buffer is followed by all-ones words
+// that reads beyond the plane's size must not see.  Prints the number of
+// mismatching voxels and exits non-zero if there is any.
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -23,13 +24,13 @@ static uint32_t rnd()
     return (uint32_t)(rng_state >> 11);
 }
 
+static bool random_vote() { return rnd() % 3 == 0; }
+
 int main(int argc, char **argv)
 {
     const int trials = argc > 1 ? atoi(argv[1]) : 2000;
     rng_state += argc > 2 ? (uint64_t)atoll(argv[2]) : 0;
     long long bad = 0, voxels = 0, steps = 0;
-    // grid words first, then set bits up to and past byte 2^26
-    std::vector<uint32_t> occ(((size_t)1 << 24) + 64, 0xFFFFFFFFu);
     for (int trial = 0; trial < trials; ++trial) {
         // every third trial: a large grid and long rays, so that most chunks
         // take the path without per-step tests
@@ -53,7 +54,10 @@ int main(int argc, char **argv)
         }
         const bool inside = f.v0[0] >= 0 && f.v0[0] < nx && f.v0[1] >= 0 && f.v0[1] < ny &&
                             f.v0[2] >= 0 && f.v0[2] < nz;
-        std::fill(occ.begin(), occ.begin() + (size_t)f.gxp / 32 * ny * nz, 0u);
+        const size_t words = (size_t)f.gxp / 32 * ny * nz;
+        std::vector<uint32_t> occ(words + 4096, 0xFFFFFFFFu);   // the plane, then set words
+        std::fill(occ.begin(), occ.begin() + words, 0u);
+        vg_host_vote = trial % 2 ? random_vote : nullptr;
         std::vector<uint8_t> ms((size_t)nx * ny * nz, 0);
         const uint32_t density = big ? 200 + rnd() % 4000 : 8 + rnd() % 120;
         for (int z = 0; z < nz; ++z)
@@ -82,7 +86,7 @@ int main(int argc, char **argv)
         if (!dead) {
             Walk w;
             walk_setup(w, f, dir);
-            const WalkMem m = walk_mem(occ.data(), (uint32_t)(4 * occ.size()), marks.data(), n, stamp);
+            const WalkMem m = walk_mem(occ.data(), (uint32_t)(4 * words), marks.data(), n, stamp);
             if (inside)
                 walk_ray<false>(w, m2, m);
             else
