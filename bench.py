@@ -206,6 +206,98 @@ def large_frames(n, workers=8):
     return {nm: flat[i * n:(i + 1) * n] for i, nm in enumerate(names)}
 
 
+# The paper's own GPU times for its standard parameters (RTX 2060, Table II):
+# populate occupied 7 us, ray-trace to free 44 us, merge 7 us; 58 us of
+# kernels per frame in all (Sec. V), next to 0.1 / 2.2 / 0.2 ms on one core of
+# an i7-9750H.
+PAPER_STANDARD_US = {"populate": 7.0, "raytrace": 44.0, "merge": 7.0, "kernels": 58.0}
+PAPER_STANDARD_CPU_MS = {"populate": 0.1, "raytrace": 2.2, "merge": 0.2}
+
+
+def run_paper_standard(K, warmup, torch, vg, oracle, scenes):
+    """The paper's standard parameters on the synthetic scene (its Gazebo world
+    is not available): 8 seeded frames of random pose cycled through one grid,
+    re-centred each frame, one frame per call; per-stage times from the
+    stages' own launches beside the paper's Table II, and the grid after one
+    cycle against the oracle."""
+    frames = [scenes.make_frame("paper-standard", k) for k in range(8)]
+    f0 = frames[0]
+    sensor = vg.pinhole_sensor(f0.intr)
+    dev = [torch.from_numpy(f.depth).cuda() for f in frames]
+    poses = [vg.make_pose(f.R, f.t) for f in frames]
+    buf = vg.GridBuffers(f0.dims, f0.vox_inf)
+    h = vg.vg_create_grid(f0.dims, f0.vox_size, f0.origin, f0.vox_inf, buf.loc, buf.spare,
+                          buf.scratch)
+
+    def step(k):
+        i = k % len(frames)
+        vg.vg_integrate_frame_shifted(h, dev[i], sensor, poses[i],
+                                      vg.vg_center_offset(h, frames[i].t))
+
+    # one cycle on the fresh grid against the oracle's shift + integrate
+    ref = np.zeros(f0.dims[::-1], np.uint8)
+    base = f0.origin.astype(np.float32)
+    total = np.zeros(3, np.int32)
+    for k, f in enumerate(frames):
+        d = oracle.center_offset(f0.dims, f0.vox_size, oracle.origin(base, total, f0.vox_size),
+                                 f.t)
+        ref = oracle.shift(ref, d)
+        total = total + np.asarray(d, np.int32)
+        oracle.integrate_pinhole(ref, oracle.origin(base, total, f0.vox_size), f0.vox_size,
+                                 f0.vox_inf, f.depth, f.intr, f.R, f.t, want_ms=False)
+        step(k)
+    got = torch.empty(ref.size, dtype=torch.uint8, device="cuda")
+    vg.vg_read_grid(h, got)
+    torch.cuda.synchronize()
+    same = bool(np.array_equal(got.cpu().numpy(), ref.reshape(-1)))
+
+    # stages timed by their own launches
+    E = vg.PROFILE_EVENTS
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(E * K)]
+    for k in range(warmup):
+        step(k)
+    vg.vg_set_profile_events(h, evs)
+    for k in range(K):
+        step(k)
+    torch.cuda.synchronize()
+    vg.vg_set_profile_events(h, [])
+    stage_us = {}
+    for j, name in enumerate(vg.PROFILE_STAGES):
+        if name != "shift":
+            stage_us[name] = round(float(np.mean([evs[E * k + 2 * j].elapsed_time(
+                evs[E * k + 2 * j + 1]) for k in range(K)])) * 1e3, 2)
+    # whole steps, no events
+    for k in range(warmup):
+        step(k)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for k in range(K):
+        step(k)
+    torch.cuda.synchronize()
+    us = (time.perf_counter() - w0) * 1e6 / K
+    vg.vg_destroy_grid(h)
+    rays = vg.vg_fan_sizes(sensor, f0.vox_size)[3]
+    ours = {"populate": round(stage_us["seed"] + stage_us["dilate"], 2),
+            "raytrace": stage_us["rays"], "merge": stage_us["resolve"]}
+    return {
+        "workload": "the paper's standard parameters: 320x240 depth, 85x101 deg as printed, "
+                    "0.3-6.5 m, 100x100x20 voxels of 0.15 m (200 000), vox_inf 2, "
+                    f"{rays} rays; synthetic scene (ground + 20 boxes, 2 % invalid pixels) "
+                    "for its Gazebo world; each frame re-centres the grid",
+        "steps": K,
+        "us_per_frame": round(us, 2),
+        "frames_per_s": round(1e6 / us, 1),
+        "stage_us": ours,
+        "stage_us_kernels_sum": round(sum(ours.values()), 2),
+        "paper_rtx2060_us": PAPER_STANDARD_US,
+        "paper_i7_one_core_ms": PAPER_STANDARD_CPU_MS,
+        "note": "stage_us: populate = seed + dilation launches, raytrace = walk launch (it "
+                "also runs the re-centring clear), merge = merge launch; each from the "
+                "start of its first launch to the end of its last",
+        "bit_exact": same,
+    }
+
+
 def run_large(seqs, torch, vg, passes=3):
     """Each large sequence into its own 400x400x200 grid, re-centred before
     every frame: one frame per call (shift + integrate) against the whole
@@ -233,8 +325,7 @@ def run_large(seqs, torch, vg, passes=3):
 
         def plain_pass():
             for f, d, p in zip(frames, dev, poses):
-                vg.vg_shift_grid(ha, *vg.vg_center_offset(ha, f.t))
-                vg.vg_integrate_frame(ha, d, sensor, p)
+                vg.vg_integrate_frame_shifted(ha, d, sensor, p, vg.vg_center_offset(ha, f.t))
 
         def batch_pass():
             shifts = vg.sequence_shifts(hb, [f.t for f in frames])
@@ -423,6 +514,8 @@ def main():
     ap.add_argument("--serve-frames", type=int, default=60, help="frames per robot")
     ap.add_argument("--large-frames", type=int, default=8,
                     help="frames per large sequence (0 skips the large runs)")
+    ap.add_argument("--paper-steps", type=int, default=200,
+                    help="steps of the paper's standard parameters (0 skips them)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -742,6 +835,11 @@ def main():
                      "re-centred before every frame",
             **run_large(large, torch, vg))
         print(f"# large runs in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    if args.paper_steps > 0:
+        t0 = time.time()
+        import oracle
+        out["paper_standard"] = run_paper_standard(args.paper_steps, 20, torch, vg, oracle, scenes)
+        print(f"# paper-standard runs in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     print(json.dumps(out))
 
 

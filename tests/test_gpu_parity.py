@@ -451,3 +451,16 @@ def test_shift_fused_into_the_medium_frame():
                                  fr.R, fr.t, want_ms=False)
         g.check(f"medium fused {k}")
     g.close()
+
+
+@pytest.mark.parametrize("index", range(3))
+def test_paper_standard_frames(index):
+    """The paper's standard parameters (320x240, 85 x 101 deg, 6.5 m, 100 x 100
+    x 20 voxels of 0.15 m, vox_inf 2; 8 295 rays) on the synthetic scene."""
+    fr = scenes.make_frame("paper-standard", index)
+    _say(f"paper-standard frame {index}")
+    g = GpuGrid(fr.dims, fr.vox_size, fr.origin, fr.vox_inf)
+    _, st = g.integrate(fr)
+    assert st["rays"] == _fan_rays(fr) == 8295
+    g.check(f"paper-standard {index}")
+    g.close()
