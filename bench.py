@@ -516,6 +516,9 @@ def main():
                     help="frames per large sequence (0 skips the large runs)")
     ap.add_argument("--paper-steps", type=int, default=200,
                     help="steps of the paper's standard parameters (0 skips them)")
+    ap.add_argument("--paper-only", action="store_true",
+                    help="run the paper's standard parameters alone (for a kernel trace of "
+                         "that workload) and print their section")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -551,6 +554,11 @@ def main():
         sys.exit(2)
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.paper_only:
+        import oracle
+        print(json.dumps({"paper_standard": run_paper_standard(max(args.paper_steps, 1), 20,
+                                                                torch, vg, oracle, scenes)}))
+        return
 
     # ---- inputs: seeded frame pool, resident on the GPU
     t0 = time.time()
