@@ -53,6 +53,7 @@ ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 CAL_BYTES = 64 << 20            # calibration copy: 64 MiB read + 64 MiB written
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+TRAFFIC_FILE_BATCHED = os.path.join(ROOT, "profiles", "traffic_batched.json")
 
 
 STAGE_KERNELS = {"k_dilate": ["k_dilate_x", "k_dilate_yz", "k_dilate_yz_tile<8>",
@@ -60,17 +61,17 @@ STAGE_KERNELS = {"k_dilate": ["k_dilate_x", "k_dilate_yz", "k_dilate_yz_tile<8>"
                  "k_rays": ["k_rays<false>", "k_rays<true>"]}
 
 
-def measured_traffic(stage):
+def measured_traffic(stage, path=TRAFFIC_FILE, workload=WORKLOAD):
     """Memory-side bytes per launch of a stage's kernels from the committed
     counter summary, or None if absent or taken on kernel sources that have
     changed since."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
     from paper_2112_13169_amd.prof_summary import kernel_source_hash
-    if t.get("source_hash") != kernel_source_hash() or t.get("workload") != WORKLOAD:
+    if t.get("source_hash") != kernel_source_hash() or t.get("workload") != workload:
         return None
     got = [t["kernels"][k]["hbm_bytes_per_launch"] for k in STAGE_KERNELS.get(stage, [stage])
            if k in t.get("kernels", {})]
@@ -367,7 +368,7 @@ def run_large(seqs, torch, vg, passes=3):
 
 
 def run_batched(frames, K, warmup, torch, vg, oracle, autotune, sample_oracle=(),
-                walk_steps=None):
+                walk_steps=None, tune=True):
     """Batched vs plain on the same frames, each frame with its own grid: one
     vg_integrate_batch call per step against len(frames) vg_integrate_frame
     calls per step.  Returns the figures of both and whether they agree."""
@@ -417,7 +418,7 @@ def run_batched(frames, K, warmup, torch, vg, oracle, autotune, sample_oracle=()
     # of the class, for the batch on the batched walk launch
     samples = [(s, f.vox_size, hb, (lambda hb=hb, d=d, s=s, p=p: vg.vg_integrate_frame(hb, d, s, p)))
                for (_, hb), d, s, p, f in zip(B, dev, sensors, poses, frames)]
-    table = autotune.tune(samples, vg, torch, reps=3)
+    table = autotune.tune(samples, vg, torch, reps=3) if tune else {}
     for (_, hb), s, f in zip(B, sensors, frames):
         vg.vg_set_ray_tile(hb, autotune.choose(table, s, f.vox_size, vg))
 
@@ -438,7 +439,7 @@ def run_batched(frames, K, warmup, torch, vg, oracle, autotune, sample_oracle=()
     classes = {}
     for (_, ha), s, f in zip(A, sensors, frames):
         classes.setdefault(autotune.fan_class(s, f.vox_size, vg), []).append(ha)
-    btable = autotune.tune_batch(classes, vg.vg_set_ray_tile, batch_rays_ms, reps=3)
+    btable = autotune.tune_batch(classes, vg.vg_set_ray_tile, batch_rays_ms, reps=3) if tune else {}
 
     def timed(step):
         for _ in range(warmup):
@@ -491,7 +492,9 @@ def run_batched(frames, K, warmup, torch, vg, oracle, autotune, sample_oracle=()
         achieved = units * OPS_PER_STEP / (rays_ms * 1e-3) / 1e12
         result["roofline"] = {"bound": "alu", "achieved": round(achieved, 3),
                               "peak": round(ALU_PEAK_TOPS, 1), "unit": "TOP/s",
-                              "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": None,
+                              "frac": round(achieved / ALU_PEAK_TOPS, 4),
+                              "traffic": measured_traffic("kb_rays", TRAFFIC_FILE_BATCHED,
+                                                          "batched-x16"),
                               "kernel": "kb_rays", "units_per_launch": units,
                               "unit_kind": "in-grid walk steps", "ops_per_unit": OPS_PER_STEP,
                               "kernel_ms": round(rays_ms, 5)}
@@ -509,6 +512,10 @@ def main():
     ap.add_argument("--batch", type=int, default=64,
                     help="frames per batch of the batch recipe (0 skips the batched runs)")
     ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--no-recipe", action="store_true",
+                    help="batched runs: the 16 medium frames only (for a counter run of them)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="batched runs: the default 8x8 ray tile, no tuning runs")
     ap.add_argument("--serve-robots", type=int, default=16,
                     help="robots of the served runs (0 skips them)")
     ap.add_argument("--serve-frames", type=int, default=60, help="frames per robot")
@@ -529,7 +536,7 @@ def main():
 
     # batch-recipe frames are rendered in worker processes before the GPU is used
     t0 = time.time()
-    recipe = batch_recipe_frames(args.batch)
+    recipe = batch_recipe_frames(0 if args.no_recipe else args.batch)
     if recipe:
         print(f"# generated {len(recipe)} batch-recipe frames in {time.time() - t0:.1f}s",
               file=sys.stderr, flush=True)
@@ -816,14 +823,15 @@ def main():
             "plain-medium x16": dict(
                 workload="16 plain-medium frames per step, each into its own 200x200x100 grid",
                 **run_batched(x16, args.batch_steps * 4, 3, torch, vg, oracle, autotune,
-                              walk_steps=walk16)),
-            "batch-recipe": dict(
+                              walk_steps=walk16, tune=not args.no_tune)),
+        }
+        if recipe:
+            out["batched"]["batch-recipe"] = dict(
                 workload=f"{len(recipe)} independent frames per step: 320x240..1280x720, range "
                          "to U[4,10] m, random 6-DoF poses, own grids of gx=gy in 100..256, gz "
                          "in 100..128 at 0.05-0.1 m, vox_inf 1-3",
                 **run_batched(recipe, args.batch_steps, 2, torch, vg, oracle, autotune,
-                              sample_oracle=(0, len(recipe) - 1))),
-        }
+                              sample_oracle=(0, len(recipe) - 1), tune=not args.no_tune))
         print(f"# batched runs in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
     if fleet:
         t0 = time.time()

@@ -7,8 +7,8 @@ Inputs are three rocprofv3 runs of the same benchmark command:
   --kernel-trace --stats --output-format csv      (durations)
   --pmc FETCH_SIZE --output-format csv            (KiB read per dispatch)
   --pmc WRITE_SIZE --output-format csv            (KiB written per dispatch)
-The benchmark ends with an untimed device copy of a known size; its counter
-readings give the factor that turns each counter into bytes (on gfx950
+The benchmark runs an untimed device copy of a known size (the run's largest
+copy); its counter readings give the factor that turns each counter into bytes (on gfx950
 FETCH_SIZE reads half the bytes a streaming copy moves; WRITE_SIZE reads them
 all).  Counter bytes are what the L2 exchanged with the memory side (HBM, or
 the last-level cache in front of it).
@@ -78,6 +78,10 @@ def read_stats(kt_dir):
     return out
 
 
+# MI355X HBM3E peak, GB/s (vendor figure)
+HBM_PEAK_GBS = 8000.0
+
+
 def read_counter(pmc_dir, counter):
     """Per-kernel list of (grid size, KiB) of each dispatch, in dispatch order."""
     rows = []
@@ -94,11 +98,13 @@ def read_counter(pmc_dir, counter):
 
 
 def calibration(rows, cal_bytes):
-    """Counter KiB of the last copy kernel dispatch (the calibration copy)."""
+    """Counter KiB of the calibration copy: the largest plain copy kernel
+    dispatch of the run (the benchmark's copy is many times larger than its
+    frame uploads and grid reads)."""
     copies = [r for r in rows if "copyBuffer" in r[1] and "Rect" not in r[1]]
     if not copies:
         raise SystemExit("no calibration copy in the counter run")
-    kib = copies[-1][3]
+    kib = max(r[3] for r in copies)
     return (cal_bytes / 1024.0) / kib, kib
 
 
@@ -135,29 +141,34 @@ def main(argv=None):
                   f"WRITE_SIZE x {w_fac:.4f} KiB.", ""]
     lines += [f"Kernel sources hash (code without comments): `{kernel_source_hash()}`", "",
               "| kernel | launches | avg us | min us | max us | % time | FETCH KiB | WRITE KiB "
-              "| bytes/launch (calibrated) |",
-              "|---|---|---|---|---|---|---|---|---|"]
+              "| bytes/launch (calibrated) | GB/s | of HBM peak |",
+              "|---|---|---|---|---|---|---|---|---|---|---|"]
     for k, s in sorted(stats.items(), key=lambda kv: -kv[1]["pct"]):
         fk = [v for _, v in fetch.get(k, [])]
         wk = [v for _, v in write.get(k, [])]
         fr = sum(fk) / len(fk) if fk else None
         wr = sum(wk) / len(wk) if wk else None
-        nbytes = None
+        nbytes = gbs = None
         if fr is not None and wr is not None:
             nbytes = 1024.0 * (fr * f_fac + wr * w_fac)
-            if k.startswith("k_"):
+            gbs = nbytes / s["avg_ns"]          # bytes per ns = GB/s
+            if k.startswith(("k_", "kb_")):
                 kernels[k] = dict(hbm_bytes_per_launch=round(nbytes), fetch_kib=round(fr, 1),
-                                  write_kib=round(wr, 1), avg_us=round(s["avg_ns"] / 1e3, 3))
+                                  write_kib=round(wr, 1), avg_us=round(s["avg_ns"] / 1e3, 3),
+                                  gb_per_s=round(gbs, 1), hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
         lines.append(f"| `{k}` | {s['calls']} | {s['avg_ns'] / 1e3:.2f} | {s['min_ns'] / 1e3:.2f} | "
                      f"{s['max_ns'] / 1e3:.2f} | {s['pct']:.1f} | "
                      f"{'-' if fr is None else f'{fr:.1f}'} | {'-' if wr is None else f'{wr:.1f}'} | "
-                     f"{'-' if nbytes is None else f'{nbytes / 1e6:.3f} MB'} |")
+                     f"{'-' if nbytes is None else f'{nbytes / 1e6:.3f} MB'} | "
+                     f"{'-' if gbs is None else f'{gbs:.0f}'} | "
+                     f"{'-' if gbs is None else f'{gbs / HBM_PEAK_GBS:.3f}'} |")
     lines.append("")
     with open(a.md, "w") as fh:
         fh.write("\n".join(lines))
     if counters and a.json:
         with open(a.json, "w") as fh:
             json.dump(dict(workload=a.workload, source_hash=kernel_source_hash(),
+                           hbm_peak_gbs=HBM_PEAK_GBS,
                            fetch_factor=round(f_fac, 4), write_factor=round(w_fac, 4),
                            kernels=kernels), fh, indent=1)
             fh.write("\n")

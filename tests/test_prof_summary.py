@@ -34,6 +34,9 @@ def test_summary_calibrates_counters_by_the_copy(tmp_path):
                  40, counter, rays_kib, 0, 1] for i in range(1, 4)]
         rows.append([9, 9, "Agent 1", 1, 1, 1, 131072, 2, "__amd_rocclr_copyBuffer", 256, 0, 0,
                      8, 0, 16, counter, copy_kib, 0, 1])
+        # a later, smaller copy (a frame upload) must not be taken for the calibration
+        rows.append([10, 10, "Agent 1", 1, 1, 1, 4096, 2, "__amd_rocclr_copyBuffer", 256, 0, 0,
+                     8, 0, 16, counter, copy_kib / 50, 0, 1])
         _write(str(tmp_path / name / "pmc_counter_collection.csv"), hdr, rows)
 
     # a 1 MiB copy reads as 512 KiB fetched (factor 2) and 1024 KiB written
@@ -46,6 +49,9 @@ def test_summary_calibrates_counters_by_the_copy(tmp_path):
     t = json.loads(js.read_text())
     assert t["fetch_factor"] == 2.0 and t["write_factor"] == 1.0
     assert t["kernels"]["k_rays<false>"]["hbm_bytes_per_launch"] == 1024 * (100 * 2 + 300)
+    # 512 000 bytes in the kernel's 30 us average: 17.07 GB/s
+    assert t["kernels"]["k_rays<false>"]["gb_per_s"] == round(512000 / 30000, 1)
+    assert t["hbm_peak_gbs"] == 8000.0
     assert t["source_hash"] == ps.kernel_source_hash()
     text = md.read_text()
     assert "`k_rays<false>`" in text and "cmd" in text
