@@ -217,7 +217,10 @@ size_t vg_batch_workspace_bytes(int32_t max_frames);
  * current device; frames of one grid are applied in their order.  Frames of
  * distinct grids run together: frame i belongs to round k if k earlier
  * frames target its grid, and each round is one launch per stage over all
- * its frames, whatever their image sizes, sensors, poses and grid sizes.
+ * its frames, whatever their image sizes, sensors, poses and grid sizes.  A
+ * round of a single frame runs the one-frame launches instead (the shift's
+ * clear inside its walk launch, as vg_integrate_frame_shifted), unless
+ * stage events are given (vg_integrate_batch_timed).
  *   workspace: device, 256-byte aligned, workspace_bytes >=
  *     vg_batch_workspace_bytes(n_frames) (else VG_ERR_BUDGET).  The frame
  *     tables are written into it through kernel arguments (no host staging

@@ -1078,16 +1078,41 @@ vg_status vg_integrate_batch_timed(const vg_frame *frames, int32_t n_frames, voi
         }
     }
 
+    // A round of one frame (untimed) runs the one-frame launches instead: no
+    // table, the shift's clear inside the walk launch.
+    std::vector<uint8_t> direct((size_t)rounds);
+    bool all_direct = true;
+    for (int32_t r = 0; r < rounds; ++r) {
+        direct[(size_t)r] = !events && members[(size_t)r].size() == 1;
+        all_direct = all_direct && direct[(size_t)r];
+    }
+
     // Upload the tables, then per round: per-frame preparation and one
     // launch per stage.
     uint8_t *ws = static_cast<uint8_t *>(workspace);
-    hipError_t e = launch_upload(reinterpret_cast<uint32_t *>(ws), host.data(), host.size(), st);
+    hipError_t e = all_direct ? hipSuccess
+                              : launch_upload(reinterpret_cast<uint32_t *>(ws), host.data(),
+                                              host.size(), st);
     for (int32_t r = 0; r < rounds && e == hipSuccess; ++r) {
         const std::vector<int32_t> &mem = members[(size_t)r];
         const int32_t m = (int32_t)mem.size();
         for (int32_t i : mem)
             if (e == hipSuccess)
                 e = prepare_frame(grids[(size_t)grid_of[i]], plans[(size_t)i], st);
+        if (direct[(size_t)r]) {
+            const int32_t i = mem[0];
+            const FramePlan &p = plans[(size_t)i];
+            const vg_grid *g = grids[(size_t)grid_of[i]];
+            if (e == hipSuccess)
+                e = launch_seeds(p.sp, st);
+            if (e == hipSuccess)
+                e = launch_dilate(p.sp.pl, st);
+            if (e == hipSuccess)
+                e = launch_rays(p.rp, p.inside, st, {}, moved_of[i] ? &clears[i] : nullptr);
+            if (e == hipSuccess)
+                e = launch_resolve(p.sp.pl, g->loc, p.rows, p.ring, st);
+            continue;
+        }
         const int32_t *start = reinterpret_cast<const int32_t *>(ws + table_at[(size_t)r]);
         const FrameDesc *fd =
             reinterpret_cast<const FrameDesc *>(ws + table_at[(size_t)r] + batch_starts_bytes(m));
