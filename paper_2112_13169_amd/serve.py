@@ -159,6 +159,13 @@ class Server:
         protected = {q.robot for q in self.queue}   # robots with frames waiting keep their grids
         kept = collections.deque()
         while self.queue:
+            if (len(batch) >= self.max_batch or
+                    len(in_batch) + len(skipped_robots) >= len(self.robots)):
+                # nothing further can join: every robot is in the batch or
+                # blocked behind an earlier frame (the rest keeps its order)
+                kept.extend(self.queue)
+                self.queue.clear()
+                break
             q = self.queue.popleft()
             r = self.robots[q.robot]
             # one frame per robot per batch: the next one is re-centred on the
@@ -322,19 +329,26 @@ class GpuBackend:
     def launch(self, s, batch, waits):
         torch, vg = self.torch, self.vg
         st = self.streams[s]
-        for e in waits:
-            st.wait_event(e)
         with torch.cuda.stream(st):
-            descs = []
+            # the uploads depend on no grid: they go first, so that they overlap
+            # the other stream's batch; the integration then waits for the
+            # robots' previous frames
+            devs = []
             for j, q in enumerate(batch):
                 fr = self.frames[q.robot][q.index]
-                r = self.robots[q.robot]
                 if self.slots is not None:
                     d = self.slots[s][j]
                 else:
                     d = torch.empty(fr.depth.shape, dtype=torch.float32, device="cuda")
                     self.dev[(q.robot, q.index)] = d
                 d.copy_(self.host[q.robot][q.index], non_blocking=True)
+                devs.append(d)
+            for e in waits:
+                st.wait_event(e)
+            descs = []
+            for q, d in zip(batch, devs):
+                fr = self.frames[q.robot][q.index]
+                r = self.robots[q.robot]
                 shift = vg.vg_center_offset(r.handle, fr.t)
                 descs.append(vg.frame_image(r.handle, d, self.sensor,
                                             self.poses[q.robot][q.index], shift))

@@ -165,3 +165,31 @@ def test_latency_summary_and_arrivals():
     reqs = [serve.Request(0, k, 0.0, 0.0, 0.001 * (k + 1)) for k in range(100)]
     s = serve.latency_summary(reqs)
     assert abs(s["p50_ms"] - 50.5) < 1e-6 and abs(s["max_ms"] - 100.0) < 1e-9
+
+
+class CountingDeque(__import__("collections").deque):
+    pops = 0
+
+    def popleft(self):
+        CountingDeque.pops += 1
+        return super().popleft()
+
+
+def test_admission_stops_scanning_once_no_frame_can_join():
+    """With every robot's frames queued at once, forming a batch looks at one
+    frame per robot (plus those blocked behind it), not the whole queue, and
+    leaves the rest in order."""
+    be = FakeBackend(np.random.default_rng(4))
+    srv = serve.Server(be, _robots(4), 10, 10 ** 6, max_batch=64, streams=1)
+    for k in range(200):
+        for rid in range(4):
+            srv.arrive(serve.Request(rid, k, 0.0))
+    srv.queue = CountingDeque(srv.queue)
+    CountingDeque.pops = 0
+    assert srv.launch(0.0) == 4
+    assert CountingDeque.pops <= 8
+    # the frames left keep their arrival order, robot by robot
+    rest = list(srv.queue)
+    assert len(rest) == 4 * 199
+    for rid in range(4):
+        assert [q.index for q in rest if q.robot == rid] == list(range(1, 200))
