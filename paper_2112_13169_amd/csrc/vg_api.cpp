@@ -407,13 +407,20 @@ struct FramePlan {
     bool inside;
     bool wrap;        // the stamp planes must be cleared first (stamp wrapped)
     bool upload_hz;   // the spinning fan table must be (re)written
+    bool direct;      // occupied cubes stamped directly into bytes (no dilation)
     uint32_t epoch;
     int32_t ring[3];  // ring offsets of the grid when the frame merges
 };
 
+// Stamping each point's (2 vox_inf + 1)^3 cube directly costs that many
+// byte stores per point; the separable dilation costs three launches over the
+// seed box.  Frames whose points times cube stay below this stamp directly
+// (one launch) when walked one per call.
+constexpr int64_t kDirectStores = 16 << 20;
+
 vg_status plan_frame(const vg_grid *g, const GridState &gs, int kind, const float *data,
                      int64_t pitch_floats, int32_t W, int32_t H, const vg_sensor *sensor,
-                     const vg_pose *T, FramePlan &p)
+                     const vg_pose *T, FramePlan &p, bool allow_direct = false)
 {
     p.kind = kind;
     if (!fan_for(*sensor, g->s, p.fan))
@@ -465,6 +472,9 @@ vg_status plan_frame(const vg_grid *g, const GridState &gs, int kind, const floa
     pl.nbytes = (uint32_t)((size_t)g->lay.gxp * g->n[1] * g->n[2]);
     seed_box(g, kind, *sensor, *T, tv, pl.lo, pl.hi);
     pl.epoch = p.epoch;
+    const int64_t side = 2 * g->r + 1;
+    p.direct = allow_direct && (int64_t)W * H * side * side * side <= kDirectStores;
+    pl.occb = p.direct ? pl.seed : nullptr;   // grid-layout stamps in the seed plane's place
 
     SeedParams &sp = p.sp;
     sp.pl = pl;
@@ -501,8 +511,9 @@ vg_status plan_frame(const vg_grid *g, const GridState &gs, int kind, const floa
     rp.tiles_a = (fan_a + tw - 1) / tw;
     rp.tiles = (int32_t)tiles;
     rp.hz = reinterpret_cast<const int32_t *>(g->scratch + g->lay.hz);
-    rp.occ = pl.occ;
-    rp.occ_bytes = pl.nbytes / 8;
+    rp.occ = p.direct ? static_cast<const void *>(pl.occb) : static_cast<const void *>(pl.occ);
+    rp.occ_bytes = p.direct ? pl.nbytes : pl.nbytes / 8;
+    rp.occ_is_bytes = p.direct ? 1 : 0;
     rp.marks = pl.marks;
     rp.nbytes = pl.nbytes;
     rp.epoch = p.epoch;
@@ -614,7 +625,7 @@ vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_float
         clear.loc = g->loc;
     }
     FramePlan p;
-    vg_status rc = plan_frame(g, gs, kind, data, pitch_floats, W, H, sensor, T, p);
+    vg_status rc = plan_frame(g, gs, kind, data, pitch_floats, W, H, sensor, T, p, true);
     if (rc != VG_OK)
         return rc;
     if (!same_device(g))
@@ -632,8 +643,9 @@ vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_float
         e = record_empty_stage(stage(kStageShift), st);
     if (e == hipSuccess)
         e = launch_seeds(p.sp, st, stage(kStageSeed));
-    if (e == hipSuccess)
-        e = launch_dilate(p.sp.pl, st, stage(kStageDilate));
+    if (e == hipSuccess)   // direct stamping has nothing to dilate
+        e = p.direct ? record_empty_stage(stage(kStageDilate), st)
+                     : launch_dilate(p.sp.pl, st, stage(kStageDilate));
     if (e == hipSuccess)
         e = launch_rays(p.rp, p.inside, st, stage(kStageRays), shifted ? &clear : nullptr);
     if (e == hipSuccess)

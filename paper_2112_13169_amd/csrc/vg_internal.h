@@ -55,6 +55,9 @@ struct Planes {
     uint8_t *seed;       // seed stamps, [pz][py][seed_pitch]
     uint32_t *bitx;      // seeds dilated along x, [pz][py][wx] words
     uint32_t *occ;       // occupied voxels of the frame, bit i = grid index i
+    uint8_t *occb;       // or (direct stamping, non-null) the frame's stamp at
+                         // byte i for an occupied voxel of grid index i; it
+                         // takes the seed plane's place
     uint8_t *marks;      // free stamps [0, nbytes), "unknown and traced" stamps
                          // [nbytes, 2 nbytes), one byte per grid index each
     uint32_t nbytes;     // bytes of the device-layout grid
@@ -62,7 +65,8 @@ struct Planes {
     uint32_t epoch;      // stamp of this frame (1..255)
 };
 
-// Step 2a: transform and quantise every measured point, stamp its voxel.
+// Step 2a: transform and quantise every measured point, stamp its voxel (or,
+// with Planes::occb, every voxel of its cube).
 struct SeedParams {
     Planes pl;
     float R[9];       // R^v_c = R^w_c, row-major
@@ -90,8 +94,9 @@ struct RayParams {
     int32_t tile_log2w;   // 0..6
     int32_t tiles_a, tiles;
     const int32_t *hz;    // spinning: half height per column
-    const uint32_t *occ;
+    const void *occ;      // occupancy: bits, or stamp bytes if occ_is_bytes
     uint32_t occ_bytes;
+    int32_t occ_is_bytes;
     uint8_t *marks;       // as Planes::marks
     uint32_t nbytes;
     uint32_t epoch;

@@ -6,7 +6,9 @@
 //   k_seed        Alg. 1, transform and quantise: one lane per pixel / point: unproject,
 //                 transform, quantise; stamp the point's voxel in a seed plane
 //                 padded by vox_inf (byte stores of the frame's stamp: no
-//                 clearing between frames, no atomics).
+//                 clearing between frames, no atomics).  For small frames it
+//                 stamps the point's whole cube into a byte occupancy plane
+//                 instead, and the two dilations do not run.
 //   k_dilate_x    Alg. 1, inflation, separably: seeds -> bits dilated by
 //   k_dilate_yz   vox_inf along x, then along y and z.  The union of the
 //                 (2 vox_inf + 1)^3 cubes is exactly this separable dilation.
@@ -141,17 +143,21 @@ __global__ __launch_bounds__(kBlock) void k_fill(uint8_t *dst, uint8_t value, si
 
 // Alg. 1, transform and quantise.  Images: block = 64 x 4 pixels (bx, by), one wavefront
 // per image row segment (coalesced row reads).  Points: 256 points per block.
-__device__ __forceinline__ void seed_body(const SeedParams &p, int32_t bx, int32_t by)
+// The point of lane (bx, by, threadIdx.x): its padded voxel coordinates, or
+// false if it has none (no pixel, invalid depth, or a cube that cannot reach
+// the grid).
+__device__ __forceinline__ bool seed_point(const SeedParams &p, int32_t bx, int32_t by,
+                                           int32_t pp[3])
 {
     float pc[3];
     if (p.kind == kPoints) {
         int64_t i = (int64_t)bx * kBlock + threadIdx.x;
         if (i >= p.W)
-            return;
+            return false;
         const float *q = p.img + 3 * i;
         float x = q[0], y = q[1], z = q[2];
         if (!(__builtin_isfinite(x) && __builtin_isfinite(y) && __builtin_isfinite(z)))
-            return;
+            return false;
         pc[0] = x;
         pc[1] = y;
         pc[2] = z;
@@ -159,10 +165,10 @@ __device__ __forceinline__ void seed_body(const SeedParams &p, int32_t bx, int32
         int32_t u = bx * 64 + (threadIdx.x & 63);
         int32_t v = by * 4 + (threadIdx.x >> 6);
         if (u >= p.W || v >= p.H)
-            return;
+            return false;
         float d = p.img[(int64_t)v * p.pitch + u];
         if (!(d >= p.dmin && d <= p.dmax))
-            return;
+            return false;
         if (p.kind == kPinhole) {
             // pixel slopes in double, rounded once
             float ku = (float)(((double)u - p.cx) / p.fx);
@@ -179,19 +185,43 @@ __device__ __forceinline__ void seed_body(const SeedParams &p, int32_t bx, int32
             pc[2] = d * se;
         }
     }
-
     const Planes &pl = p.pl;
-    int32_t pp[3];
     for (int a = 0; a < 3; ++a) {
         float pv = row_dot(p.R + 3 * a, pc[0], pc[1], pc[2]) + p.tv[a];
         float q = floorf(pv / p.s);
         // the cube cannot reach the grid: drop the point
         if (!(q >= (float)(-pl.r) && q <= (float)(pl.n[a] - 1 + pl.r)))
-            return;
+            return false;
         pp[a] = (int32_t)q + pl.r;   // padded coordinate
     }
-    pl.seed[(int64_t)pl.seed_pitch * (pp[1] + (int64_t)pl.py * pp[2]) + pp[0]] =
-        (uint8_t)pl.epoch;
+    return true;
+}
+
+__device__ __forceinline__ void seed_body(const SeedParams &p, int32_t bx, int32_t by)
+{
+    const Planes &pl = p.pl;
+    int32_t pp[3] = {0, 0, 0};
+    const bool ok = seed_point(p, bx, by, pp);
+    if (!pl.occb) {
+        if (ok)
+            pl.seed[(int64_t)pl.seed_pitch * (pp[1] + (int64_t)pl.py * pp[2]) + pp[0]] =
+                (uint8_t)pl.epoch;
+        return;
+    }
+    // Stamp the cube of the point's voxel, clipped to the grid: padded
+    // coordinates pp - r .. pp + r are grid coordinates pp - 2r .. pp.
+    if (!ok)
+        return;
+    const int32_t gxp = pl.wx * 32;
+    const int32_t x0 = max(pp[0] - 2 * pl.r, 0), x1 = min(pp[0], pl.n[0] - 1);
+    const int32_t y0 = max(pp[1] - 2 * pl.r, 0), y1 = min(pp[1], pl.n[1] - 1);
+    const int32_t z0 = max(pp[2] - 2 * pl.r, 0), z1 = min(pp[2], pl.n[2] - 1);
+    for (int32_t z = z0; z <= z1; ++z)
+        for (int32_t y = y0; y <= y1; ++y) {
+            uint8_t *row = pl.occb + (int64_t)gxp * (y + (int64_t)pl.n[1] * z);
+            for (int32_t x = x0; x <= x1; ++x)
+                row[x] = (uint8_t)pl.epoch;
+        }
 }
 
 // Seeds -> bits dilated along x.  One lane per 32-voxel word of a padded row
@@ -321,7 +351,7 @@ __device__ __forceinline__ void dilate_yz_tile_body(const Planes &pl, int32_t ti
 }
 
 // Alg. 2 for the 64 rays of fan tile `tile` (one wavefront).
-template <bool kGeneral>
+template <bool kGeneral, bool kBytes>
 __device__ __forceinline__ void rays_body(const RayParams &p, int32_t tile)
 {
     const int lane = threadIdx.x & 63;
@@ -340,7 +370,8 @@ __device__ __forceinline__ void rays_body(const RayParams &p, int32_t tile)
         return;
     Walk w;
     walk_setup(w, p.wf, dir);
-    walk_ray<kGeneral>(w, m2, walk_mem(p.occ, p.occ_bytes, p.marks, p.nbytes, p.epoch & 0xFFu));
+    walk_ray<kGeneral, kBytes>(w, m2,
+                               walk_mem(p.occ, p.occ_bytes, p.marks, p.nbytes, p.epoch & 0xFFu));
 }
 
 // (v + r) mod n for v, r in [0, n).
@@ -401,7 +432,13 @@ __device__ __forceinline__ void resolve_body(const Planes &pl, uint8_t *loc, con
     if ((x0 & 15) == 0 && x0 + nvalid <= gx) {
         // one run of grid columns starting on a 16-column boundary
         const int64_t b = prow + x0;
-        occ16 = (pl.occ[b >> 5] >> (b & 16)) & 0xFFFFu;
+        if (pl.occb) {
+            const uint4 oc = *reinterpret_cast<const uint4 *>(pl.occb + b);
+            occ16 = byte_eq_mask(oc.x, rep) | (byte_eq_mask(oc.y, rep) << 4) |
+                    (byte_eq_mask(oc.z, rep) << 8) | (byte_eq_mask(oc.w, rep) << 12);
+        } else {
+            occ16 = (pl.occ[b >> 5] >> (b & 16)) & 0xFFFFu;
+        }
         const uint4 fr = *reinterpret_cast<const uint4 *>(pl.marks + b);
         const uint4 tr = *reinterpret_cast<const uint4 *>(pl.marks + pl.nbytes + b);
         tr16 = byte_eq_mask(tr.x, rep) | (byte_eq_mask(tr.y, rep) << 4) |
@@ -410,8 +447,13 @@ __device__ __forceinline__ void resolve_body(const Planes &pl, uint8_t *loc, con
                (byte_eq_mask(fr.z, rep) << 8) | (byte_eq_mask(fr.w, rep) << 12);
     } else if (x0 + nvalid <= gx) {
         const int64_t b = prow + x0;
-        const uint64_t two = (uint64_t)pl.occ[b >> 5] | ((uint64_t)pl.occ[(b >> 5) + 1] << 32);
-        occ16 = (uint32_t)(two >> (b & 31)) & 0xFFFFu;
+        if (pl.occb) {
+            occ16 = stamp_mask16(pl.occb + b, rep);
+        } else {
+            const uint64_t two =
+                (uint64_t)pl.occ[b >> 5] | ((uint64_t)pl.occ[(b >> 5) + 1] << 32);
+            occ16 = (uint32_t)(two >> (b & 31)) & 0xFFFFu;
+        }
         fr16 = stamp_mask16(pl.marks + b, rep);
         tr16 = stamp_mask16(pl.marks + pl.nbytes + b, rep);
     } else {
@@ -422,7 +464,8 @@ __device__ __forceinline__ void resolve_body(const Planes &pl, uint8_t *loc, con
             if (x >= gx)
                 x -= gx;
             const int64_t b = prow + x;
-            occ16 |= ((pl.occ[b >> 5] >> (b & 31)) & 1u) << j;
+            occ16 |= (pl.occb ? (uint32_t)(pl.occb[b] == e) : (pl.occ[b >> 5] >> (b & 31)) & 1u)
+                     << j;
             tr16 |= (uint32_t)(pl.marks[pl.nbytes + b] == e) << j;
             fr16 |= (uint32_t)(pl.marks[b] == e) << j;
         }
@@ -509,14 +552,14 @@ __global__ __launch_bounds__(kBlock) void k_dilate_yz_tile(Planes pl)
 
 // The walk; workgroups from ray_blocks on run the slab clear c instead (the
 // walk leaves most compute units idle for its longest rays).
-template <bool kGeneral>
+template <bool kGeneral, bool kBytes>
 __global__ __launch_bounds__(kBlock) void k_rays(RayParams p, SlabClear c, int32_t ray_blocks)
 {
     if ((int32_t)blockIdx.x >= ray_blocks) {
         clear_body(c, (int64_t)(blockIdx.x - ray_blocks) * kBlock + threadIdx.x);
         return;
     }
-    rays_body<kGeneral>(p, blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6));
+    rays_body<kGeneral, kBytes>(p, blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6));
 }
 
 __global__ __launch_bounds__(kBlock) void k_resolve(Planes pl, uint8_t *loc, RowBox rows,
@@ -614,9 +657,9 @@ __global__ __launch_bounds__(kBlock) void kb_rays(const FrameDesc *__restrict__ 
     const FrameDesc &f = fd[frame_of(start, n, blockIdx.x, local)];
     const int32_t tile = local * (kBlock / 64) + (threadIdx.x >> 6);
     if (f.inside)
-        rays_body<false>(f.rp, tile);
+        rays_body<false, false>(f.rp, tile);
     else
-        rays_body<true>(f.rp, tile);
+        rays_body<true, false>(f.rp, tile);
 }
 
 __global__ __launch_bounds__(kBlock) void kb_resolve(const FrameDesc *__restrict__ fd,
@@ -712,12 +755,18 @@ hipError_t launch_rays(const RayParams &p, bool camera_inside, hipStream_t st,
     const uint32_t blocks = (uint32_t)(ray_blocks + clear_blocks);
     if (blocks == 0)
         return record_empty_stage(ev, st);
-    if (camera_inside)
-        hipExtLaunchKernelGGL(k_rays<false>, dim3(blocks), dim3(kBlock), 0, st, ev.start, ev.stop,
-                              0, p, c, (int32_t)ray_blocks);
+    if (camera_inside && !p.occ_is_bytes)
+        hipExtLaunchKernelGGL((k_rays<false, false>), dim3(blocks), dim3(kBlock), 0, st, ev.start,
+                              ev.stop, 0, p, c, (int32_t)ray_blocks);
+    else if (camera_inside)
+        hipExtLaunchKernelGGL((k_rays<false, true>), dim3(blocks), dim3(kBlock), 0, st, ev.start,
+                              ev.stop, 0, p, c, (int32_t)ray_blocks);
+    else if (!p.occ_is_bytes)
+        hipExtLaunchKernelGGL((k_rays<true, false>), dim3(blocks), dim3(kBlock), 0, st, ev.start,
+                              ev.stop, 0, p, c, (int32_t)ray_blocks);
     else
-        hipExtLaunchKernelGGL(k_rays<true>, dim3(blocks), dim3(kBlock), 0, st, ev.start, ev.stop,
-                              0, p, c, (int32_t)ray_blocks);
+        hipExtLaunchKernelGGL((k_rays<true, true>), dim3(blocks), dim3(kBlock), 0, st, ev.start,
+                              ev.stop, 0, p, c, (int32_t)ray_blocks);
     return hipGetLastError();
 }
 

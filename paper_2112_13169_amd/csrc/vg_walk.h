@@ -30,11 +30,13 @@ namespace vg {
 
 constexpr int kChunk = 8;   // walk steps whose occupancy words load together
 
-// Memory the walk touches: the frame's occupancy bits (32-bit words) and its
-// mark planes -- byte stamps, free marks at [0, n) and "unknown and traced"
-// marks at [n, 2n), both indexed like the device-layout grid.  Offsets at or
-// beyond a buffer's size read 0 and write nothing (on the device these are
-// buffer-resource range checks, so masked lanes need no branches).
+// Memory the walk touches: the frame's occupancy -- bits (32-bit words), or
+// byte stamps (one per device-layout voxel) for frames whose occupied cubes
+// were stamped directly -- and its mark planes -- byte stamps, free marks at
+// [0, n) and "unknown and traced" marks at [n, 2n), both indexed like the
+// device-layout grid.  Offsets at or beyond a buffer's size read 0 and write
+// nothing (on the device these are buffer-resource range checks, so masked
+// lanes need no branches).
 constexpr uint32_t kOob = 0x80000000u;
 
 #ifdef __HIPCC__
@@ -50,7 +52,7 @@ VG_HD __amdgpu_buffer_rsrc_t buffer_rsrc(const void *p, uint32_t bytes)
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, (int)bytes, 0x00020000);
 }
 
-VG_HD WalkMem walk_mem(const uint32_t *occ, uint32_t occ_bytes, uint8_t *marks, uint32_t n,
+VG_HD WalkMem walk_mem(const void *occ, uint32_t occ_bytes, uint8_t *marks, uint32_t n,
                        uint32_t stamp)
 {
     WalkMem m;
@@ -66,6 +68,11 @@ VG_HD uint32_t load_occ(const WalkMem &m, uint32_t byte_off)
     return __builtin_amdgcn_raw_buffer_load_b32(m.occ, (int)byte_off, 0, 0);
 }
 
+VG_HD uint32_t load_occ_byte(const WalkMem &m, uint32_t off)
+{
+    return __builtin_amdgcn_raw_buffer_load_b8(m.occ, (int)off, 0, 0);
+}
+
 VG_HD void store_mark(const WalkMem &m, uint32_t off)
 {
     __builtin_amdgcn_raw_buffer_store_b8((unsigned char)m.stamp, m.marks, (int)off, 0, 0);
@@ -79,15 +86,20 @@ struct WalkMem {
     uint32_t stamp;
 };
 
-VG_HD WalkMem walk_mem(const uint32_t *occ, uint32_t occ_bytes, uint8_t *marks, uint32_t n,
+VG_HD WalkMem walk_mem(const void *occ, uint32_t occ_bytes, uint8_t *marks, uint32_t n,
                        uint32_t stamp)
 {
-    return WalkMem{occ, occ_bytes, marks, n, stamp};
+    return WalkMem{static_cast<const uint32_t *>(occ), occ_bytes, marks, n, stamp};
 }
 
 VG_HD uint32_t load_occ(const WalkMem &m, uint32_t byte_off)
 {
     return byte_off + 4 <= m.occ_bytes ? m.occ[byte_off / 4] : 0u;
+}
+
+VG_HD uint32_t load_occ_byte(const WalkMem &m, uint32_t off)
+{
+    return off < m.occ_bytes ? reinterpret_cast<const uint8_t *>(m.occ)[off] : 0u;
 }
 
 VG_HD void store_mark(const WalkMem &m, uint32_t off)
@@ -276,13 +288,15 @@ VG_HD uint32_t mul24(uint32_t a, uint32_t b)
 // stays kOob).  A step that was not taken, or whose voxel is outside the
 // grid, has index kOob.  Loads at traced-plane indices or at kOob fall beyond
 // the occupancy plane and read 0 (the word of index i is at byte
-// (i >> 5) << 2, at least n / 8 for i >= n, and 2^28 for kOob); stores at
-// kOob or kOob + n write nothing (kOob is at least twice any plane size).  So
-// a ray after its hit needs no test for its loads or for the plane of its
-// marks.
+// (i >> 5) << 2, at least n / 8 for i >= n, and 2^28 for kOob; with kBytes
+// the stamp of index i is at byte i, at least n); stores at kOob or kOob + n
+// write nothing (kOob is at least twice any plane size).  So a ray after its
+// hit needs no test for its loads or for the plane of its marks.  A stamp
+// byte of a voxel stamped in an earlier frame holds that frame's number,
+// never this frame's (the numbers only grow until the planes are cleared).
 struct Chunk {
     uint32_t ids[kChunk];     // index of each step's voxel, or kOob
-    uint32_t words[kChunk];   // occupancy word of that voxel (0 when not loaded)
+    uint32_t words[kChunk];   // occupancy word (kBytes: stamp byte) of that voxel, 0 when not loaded
     bool loaded;              // some lane of the wavefront loaded words
 };
 
@@ -298,7 +312,7 @@ VG_HD bool chunk_safe(const Walk &w, int32_t m2)
            w.d2 + (kChunk - 1) * qm + (kChunk - 1) * (kChunk - 2) < m2;
 }
 
-template <bool kGeneral>
+template <bool kGeneral, bool kBytes>
 VG_HD bool walk_chunk(Walk &w, int32_t m2, bool alive, Chunk &c, bool load, const WalkMem &m)
 {
     if (!kGeneral && vg_all(!alive || chunk_safe(w, m2))) {
@@ -347,7 +361,7 @@ VG_HD bool walk_chunk(Walk &w, int32_t m2, bool alive, Chunk &c, bool load, cons
     if (c.loaded) {
 #pragma unroll
         for (int s = 0; s < kChunk; ++s)
-            c.words[s] = load_occ(m, (c.ids[s] >> 5) << 2);
+            c.words[s] = kBytes ? load_occ_byte(m, c.ids[s]) : load_occ(m, (c.ids[s] >> 5) << 2);
     } else {
 #pragma unroll
         for (int s = 0; s < kChunk; ++s)
@@ -362,6 +376,7 @@ VG_HD bool walk_chunk(Walk &w, int32_t m2, bool alive, Chunk &c, bool load, cons
 // after it loaded zeros).  A lane that hits here moves to the traced plane:
 // its walk index and the indices of the chunk walked after c (`next`, whose
 // words it must no longer test) move up by n.
+template <bool kBytes>
 VG_HD void resolve_chunk(const Chunk &c, bool &before_hit, Walk &w, Chunk &next,
                          const WalkMem &m)
 {
@@ -370,7 +385,8 @@ VG_HD void resolve_chunk(const Chunk &c, bool &before_hit, Walk &w, Chunk &next,
         uint32_t hits = 1u << kChunk;
 #pragma unroll
         for (int s = 0; s < kChunk; ++s)
-            hits |= bit_of(c.words[s], c.ids[s]) << s;
+            hits |= (kBytes ? (uint32_t)(c.words[s] == m.stamp) : bit_of(c.words[s], c.ids[s]))
+                    << s;
         hit = lowest_set(hits);
     }
     if (vg_any(hit < kChunk)) {
@@ -397,21 +413,21 @@ VG_HD void resolve_chunk(const Chunk &c, bool &before_hit, Walk &w, Chunk &next,
 // before it and "unknown and traced" from it on.  A chunk walked after the
 // walk ended holds no step, so the loop ends once the chunk that ended it is
 // resolved.
-template <bool kGeneral>
+template <bool kGeneral, bool kBytes>
 VG_HD void walk_ray(Walk &w, int32_t m2, const WalkMem &m)
 {
     bool before_hit = true;   // Alg. 2: vox_val is still "free"
     Chunk a, b;
-    bool alive = walk_chunk<kGeneral>(w, m2, true, a, true, m);
+    bool alive = walk_chunk<kGeneral, kBytes>(w, m2, true, a, true, m);
     while (true) {
         bool more = alive;
-        alive = walk_chunk<kGeneral>(w, m2, alive, b, before_hit, m);
-        resolve_chunk(a, before_hit, w, b, m);
+        alive = walk_chunk<kGeneral, kBytes>(w, m2, alive, b, before_hit, m);
+        resolve_chunk<kBytes>(a, before_hit, w, b, m);
         if (!more)
             break;
         more = alive;
-        alive = walk_chunk<kGeneral>(w, m2, alive, a, before_hit, m);
-        resolve_chunk(b, before_hit, w, a, m);
+        alive = walk_chunk<kGeneral, kBytes>(w, m2, alive, a, before_hit, m);
+        resolve_chunk<kBytes>(b, before_hit, w, a, m);
         if (!more)
             break;
     }

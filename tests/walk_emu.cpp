@@ -3,9 +3,11 @@
 // occupancy, random rays from inside and outside the grid.  In every other
 // trial the lane's wavefront votes at random (vg_host_vote): other lanes may
 // still need occupancy loads after this ray's hit, or force the chunk path
-// with per-step tests.  The occupancy buffer is followed by all-ones words
-// that reads beyond the plane's size must not see.  Prints the number of
-// mismatching voxels and exits non-zero if there is any.
+// with per-step tests.  Occupancy as bits, or (every third trial) as stamp
+// bytes with stale stamps of other frames on free voxels.  Either buffer is
+// followed by set words / this frame's stamp, which reads beyond the plane's
+// size must not see.  Prints the number of mismatching voxels and exits
+// non-zero if there is any.
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -57,6 +59,14 @@ int main(int argc, char **argv)
         const size_t words = (size_t)f.gxp / 32 * ny * nz;
         std::vector<uint32_t> occ(words + 4096, 0xFFFFFFFFu);   // the plane, then set words
         std::fill(occ.begin(), occ.begin() + words, 0u);
+        const bool bytes = trial % 3 == 2;
+        const uint8_t stamp = 1 + rnd() % 255;
+        // byte stamps: the plane (one byte per device-layout voxel), then bytes
+        // holding this frame's stamp that reads beyond the plane must not see
+        const size_t nvox = (size_t)f.gxp * ny * nz;
+        std::vector<uint8_t> occb(nvox + 4096, stamp);
+        for (size_t j = 0; j < nvox; ++j)
+            occb[j] = (uint8_t)(rnd() % 4 == 0 ? (stamp + 1 + rnd() % 254) & 0xFF : 0);
         vg_host_vote = trial % 2 ? random_vote : nullptr;
         std::vector<uint8_t> ms((size_t)nx * ny * nz, 0);
         const uint32_t density = big ? 200 + rnd() % 4000 : 8 + rnd() % 120;
@@ -66,6 +76,7 @@ int main(int argc, char **argv)
                     if (rnd() % density == 0) {
                         size_t j = (size_t)x + (size_t)f.gxp * (y + (size_t)ny * z);
                         occ[j >> 5] |= 1u << (j & 31);
+                        occb[j] = stamp;
                         ms[x + (size_t)nx * (y + (size_t)ny * z)] = OG_OCCUPIED;
                     }
         float dir[3];
@@ -78,7 +89,6 @@ int main(int argc, char **argv)
         const int32_t m2 = 1 + (int32_t)(rnd() % (big ? 60000 : 4000));
         const uint32_t n = (uint32_t)((size_t)f.gxp * ny * nz);
         std::vector<uint8_t> marks(2 * (size_t)n, 0);
-        const uint8_t stamp = 1 + rnd() % 255;
 
         bool dead = false;
         for (int a = 0; a < 3; ++a)
@@ -86,11 +96,20 @@ int main(int argc, char **argv)
         if (!dead) {
             Walk w;
             walk_setup(w, f, dir);
-            const WalkMem m = walk_mem(occ.data(), (uint32_t)(4 * words), marks.data(), n, stamp);
-            if (inside)
-                walk_ray<false>(w, m2, m);
-            else
-                walk_ray<true>(w, m2, m);
+            if (bytes) {
+                const WalkMem m = walk_mem(occb.data(), (uint32_t)nvox, marks.data(), n, stamp);
+                if (inside)
+                    walk_ray<false, true>(w, m2, m);
+                else
+                    walk_ray<true, true>(w, m2, m);
+            } else {
+                const WalkMem m = walk_mem(occ.data(), (uint32_t)(4 * words), marks.data(), n,
+                                           stamp);
+                if (inside)
+                    walk_ray<false, false>(w, m2, m);
+                else
+                    walk_ray<true, false>(w, m2, m);
+            }
         }
         std::vector<uint8_t> ref = ms;
         steps += og_trace_ray(f.o, dir, m2, nx, ny, nz, ref.data(), nullptr, nullptr, 0);
