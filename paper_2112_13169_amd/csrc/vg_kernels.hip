@@ -405,6 +405,7 @@ __device__ __forceinline__ uint32_t stamp_mask16(const uint8_t *p, uint32_t rep)
 // occupied bit -> occupied; else a traced stamp -> unknown; else a free stamp
 // -> free; else unchanged.  The frame's planes are read at the grid columns
 // the 16 buffer columns hold (one run, or two where the ring wraps).
+template <bool kBytes>
 __device__ __forceinline__ void resolve_body(const Planes &pl, uint8_t *loc, const RowBox &rows,
                                              const int32_t ring[3], int64_t gid)
 {
@@ -432,7 +433,7 @@ __device__ __forceinline__ void resolve_body(const Planes &pl, uint8_t *loc, con
     if ((x0 & 15) == 0 && x0 + nvalid <= gx) {
         // one run of grid columns starting on a 16-column boundary
         const int64_t b = prow + x0;
-        if (pl.occb) {
+        if (kBytes) {
             const uint4 oc = *reinterpret_cast<const uint4 *>(pl.occb + b);
             occ16 = byte_eq_mask(oc.x, rep) | (byte_eq_mask(oc.y, rep) << 4) |
                     (byte_eq_mask(oc.z, rep) << 8) | (byte_eq_mask(oc.w, rep) << 12);
@@ -447,7 +448,7 @@ __device__ __forceinline__ void resolve_body(const Planes &pl, uint8_t *loc, con
                (byte_eq_mask(fr.z, rep) << 8) | (byte_eq_mask(fr.w, rep) << 12);
     } else if (x0 + nvalid <= gx) {
         const int64_t b = prow + x0;
-        if (pl.occb) {
+        if (kBytes) {
             occ16 = stamp_mask16(pl.occb + b, rep);
         } else {
             const uint64_t two =
@@ -464,7 +465,7 @@ __device__ __forceinline__ void resolve_body(const Planes &pl, uint8_t *loc, con
             if (x >= gx)
                 x -= gx;
             const int64_t b = prow + x;
-            occ16 |= (pl.occb ? (uint32_t)(pl.occb[b] == e) : (pl.occ[b >> 5] >> (b & 31)) & 1u)
+            occ16 |= (kBytes ? (uint32_t)(pl.occb[b] == e) : (pl.occ[b >> 5] >> (b & 31)) & 1u)
                      << j;
             tr16 |= (uint32_t)(pl.marks[pl.nbytes + b] == e) << j;
             fr16 |= (uint32_t)(pl.marks[b] == e) << j;
@@ -562,11 +563,12 @@ __global__ __launch_bounds__(kBlock) void k_rays(RayParams p, SlabClear c, int32
     rays_body<kGeneral, kBytes>(p, blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6));
 }
 
+template <bool kBytes>
 __global__ __launch_bounds__(kBlock) void k_resolve(Planes pl, uint8_t *loc, RowBox rows,
                                                     int32_t rx, int32_t ry, int32_t rz)
 {
     const int32_t ring[3] = {rx, ry, rz};
-    resolve_body(pl, loc, rows, ring, (int64_t)blockIdx.x * kBlock + threadIdx.x);
+    resolve_body<kBytes>(pl, loc, rows, ring, (int64_t)blockIdx.x * kBlock + threadIdx.x);
 }
 
 __global__ __launch_bounds__(kBlock) void k_clear(SlabClear c)
@@ -667,7 +669,7 @@ __global__ __launch_bounds__(kBlock) void kb_resolve(const FrameDesc *__restrict
 {
     int32_t local;
     const FrameDesc &f = fd[frame_of(start, n, blockIdx.x, local)];
-    resolve_body(f.sp.pl, f.loc, f.rows, f.ring, (int64_t)local * kBlock + threadIdx.x);
+    resolve_body<false>(f.sp.pl, f.loc, f.rows, f.ring, (int64_t)local * kBlock + threadIdx.x);
 }
 
 uint32_t blocks_for(int64_t threads) { return (uint32_t)((threads + kBlock - 1) / kBlock); }
@@ -777,8 +779,12 @@ hipError_t launch_resolve(const Planes &pl, uint8_t *loc, const RowBox &rows,
         return record_empty_stage(ev, st);
     const int32_t ny = rows.y1 - rows.y0 + 1, nz = rows.z1 - rows.z0 + 1;
     int64_t n = (int64_t)pl.wx * 2 * ny * nz;
-    hipExtLaunchKernelGGL(k_resolve, dim3(blocks_for(n)), dim3(kBlock), 0, st, ev.start, ev.stop,
-                          0, pl, loc, rows, ring[0], ring[1], ring[2]);
+    if (pl.occb)
+        hipExtLaunchKernelGGL(k_resolve<true>, dim3(blocks_for(n)), dim3(kBlock), 0, st, ev.start,
+                              ev.stop, 0, pl, loc, rows, ring[0], ring[1], ring[2]);
+    else
+        hipExtLaunchKernelGGL(k_resolve<false>, dim3(blocks_for(n)), dim3(kBlock), 0, st, ev.start,
+                              ev.stop, 0, pl, loc, rows, ring[0], ring[1], ring[2]);
     return hipGetLastError();
 }
 
