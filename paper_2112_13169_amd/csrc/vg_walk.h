@@ -29,6 +29,7 @@ inline bool (*vg_host_vote)() = nullptr;
 namespace vg {
 
 constexpr int kChunk = 8;   // walk steps whose occupancy words load together
+constexpr int32_t kNoLimit = 0x3FFFFFFF;   // a q limit no walk reaches
 
 // Memory the walk touches: the frame's occupancy -- bits (32-bit words), or
 // byte stamps (one per device-layout voxel) for frames whose occupied cubes
@@ -170,9 +171,14 @@ VG_HD void walk_setup(Walk &w, const WalkFrame &p, const float dir[3])
     axis_limits(sx, p.v0[0], p.n[0], lx, ex);
     axis_limits(sy, p.v0[1], p.n[1], ly, ey);
     axis_limits(sz, p.v0[2], p.n[2], lz, ez);
-    w.lx = 2 * lx - 1;
-    w.ly = 2 * ly - 1;
-    w.lz = 2 * lz - 1;
+    // An axis the ray does not move on is never chosen while another one
+    // moves (its boundary parameter is infinite): give it a limit no walk
+    // reaches, so that chunks of such a ray may skip the tests.  A ray that
+    // moves on no axis keeps the limit that ends its walk at once.
+    const bool moves = sx != 0 || sy != 0 || sz != 0;
+    w.lx = sx == 0 && moves ? kNoLimit : 2 * lx - 1;
+    w.ly = sy == 0 && moves ? kNoLimit : 2 * ly - 1;
+    w.lz = sz == 0 && moves ? kNoLimit : 2 * lz - 1;
     w.ex = 2 * ex + 1;
     w.ey = 2 * ey + 1;
     w.ez = 2 * ez + 1;
@@ -302,8 +308,8 @@ struct Chunk {
 
 // A live walk whose next kChunk steps can neither reach its length nor leave
 // the grid: every axis has room for kChunk more steps (an axis the ray does
-// not move on has none, so such rays never qualify) and the distance stays
-// below the length even if every step is taken on the axis with the largest q.
+// not move on always has) and the distance stays below the length even if
+// every step is taken on the axis with the largest q.
 VG_HD bool chunk_safe(const Walk &w, int32_t m2)
 {
     constexpr int32_t room = 2 * (kChunk - 1);
