@@ -58,8 +58,8 @@ TRAFFIC_FILE_BATCHED = os.path.join(ROOT, "profiles", "traffic_batched.json")
 
 STAGE_KERNELS = {"k_dilate": ["k_dilate_x", "k_dilate_yz", "k_dilate_yz_tile<8>",
                               "k_dilate_yz_tile<16>"],
-                 "k_rays": [f"k_rays<{g}, {b}>" for g in ("false", "true")
-                            for b in ("false", "true")],
+                 "k_rays": [f"k_rays<{g}, {b}, {l}>" for g in ("false", "true")
+                            for b in ("false", "true") for l in ("false", "true")],
                  "k_resolve": ["k_resolve<false>", "k_resolve<true>"]}
 
 

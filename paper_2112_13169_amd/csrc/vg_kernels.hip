@@ -40,6 +40,9 @@ namespace vg {
 namespace {
 
 constexpr int kBlock = 256;
+// Ray wavefronts up to which a launch has at most one per SIMD (gfx950:
+// 256 compute units x 4 SIMDs) and the walk takes its lone form.
+constexpr int64_t kLoneWaves = 1024;
 
 // ----------------------------------------------------------------- helpers
 
@@ -351,7 +354,7 @@ __device__ __forceinline__ void dilate_yz_tile_body(const Planes &pl, int32_t ti
 }
 
 // Alg. 2 for the 64 rays of fan tile `tile` (one wavefront).
-template <bool kGeneral, bool kBytes>
+template <bool kGeneral, bool kBytes, bool kLone>
 __device__ __forceinline__ void rays_body(const RayParams &p, int32_t tile)
 {
     const int lane = threadIdx.x & 63;
@@ -370,8 +373,8 @@ __device__ __forceinline__ void rays_body(const RayParams &p, int32_t tile)
         return;
     Walk w;
     walk_setup(w, p.wf, dir);
-    walk_ray<kGeneral, kBytes>(w, m2,
-                               walk_mem(p.occ, p.occ_bytes, p.marks, p.nbytes, p.epoch & 0xFFu));
+    walk_ray<kGeneral, kBytes, kLone>(w, m2, walk_mem(p.occ, p.occ_bytes, p.marks, p.nbytes,
+                                                      p.epoch & 0xFFu));
 }
 
 // (v + r) mod n for v, r in [0, n).
@@ -552,15 +555,16 @@ __global__ __launch_bounds__(kBlock) void k_dilate_yz_tile(Planes pl)
 }
 
 // The walk; workgroups from ray_blocks on run the slab clear c instead (the
-// walk leaves most compute units idle for its longest rays).
-template <bool kGeneral, bool kBytes>
+// walk leaves most compute units idle for its longest rays).  kLone: the walk
+// form for launches of at most one ray wavefront per SIMD.
+template <bool kGeneral, bool kBytes, bool kLone>
 __global__ __launch_bounds__(kBlock) void k_rays(RayParams p, SlabClear c, int32_t ray_blocks)
 {
     if ((int32_t)blockIdx.x >= ray_blocks) {
         clear_body(c, (int64_t)(blockIdx.x - ray_blocks) * kBlock + threadIdx.x);
         return;
     }
-    rays_body<kGeneral, kBytes>(p, blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6));
+    rays_body<kGeneral, kBytes, kLone>(p, blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6));
 }
 
 template <bool kBytes>
@@ -659,9 +663,9 @@ __global__ __launch_bounds__(kBlock) void kb_rays(const FrameDesc *__restrict__ 
     const FrameDesc &f = fd[frame_of(start, n, blockIdx.x, local)];
     const int32_t tile = local * (kBlock / 64) + (threadIdx.x >> 6);
     if (f.inside)
-        rays_body<false, false>(f.rp, tile);
+        rays_body<false, false, false>(f.rp, tile);
     else
-        rays_body<true, false>(f.rp, tile);
+        rays_body<true, false, false>(f.rp, tile);
 }
 
 __global__ __launch_bounds__(kBlock) void kb_resolve(const FrameDesc *__restrict__ fd,
@@ -757,18 +761,28 @@ hipError_t launch_rays(const RayParams &p, bool camera_inside, hipStream_t st,
     const uint32_t blocks = (uint32_t)(ray_blocks + clear_blocks);
     if (blocks == 0)
         return record_empty_stage(ev, st);
-    if (camera_inside && !p.occ_is_bytes)
-        hipExtLaunchKernelGGL((k_rays<false, false>), dim3(blocks), dim3(kBlock), 0, st, ev.start,
-                              ev.stop, 0, p, c, (int32_t)ray_blocks);
+    // at most one ray wavefront per SIMD (256 compute units x 4): the walk
+    // form that keeps its loads in flight (the camera inside the grid; from
+    // outside, most steps take the tested path anyway)
+    const bool lone = p.tiles <= kLoneWaves;
+    if (camera_inside && !p.occ_is_bytes && lone)
+        hipExtLaunchKernelGGL((k_rays<false, false, true>), dim3(blocks), dim3(kBlock), 0, st,
+                              ev.start, ev.stop, 0, p, c, (int32_t)ray_blocks);
+    else if (camera_inside && !p.occ_is_bytes)
+        hipExtLaunchKernelGGL((k_rays<false, false, false>), dim3(blocks), dim3(kBlock), 0, st,
+                              ev.start, ev.stop, 0, p, c, (int32_t)ray_blocks);
+    else if (camera_inside && lone)
+        hipExtLaunchKernelGGL((k_rays<false, true, true>), dim3(blocks), dim3(kBlock), 0, st,
+                              ev.start, ev.stop, 0, p, c, (int32_t)ray_blocks);
     else if (camera_inside)
-        hipExtLaunchKernelGGL((k_rays<false, true>), dim3(blocks), dim3(kBlock), 0, st, ev.start,
-                              ev.stop, 0, p, c, (int32_t)ray_blocks);
+        hipExtLaunchKernelGGL((k_rays<false, true, false>), dim3(blocks), dim3(kBlock), 0, st,
+                              ev.start, ev.stop, 0, p, c, (int32_t)ray_blocks);
     else if (!p.occ_is_bytes)
-        hipExtLaunchKernelGGL((k_rays<true, false>), dim3(blocks), dim3(kBlock), 0, st, ev.start,
-                              ev.stop, 0, p, c, (int32_t)ray_blocks);
+        hipExtLaunchKernelGGL((k_rays<true, false, false>), dim3(blocks), dim3(kBlock), 0, st,
+                              ev.start, ev.stop, 0, p, c, (int32_t)ray_blocks);
     else
-        hipExtLaunchKernelGGL((k_rays<true, true>), dim3(blocks), dim3(kBlock), 0, st, ev.start,
-                              ev.stop, 0, p, c, (int32_t)ray_blocks);
+        hipExtLaunchKernelGGL((k_rays<true, true, false>), dim3(blocks), dim3(kBlock), 0, st,
+                              ev.start, ev.stop, 0, p, c, (int32_t)ray_blocks);
     return hipGetLastError();
 }
 

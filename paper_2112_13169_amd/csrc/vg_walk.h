@@ -12,6 +12,8 @@
 #define VG_INF __builtin_inff()
 #define vg_any(p) __any(p)
 #define vg_all(p) __all(p)
+// a vote the compiler can see is the same on every lane
+#define vg_any_u(p) (__builtin_amdgcn_readfirstlane(__any(p)) != 0)
 #else
 #include <cmath>
 #define VG_HD static inline
@@ -24,6 +26,7 @@
 inline bool (*vg_host_vote)() = nullptr;
 #define vg_any(p) ((p) || (vg_host_vote && vg_host_vote()))
 #define vg_all(p) ((p) && !(vg_host_vote && vg_host_vote()))
+#define vg_any_u(p) vg_any(p)
 #endif
 
 namespace vg {
@@ -318,7 +321,9 @@ VG_HD bool chunk_safe(const Walk &w, int32_t m2)
            w.d2 + (kChunk - 1) * qm + (kChunk - 1) * (kChunk - 2) < m2;
 }
 
-template <bool kGeneral, bool kBytes>
+// kLone selects the form for wavefronts that each have a SIMD to themselves
+// (see walk_ray).
+template <bool kGeneral, bool kBytes, bool kLone>
 VG_HD bool walk_chunk(Walk &w, int32_t m2, bool alive, Chunk &c, bool load, const WalkMem &m)
 {
     if (!kGeneral && vg_all(!alive || chunk_safe(w, m2))) {
@@ -362,9 +367,15 @@ VG_HD bool walk_chunk(Walk &w, int32_t m2, bool alive, Chunk &c, bool load, cons
             w.sx = w.sy = w.sz = 0;
         }
     }
-    // a wavefront whose rays have all met their obstacle loads nothing
+    // A wavefront whose rays have all met their obstacle need not load (its
+    // indices lie in the traced plane or at kOob, past the occupancy plane,
+    // and would read 0).  The lone form loads anyway: with the same memory
+    // operations on every path, the compiler's wait counts let the hit test
+    // of a chunk wait for that chunk's loads only, not for the next chunk's,
+    // which then stay in flight during the next chunk's steps.  Only the hit
+    // test is skipped.
     c.loaded = vg_any(load);
-    if (c.loaded) {
+    if (kLone || c.loaded) {
 #pragma unroll
         for (int s = 0; s < kChunk; ++s)
             c.words[s] = kBytes ? load_occ_byte(m, c.ids[s]) : load_occ(m, (c.ids[s] >> 5) << 2);
@@ -378,11 +389,13 @@ VG_HD bool walk_chunk(Walk &w, int32_t m2, bool alive, Chunk &c, bool load, cons
 
 // Marks of chunk c: free before the ray's first occupied voxel, traced from
 // it on (the occupied voxel itself becomes occupied whatever its marks say).
-// The hit is the lowest occupied slot of a ray still before its hit (a ray
-// after it loaded zeros).  A lane that hits here moves to the traced plane:
-// its walk index and the indices of the chunk walked after c (`next`, whose
-// words it must no longer test) move up by n.
-template <bool kBytes>
+// The hit is the lowest occupied slot of a ray still before its hit.  A lane
+// that hits here moves to the traced plane: its walk index and the indices
+// of the chunk walked after c (`next`) move up by n.  That chunk's words
+// were loaded from the free plane and must no longer count: they are zeroed,
+// or, in the lone form, whose registers are left alone while their loads are
+// in flight, the hit test skips lanes whose before_hit is false.
+template <bool kBytes, bool kLone>
 VG_HD void resolve_chunk(const Chunk &c, bool &before_hit, Walk &w, Chunk &next,
                          const WalkMem &m)
 {
@@ -394,6 +407,8 @@ VG_HD void resolve_chunk(const Chunk &c, bool &before_hit, Walk &w, Chunk &next,
             hits |= (kBytes ? (uint32_t)(c.words[s] == m.stamp) : bit_of(c.words[s], c.ids[s]))
                     << s;
         hit = lowest_set(hits);
+        if (kLone && !before_hit)
+            hit = kChunk;
     }
     if (vg_any(hit < kChunk)) {
 #pragma unroll
@@ -405,7 +420,8 @@ VG_HD void resolve_chunk(const Chunk &c, bool &before_hit, Walk &w, Chunk &next,
 #pragma unroll
             for (int s = 0; s < kChunk; ++s) {
                 next.ids[s] += m.n;
-                next.words[s] = 0u;
+                if (!kLone)
+                    next.words[s] = 0u;
             }
         }
     } else {
@@ -416,26 +432,51 @@ VG_HD void resolve_chunk(const Chunk &c, bool &before_hit, Walk &w, Chunk &next,
 }
 
 // Alg. 2 for one ray: walk, test occupancy before the first hit, mark free
-// before it and "unknown and traced" from it on.  A chunk walked after the
-// walk ended holds no step, so the loop ends once the chunk that ended it is
-// resolved.
-template <bool kGeneral, bool kBytes>
+// before it and "unknown and traced" from it on.  Chunks alternate: while one
+// chunk's loads are in flight the other is walked.  A chunk walked after the
+// walk ended holds no step (its indices are kOob: it loads 0 and stores
+// nothing), so a lane is done once it has resolved the chunk that ended its
+// walk.
+//
+// Two forms.  With many wavefronts per SIMD (batches, large frames) others
+// hide a wavefront's load latency, and the plain form does the least work: a
+// lane leaves the loop as soon as it is done, and a wavefront past all its
+// obstacles loads nothing.  A wavefront that has its SIMD to itself (a small
+// frame) waits out every latency, so the lone form keeps the next chunk's
+// loads in flight: each iteration walks and resolves both chunks, its only
+// exit, at the end, is wave-uniform, and every chunk loads, so that one
+// sequence of memory operations runs through each iteration (otherwise the
+// compiler's wait counts, merged over the paths, make each hit test wait for
+// the next chunk's loads too).
+template <bool kGeneral, bool kBytes, bool kLone>
 VG_HD void walk_ray(Walk &w, int32_t m2, const WalkMem &m)
 {
     bool before_hit = true;   // Alg. 2: vox_val is still "free"
     Chunk a, b;
-    bool alive = walk_chunk<kGeneral, kBytes>(w, m2, true, a, true, m);
-    while (true) {
-        bool more = alive;
-        alive = walk_chunk<kGeneral, kBytes>(w, m2, alive, b, before_hit, m);
-        resolve_chunk<kBytes>(a, before_hit, w, b, m);
-        if (!more)
-            break;
-        more = alive;
-        alive = walk_chunk<kGeneral, kBytes>(w, m2, alive, a, before_hit, m);
-        resolve_chunk<kBytes>(b, before_hit, w, a, m);
-        if (!more)
-            break;
+    bool alive = walk_chunk<kGeneral, kBytes, kLone>(w, m2, true, a, true, m);
+    if (kLone) {
+        while (true) {
+            alive = walk_chunk<kGeneral, kBytes, kLone>(w, m2, alive, b, before_hit, m);
+            resolve_chunk<kBytes, kLone>(a, before_hit, w, b, m);
+            const bool more = alive;   // b was not the chunk that ended the walk
+            alive = walk_chunk<kGeneral, kBytes, kLone>(w, m2, alive, a, before_hit, m);
+            resolve_chunk<kBytes, kLone>(b, before_hit, w, a, m);
+            if (!vg_any_u(more))
+                break;
+        }
+    } else {
+        while (true) {
+            bool more = alive;
+            alive = walk_chunk<kGeneral, kBytes, kLone>(w, m2, alive, b, before_hit, m);
+            resolve_chunk<kBytes, kLone>(a, before_hit, w, b, m);
+            if (!more)
+                break;
+            more = alive;
+            alive = walk_chunk<kGeneral, kBytes, kLone>(w, m2, alive, a, before_hit, m);
+            resolve_chunk<kBytes, kLone>(b, before_hit, w, a, m);
+            if (!more)
+                break;
+        }
     }
 }
 

@@ -96,19 +96,25 @@ int main(int argc, char **argv)
         if (!dead) {
             Walk w;
             walk_setup(w, f, dir);
+            // both walk forms (the lone one for wavefronts alone on a SIMD)
+            const bool lone = trial / 4 % 2 == 1;
             if (bytes) {
                 const WalkMem m = walk_mem(occb.data(), (uint32_t)nvox, marks.data(), n, stamp);
-                if (inside)
-                    walk_ray<false, true>(w, m2, m);
+                if (inside && lone)
+                    walk_ray<false, true, true>(w, m2, m);
+                else if (inside)
+                    walk_ray<false, true, false>(w, m2, m);
                 else
-                    walk_ray<true, true>(w, m2, m);
+                    walk_ray<true, true, false>(w, m2, m);
             } else {
                 const WalkMem m = walk_mem(occ.data(), (uint32_t)(4 * words), marks.data(), n,
                                            stamp);
-                if (inside)
-                    walk_ray<false, false>(w, m2, m);
+                if (inside && lone)
+                    walk_ray<false, false, true>(w, m2, m);
+                else if (inside)
+                    walk_ray<false, false, false>(w, m2, m);
                 else
-                    walk_ray<true, false>(w, m2, m);
+                    walk_ray<true, false, false>(w, m2, m);
             }
         }
         std::vector<uint8_t> ref = ms;
