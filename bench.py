@@ -75,9 +75,13 @@ def measured_traffic(stage, path=TRAFFIC_FILE, workload=WORKLOAD):
     from paper_2112_13169_amd.prof_summary import kernel_source_hash
     if t.get("source_hash") != kernel_source_hash() or t.get("workload") != workload:
         return None
-    got = [t["kernels"][k]["hbm_bytes_per_launch"] for k in STAGE_KERNELS.get(stage, [stage])
-           if k in t.get("kernels", {})]
-    return float(sum(got)) if got else None
+    # a stage may launch one of several kernels (template forms): the mean
+    # over the profiled run's launches of the stage
+    got = [t["kernels"][k] for k in STAGE_KERNELS.get(stage, [stage]) if k in t.get("kernels", {})]
+    if not got:
+        return None
+    n = sum(k.get("launches", 1) for k in got)
+    return float(sum(k["hbm_bytes_per_launch"] * k.get("launches", 1) for k in got)) / n
 
 
 def cpu_model():

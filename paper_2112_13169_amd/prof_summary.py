@@ -153,7 +153,8 @@ def main(argv=None):
             nbytes = 1024.0 * (fr * f_fac + wr * w_fac)
             gbs = nbytes / s["avg_ns"]          # bytes per ns = GB/s
             if k.startswith(("k_", "kb_")):
-                kernels[k] = dict(hbm_bytes_per_launch=round(nbytes), fetch_kib=round(fr, 1),
+                kernels[k] = dict(hbm_bytes_per_launch=round(nbytes), launches=s["calls"],
+                                  fetch_kib=round(fr, 1),
                                   write_kib=round(wr, 1), avg_us=round(s["avg_ns"] / 1e3, 3),
                                   gb_per_s=round(gbs, 1), hbm_frac=round(gbs / HBM_PEAK_GBS, 4))
         lines.append(f"| `{k}` | {s['calls']} | {s['avg_ns'] / 1e3:.2f} | {s['min_ns'] / 1e3:.2f} | "

@@ -1,10 +1,15 @@
 """The profile summary tool on small synthetic rocprofv3 outputs: counter
-calibration by the copy kernel, per-kernel bytes, and the staleness hash that
-ignores comments but not code."""
+calibration by the copy kernel, per-kernel bytes, the staleness hash that
+ignores comments but not code, and the benchmark's per-stage bytes."""
 import json
 import os
+import sys
+
+import pytest
 
 from paper_2112_13169_amd import prof_summary as ps
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
 
 
 def _write(path, header, rows):
@@ -67,3 +72,18 @@ def test_hash_ignores_comments_but_not_code():
     assert ps.kernel_source_hash(lambda rel: files[rel]) == h0
     files[ps.KERNEL_SOURCES[1]] = base + "int g;"
     assert ps.kernel_source_hash(lambda rel: files[rel]) != h0
+
+
+def test_stage_traffic_is_the_launch_weighted_mean_of_its_kernels(tmp_path, monkeypatch):
+    """A stage whose launches use one of several kernel forms reports the
+    bytes of an average launch, not the sum over the forms."""
+    import bench
+    from paper_2112_13169_amd.prof_summary import kernel_source_hash
+    path = tmp_path / "traffic.json"
+    kernels = {"k_rays<false, false, true>": dict(hbm_bytes_per_launch=8000, launches=90),
+               "k_rays<false, false, false>": dict(hbm_bytes_per_launch=9000, launches=10)}
+    path.write_text(json.dumps(dict(workload="w", source_hash=kernel_source_hash(),
+                                    kernels=kernels)))
+    assert bench.measured_traffic("k_rays", str(path), "w") == pytest.approx(8100.0)
+    assert bench.measured_traffic("k_rays", str(path), "other") is None
+    assert bench.measured_traffic("k_seed", str(path), "w") is None
