@@ -323,8 +323,9 @@ VG_HD bool chunk_safe(const Walk &w, int32_t m2)
 
 // kLone selects the form for wavefronts that each have a SIMD to themselves
 // (see walk_ray).
-template <bool kGeneral, bool kBytes, bool kLone>
-VG_HD bool walk_chunk(Walk &w, int32_t m2, bool alive, Chunk &c, bool load, const WalkMem &m)
+// kChunk steps of a walk: the index of each step's voxel into c.ids.
+template <bool kGeneral>
+VG_HD bool step_chunk(Walk &w, int32_t m2, bool alive, Chunk &c)
 {
     if (!kGeneral && vg_all(!alive || chunk_safe(w, m2))) {
         // No step of this chunk can end a walk, so the steps skip the tests
@@ -367,6 +368,14 @@ VG_HD bool walk_chunk(Walk &w, int32_t m2, bool alive, Chunk &c, bool load, cons
             w.sx = w.sy = w.sz = 0;
         }
     }
+    return alive;
+}
+
+// kChunk steps and the occupancy of their voxels.
+template <bool kGeneral, bool kBytes, bool kLone>
+VG_HD bool walk_chunk(Walk &w, int32_t m2, bool alive, Chunk &c, bool load, const WalkMem &m)
+{
+    alive = step_chunk<kGeneral>(w, m2, alive, c);
     // A wavefront whose rays have all met their obstacle need not load (its
     // indices lie in the traced plane or at kOob, past the occupancy plane,
     // and would read 0).  The lone form loads anyway: with the same memory
@@ -400,7 +409,9 @@ VG_HD void resolve_chunk(const Chunk &c, bool &before_hit, Walk &w, Chunk &next,
                          const WalkMem &m)
 {
     int hit = kChunk;
-    if (c.loaded) {
+    // the lone form tests every chunk it loads (in its loading loop some ray
+    // is still before its hit), so that every path consumes the loads
+    if (kLone || c.loaded) {
         uint32_t hits = 1u << kChunk;
 #pragma unroll
         for (int s = 0; s < kChunk; ++s)
@@ -447,7 +458,9 @@ VG_HD void resolve_chunk(const Chunk &c, bool &before_hit, Walk &w, Chunk &next,
 // exit, at the end, is wave-uniform, and every chunk loads, so that one
 // sequence of memory operations runs through each iteration (otherwise the
 // compiler's wait counts, merged over the paths, make each hit test wait for
-// the next chunk's loads too).
+// the next chunk's loads too).  Once every ray of the wavefront has met its
+// obstacle (for good: before_hit never turns true again) the lone form goes
+// on in a second loop that only steps and stores traced marks.
 template <bool kGeneral, bool kBytes, bool kLone>
 VG_HD void walk_ray(Walk &w, int32_t m2, const WalkMem &m)
 {
@@ -462,7 +475,19 @@ VG_HD void walk_ray(Walk &w, int32_t m2, const WalkMem &m)
             alive = walk_chunk<kGeneral, kBytes, kLone>(w, m2, alive, a, before_hit, m);
             resolve_chunk<kBytes, kLone>(b, before_hit, w, a, m);
             if (!vg_any_u(more))
+                return;
+            if (!vg_any_u(before_hit))
                 break;
+        }
+        // Chunk a is walked but not resolved; its indices are in the traced
+        // plane (or kOob) on every lane.
+        while (true) {
+#pragma unroll
+            for (int s = 0; s < kChunk; ++s)
+                store_mark(m, a.ids[s]);
+            if (!vg_any_u(alive))
+                return;
+            alive = step_chunk<kGeneral>(w, m2, alive, a);
         }
     } else {
         while (true) {
