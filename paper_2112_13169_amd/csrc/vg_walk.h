@@ -459,8 +459,8 @@ VG_HD void resolve_chunk(const Chunk &c, bool &before_hit, Walk &w, Chunk &next,
 // sequence of memory operations runs through each iteration (otherwise the
 // compiler's wait counts, merged over the paths, make each hit test wait for
 // the next chunk's loads too).  Once every ray of the wavefront has met its
-// obstacle (for good: before_hit never turns true again) the lone form goes
-// on in a second loop that only steps and stores traced marks.
+// obstacle (for good: before_hit never turns true again) either form goes on
+// in a second loop that only steps and stores traced marks.
 template <bool kGeneral, bool kBytes, bool kLone>
 VG_HD void walk_ray(Walk &w, int32_t m2, const WalkMem &m)
 {
@@ -490,6 +490,7 @@ VG_HD void walk_ray(Walk &w, int32_t m2, const WalkMem &m)
             alive = step_chunk<kGeneral>(w, m2, alive, a);
         }
     } else {
+        bool traced_only = false;
         while (true) {
             bool more = alive;
             alive = walk_chunk<kGeneral, kBytes, kLone>(w, m2, alive, b, before_hit, m);
@@ -501,6 +502,22 @@ VG_HD void walk_ray(Walk &w, int32_t m2, const WalkMem &m)
             resolve_chunk<kBytes, kLone>(b, before_hit, w, a, m);
             if (!more)
                 break;
+            if (!vg_any(before_hit)) {
+                traced_only = true;
+                break;
+            }
+        }
+        if (traced_only) {
+            // as in the lone form: chunk a is walked but not resolved, its
+            // indices in the traced plane or at kOob
+            while (true) {
+#pragma unroll
+                for (int s = 0; s < kChunk; ++s)
+                    store_mark(m, a.ids[s]);
+                if (!alive)
+                    break;
+                alive = step_chunk<kGeneral>(w, m2, alive, a);
+            }
         }
     }
 }
