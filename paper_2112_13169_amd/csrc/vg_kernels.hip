@@ -564,7 +564,17 @@ __global__ __launch_bounds__(kBlock) void k_rays(RayParams p, SlabClear c, int32
         clear_body(c, (int64_t)(blockIdx.x - ray_blocks) * kBlock + threadIdx.x);
         return;
     }
-    rays_body<kGeneral, kBytes, kLone>(p, blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6));
+    int32_t rb = (int32_t)blockIdx.x;
+    if (kLone) {
+        // Workgroups go to the 8 XCDs in turn.  With every ray wavefront
+        // resident at once, each XCD takes a contiguous range of ray blocks,
+        // whose neighbouring tiles share cache lines in its L2.  (With more
+        // wavefronts than SIMDs the turn order spreads the costly tiles
+        // over the XCDs, which matters more.)
+        const int32_t q = ray_blocks / 8, rem = ray_blocks % 8, xcd = rb % 8;
+        rb = xcd * q + min(xcd, rem) + rb / 8;
+    }
+    rays_body<kGeneral, kBytes, kLone>(p, rb * (kBlock / 64) + (threadIdx.x >> 6));
 }
 
 template <bool kBytes>
