@@ -1,8 +1,10 @@
 """The GPU ray walk (vg_walk.h, shared by the k_rays kernel) compiled for the
 host and compared with the CPU oracle's walk ray by ray: random grids,
-occupancy, camera positions inside and outside the grid, voxel-centre ties
-and zero direction components.  Catches logic errors in the walk without a
-GPU; the GPU parity tests cover the device build."""
+occupancy (bits, or stamp bytes), camera positions inside and outside the
+grid, voxel-centre ties and zero direction components, both walk forms (for
+wavefronts alone on a SIMD and for shared SIMDs) under random wavefront
+votes.  Catches logic errors in the walk without a GPU; the GPU parity tests
+cover the device build."""
 import os
 import subprocess
 
