@@ -41,7 +41,7 @@ namespace {
 
 constexpr int kBlock = 256;
 // Ray wavefronts up to which a launch has at most one per SIMD (gfx950:
-// 256 compute units x 4 SIMDs) and the walk takes its lone form.
+// 256 compute units x 4 SIMDs) and its ray blocks go to the XCDs in ranges.
 constexpr int64_t kLoneWaves = 1024;
 
 // ----------------------------------------------------------------- helpers
@@ -556,7 +556,7 @@ __global__ __launch_bounds__(kBlock) void k_dilate_yz_tile(Planes pl)
 
 // The walk; workgroups from ray_blocks on run the slab clear c instead (the
 // walk leaves most compute units idle for its longest rays).  kLone: the walk
-// form for launches of at most one ray wavefront per SIMD.
+// form that overlaps each chunk's loads with the next chunk's steps.
 template <bool kGeneral, bool kBytes, bool kLone>
 __global__ __launch_bounds__(kBlock) void k_rays(RayParams p, SlabClear c, int32_t ray_blocks)
 {
@@ -565,7 +565,7 @@ __global__ __launch_bounds__(kBlock) void k_rays(RayParams p, SlabClear c, int32
         return;
     }
     int32_t rb = (int32_t)blockIdx.x;
-    if (kLone) {
+    if (kLone && (int64_t)ray_blocks * (kBlock / 64) <= kLoneWaves) {
         // Workgroups go to the 8 XCDs in turn.  With every ray wavefront
         // resident at once, each XCD takes a contiguous range of ray blocks,
         // whose neighbouring tiles share cache lines in its L2.  (With more
@@ -673,7 +673,7 @@ __global__ __launch_bounds__(kBlock) void kb_rays(const FrameDesc *__restrict__ 
     const FrameDesc &f = fd[frame_of(start, n, blockIdx.x, local)];
     const int32_t tile = local * (kBlock / 64) + (threadIdx.x >> 6);
     if (f.inside)
-        rays_body<false, false, false>(f.rp, tile);
+        rays_body<false, false, true>(f.rp, tile);
     else
         rays_body<true, false, false>(f.rp, tile);
 }
@@ -771,21 +771,13 @@ hipError_t launch_rays(const RayParams &p, bool camera_inside, hipStream_t st,
     const uint32_t blocks = (uint32_t)(ray_blocks + clear_blocks);
     if (blocks == 0)
         return record_empty_stage(ev, st);
-    // at most one ray wavefront per SIMD (256 compute units x 4): the walk
-    // form that keeps its loads in flight (the camera inside the grid; from
-    // outside, most steps take the tested path anyway)
-    const bool lone = p.tiles <= kLoneWaves;
-    if (camera_inside && !p.occ_is_bytes && lone)
+    // the camera inside the grid: the walk form that keeps its loads in
+    // flight; from outside, every step takes the tested path anyway
+    if (camera_inside && !p.occ_is_bytes)
         hipExtLaunchKernelGGL((k_rays<false, false, true>), dim3(blocks), dim3(kBlock), 0, st,
                               ev.start, ev.stop, 0, p, c, (int32_t)ray_blocks);
-    else if (camera_inside && !p.occ_is_bytes)
-        hipExtLaunchKernelGGL((k_rays<false, false, false>), dim3(blocks), dim3(kBlock), 0, st,
-                              ev.start, ev.stop, 0, p, c, (int32_t)ray_blocks);
-    else if (camera_inside && lone)
-        hipExtLaunchKernelGGL((k_rays<false, true, true>), dim3(blocks), dim3(kBlock), 0, st,
-                              ev.start, ev.stop, 0, p, c, (int32_t)ray_blocks);
     else if (camera_inside)
-        hipExtLaunchKernelGGL((k_rays<false, true, false>), dim3(blocks), dim3(kBlock), 0, st,
+        hipExtLaunchKernelGGL((k_rays<false, true, true>), dim3(blocks), dim3(kBlock), 0, st,
                               ev.start, ev.stop, 0, p, c, (int32_t)ray_blocks);
     else if (!p.occ_is_bytes)
         hipExtLaunchKernelGGL((k_rays<true, false, false>), dim3(blocks), dim3(kBlock), 0, st,

@@ -449,18 +449,20 @@ VG_HD void resolve_chunk(const Chunk &c, bool &before_hit, Walk &w, Chunk &next,
 // nothing), so a lane is done once it has resolved the chunk that ended its
 // walk.
 //
-// Two forms.  With many wavefronts per SIMD (batches, large frames) others
-// hide a wavefront's load latency, and the plain form does the least work: a
-// lane leaves the loop as soon as it is done, and a wavefront past all its
-// obstacles loads nothing.  A wavefront that has its SIMD to itself (a small
-// frame) waits out every latency, so the lone form keeps the next chunk's
-// loads in flight: each iteration walks and resolves both chunks, its only
-// exit, at the end, is wave-uniform, and every chunk loads, so that one
+// Two forms.  The first does the least work per chunk: a lane leaves the
+// loop as soon as it is done, and a wavefront past all its obstacles loads
+// nothing; other wavefronts on its SIMD may hide its load latency.  The lone
+// form, made for a wavefront that has its SIMD to itself (a small frame,
+// which waits out every latency), keeps the next chunk's loads in flight:
+// each iteration walks and resolves both chunks, its only exit, at the end,
+// is wave-uniform, and every chunk loads and is hit-tested, so that one
 // sequence of memory operations runs through each iteration (otherwise the
 // compiler's wait counts, merged over the paths, make each hit test wait for
 // the next chunk's loads too).  Once every ray of the wavefront has met its
 // obstacle (for good: before_hit never turns true again) either form goes on
-// in a second loop that only steps and stores traced marks.
+// in a second loop that only steps and stores traced marks.  With that loop
+// the lone form measured as fast as the first also where SIMDs are shared, and
+// the kernels use it whenever the camera is inside the grid.
 template <bool kGeneral, bool kBytes, bool kLone>
 VG_HD void walk_ray(Walk &w, int32_t m2, const WalkMem &m)
 {
