@@ -154,6 +154,23 @@ def test_mixed_batch_matches_oracle():
         t.close()
 
 
+def test_batch_with_cameras_inside_and_outside_their_grids():
+    """One batch launch whose walk takes both forms: frames whose camera is
+    outside their grid (every step tested) beside frames whose camera is
+    inside (chunks of steps, loads in flight)."""
+    fr = scenes.make_frame("plain-small", 70, size=(40, 30))
+    offsets = ([6.0, 0.2, 0.1], [0.0, 0.0, 0.0], [-6.0, 0.3, 0.0], [0.1, 0.2, 0.02])
+    twins = [Twin(fr.dims, fr.vox_size, fr.origin + np.array(o, np.float32), fr.vox_inf)
+             for o in offsets]
+    dev = [DevFrame(t, fr) for t in twins]
+    _say("batch: cameras inside and outside")
+    vg.vg_integrate_batch([d.desc for d in dev], _workspace(len(dev)))
+    for o, t in zip(offsets, twins):
+        t.oracle_frame(fr)
+        t.check(f"origin offset {o}")
+        t.close()
+
+
 def test_sequence_batch_with_shifts_matches_oracle():
     """Eight consecutive frames of one trajectory as one batch (order kept
     across the re-centring shifts)."""
