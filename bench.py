@@ -1,26 +1,33 @@
 #!/usr/bin/env python3
 """Benchmark: frames/s and voxel-updates/s of depth-frame -> voxel-grid
-integration on one MI355X, with p50/p99 frame latency, per-kernel times,
-the roofline of the dominant kernel and the CPU oracle timed beside it.
+integration on one MI355X, with p50/p99 frame latency, batched against plain,
+per-kernel times, the roofline of the dominant kernel and the CPU oracle timed
+beside it.
 
-Workload (one "step" = one frame through the whole path): a 640x480 float32
-z-depth frame (90x60 deg pinhole, 0.3-8 m, 200 boxes + 50 spheres, depth noise
-N(0, (0.005 d^2)^2), 5 % invalid pixels in 8x8 blocks), integrated into a
-resident 200x200x100 uint8 grid at 0.05 m with vox_inf 2: re-centre the grid
-on the camera by vg_center_offset and integrate the frame, in one
-vg_integrate_frame_shifted call (shift, seed, dilation, walk, merge; the
-shift's clear runs inside the walk launch).  A pool of seeded frames with
-random yaw and position is cycled; depth images are resident on the GPU
-before the timed region starts.
+Headline workload (one "step" = one frame through the whole path, in one
+vg_integrate_frame_shifted call: re-centre shift, seed, dilation, walk,
+merge): the large pinhole sequence -- 300 consecutive 1280x720 float32
+z-depth frames (90x60 deg, 0.3-12 m, depth noise N(0, (0.005 d^2)^2), 5 %
+invalid pixels in 8x8 blocks) of a 2 m/s, 30 Hz walk through a seeded
+30x30x8 m world of 1500 boxes + 500 spheres, integrated into a resident
+400x400x200 uint8 grid (32 M voxels) at 0.025 m with vox_inf 3, re-centred on
+the camera before every frame.  Depth images are resident on the GPU before
+any timed region.  The timed region is K steps that continue the sequence
+after W warm-up steps; p50/p99 latency, per-stage and per-walk-launch times
+come from dedicated passes over the whole sequence; the same sequence also
+runs as 8-frame batches (vg_integrate_batch), whose final grid must equal the
+plain path's.  The first frames are checked against the CPU oracle (which
+also gives the single-thread CPU baseline), and a sample of frames is run
+through the oracle on every host thread for the voxel-update and walk-step
+counts (the CPU oracle runs on a bounded sample only).
 
-Batched runs (--batch N, default 64; 0 skips them) put the same integration
-through vg_integrate_batch and compare it with one vg_integrate_frame call per
-frame on the same frames, each frame with its own grid: 16 of the medium frames
-per step, and N independent frames of the batch recipe (320x240 .. 1280x720,
-range to U[4, 10] m, random 6-DoF poses, grids of 100..256 x 100..256 x
-100..128 at 0.05-0.1 m, vox_inf 1-3).  Ray-bundle shapes are tuned per fan
-class first (autotune.py); both paths are checked equal on every grid, and two
-sampled frames of the recipe against the CPU oracle.
+Other workloads are extra keys of the same line: the 128x2048 spinning
+sequence into the same grid, the medium (640x480 -> 200x200x100 at 0.05 m)
+and small (160x120 -> 100x100x50 at 0.1 m) frame pools, batches of
+independent frames (16 medium frames, and 64 frames of the batch recipe:
+320x240 .. 1280x720, random 6-DoF poses, own grids), the served fleet (16
+robots x 300 frames at 30 Hz, continuous batching) and the paper's standard
+parameters beside its Table II.
 """
 from __future__ import annotations
 
@@ -38,29 +45,74 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "frames/s + voxel-updates/s at 1 GPU, p50/p99 frame latency; batched vs plain, bit-exact"
-WORKLOAD = "plain-medium"
+WORKLOAD = "large-pinhole"
 
-# Algorithmic operations of one walk step (Alg. 2 inner loop): choose the axis
-# with the nearest boundary (2 compares), advance the voxel (1 add), advance
-# that axis' boundary parameter (1 fp32 add), update the squared lattice
-# distance (2 integer ops), the termination test (1 compare), the in-grid test
-# (3 compares), the linear index (2 integer multiply-adds), the occupancy test
-# (1 compare) and the free / traced store (1).
-OPS_PER_STEP = 14
+# Algorithmic operations of one walk step (Alg. 2 inner loop, Amanatides &
+# Woo): choose the axis with the nearest boundary (2 compares, 1 select), step
+# the voxel coordinate (1 add), advance that axis' boundary parameter (1 fp32
+# add, 1 select), the per-axis step count and the squared lattice distance of
+# the termination rule (3 integer ops), the termination test (1 compare), the
+# in-grid test (3 compares, 1 and), the linear voxel index (2 integer
+# multiply-adds), the occupancy read and test (2), the free / traced choice
+# (1) and the mark store (1): 20.
+OPS_PER_STEP = 20
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes, one 32-bit VALU op per lane per clock
 # at 2.4 GHz (packed fp32 excluded: the library is built without it).
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
 CAL_BYTES = 64 << 20            # calibration copy: 64 MiB read + 64 MiB written
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-TRAFFIC_FILE_BATCHED = os.path.join(ROOT, "profiles", "traffic_batched.json")
-
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILES, "traffic_large-pinhole.json")
+TRAFFIC_FILE_MEDIUM = os.path.join(PROFILES, "traffic.json")
+TRAFFIC_FILE_BATCHED = os.path.join(PROFILES, "traffic_batched.json")
+SECTIONS = ("headline", "spinning", "medium", "small", "batched", "served", "paper")
 
 STAGE_KERNELS = {"k_dilate": ["k_dilate_x", "k_dilate_yz", "k_dilate_yz_tile<8>",
                               "k_dilate_yz_tile<16>"],
                  "k_rays": [f"k_rays<{g}, {b}, {l}>" for g in ("false", "true")
                             for b in ("false", "true") for l in ("false", "true")],
                  "k_resolve": ["k_resolve<false>", "k_resolve<true>"]}
+
+
+def log(msg):
+    print(f"# {msg}", file=sys.stderr, flush=True)
+
+
+def host_workers():
+    """Worker processes / threads for host work: at most 16 (one GPU's share
+    of the host) and no more than this process may use."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_model():
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name"):
+                return line.split(":", 1)[1].strip()
+    except Exception:
+        pass
+    return platform.processor() or "unknown"
+
+
+def host_info():
+    try:
+        nproc = int(subprocess.run(["nproc"], capture_output=True, text=True,
+                                   timeout=10).stdout.strip())
+    except Exception:
+        nproc = os.cpu_count()
+    return {"lscpu_model": cpu_model(), "nproc": nproc, "cpu_count": os.cpu_count()}
+
+
+def pct(a, nd=5):
+    a = np.asarray(a, float)
+    return {"p50": round(float(np.percentile(a, 50)), nd),
+            "p99": round(float(np.percentile(a, 99)), nd),
+            "mean": round(float(a.mean()), nd), "samples": int(a.size)}
 
 
 def calibration_copy(torch):
@@ -76,7 +128,7 @@ def calibration_copy(torch):
     del cal_src, cal_dst, cal_evict
 
 
-def measured_traffic(stage, path=TRAFFIC_FILE, workload=WORKLOAD):
+def measured_traffic(stage, path, workload):
     """Memory-side bytes per launch of a stage's kernels from the committed
     counter summary, or None if absent or taken on kernel sources that have
     changed since."""
@@ -97,15 +149,65 @@ def measured_traffic(stage, path=TRAFFIC_FILE, workload=WORKLOAD):
     return float(sum(k["hbm_bytes_per_launch"] * k.get("launches", 1) for k in got)) / n
 
 
-def cpu_model():
-    try:
-        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
-        for line in out.splitlines():
-            if line.startswith("Model name"):
-                return line.split(":", 1)[1].strip()
-    except Exception:
-        pass
-    return platform.processor() or "unknown"
+# ------------------------------------------------ inputs (worker processes)
+
+_TRAJ = {}
+
+
+def _seq_frame(arg):
+    from paper_2112_13169_amd import scenes
+    name, n, k = arg
+    if (name, n) not in _TRAJ:
+        _TRAJ[(name, n)] = scenes.make_trajectory(name, n_frames=n)
+    return scenes.trajectory_frame(_TRAJ[(name, n)], k)
+
+
+def _pool_map(fn, args, chunksize=4):
+    import multiprocessing as mp
+    with mp.get_context("fork").Pool(host_workers()) as pool:
+        return pool.map(fn, args, chunksize=chunksize)
+
+
+def save_frames(path, frames):
+    """A rendered sequence as <path>.npz (arrays) + <path>.json (sensor and
+    grid description)."""
+    f0 = frames[0]
+    arrays = dict(depth=np.stack([f.depth for f in frames]), R=np.stack([f.R for f in frames]),
+                  t=np.stack([f.t for f in frames]), origin=np.stack([f.origin for f in frames]))
+    if f0.kind == "spinning":
+        arrays.update(col_tab=f0.col_tab, row_tab=f0.row_tab)
+    np.savez(path + ".npz", **arrays)
+    with open(path + ".json", "w") as fh:
+        json.dump(dict(intr=f0.intr, dims=list(f0.dims), vox_size=f0.vox_size,
+                       vox_inf=f0.vox_inf, kind=f0.kind, n=len(frames)), fh)
+
+
+def load_frames(path):
+    from paper_2112_13169_amd import scenes
+    with open(path + ".json") as fh:
+        meta = json.load(fh)
+    a = np.load(path + ".npz")
+    col, row = (a["col_tab"], a["row_tab"]) if meta["kind"] == "spinning" else (None, None)
+    return [scenes.Frame(depth=a["depth"][k], R=a["R"][k], t=a["t"][k], intr=meta["intr"],
+                         dims=tuple(meta["dims"]), vox_size=meta["vox_size"],
+                         vox_inf=meta["vox_inf"], origin=a["origin"][k], kind=meta["kind"],
+                         col_tab=col, row_tab=row) for k in range(meta["n"])]
+
+
+def sequence_frames(name, n, cache=None):
+    """The first n frames of a named trajectory (scenes.SEQUENCES), rendered
+    in worker processes, or read from `cache` (a directory) when it holds
+    them (a cache lets a profiled run skip the rendering)."""
+    if n <= 0:
+        return []
+    path = os.path.join(cache, f"{name}-{n}") if cache else None
+    if path and os.path.exists(path + ".json"):
+        return load_frames(path)
+    frames = _pool_map(_seq_frame, [(name, n, k) for k in range(n)])
+    if path:
+        os.makedirs(cache, exist_ok=True)
+        save_frames(path, frames)
+    return frames
 
 
 def _batch_frame(arg):
@@ -114,14 +216,9 @@ def _batch_frame(arg):
     return scenes.batched_frame(np.random.default_rng([scenes.SEED_BASE + 2, key, k]))
 
 
-def batch_recipe_frames(n, key=64, workers=8):
-    """n independent frames of the batch recipe (seeded per frame), rendered
-    in worker processes before the GPU is touched."""
-    import multiprocessing as mp
-    if n <= 0:
-        return []
-    with mp.get_context("fork").Pool(max(1, min(workers, os.cpu_count() or 1))) as pool:
-        return pool.map(_batch_frame, [(key, k) for k in range(n)])
+def batch_recipe_frames(n, key=64):
+    """n independent frames of the batch recipe (seeded per frame)."""
+    return _pool_map(_batch_frame, [(key, k) for k in range(n)], 1) if n > 0 else []
 
 
 _FLEET = {}
@@ -136,261 +233,423 @@ def _fleet_frame(arg):
     return scenes.trajectory_frame(_FLEET[key][r], k, robot=r)
 
 
-def served_frames(n_robots, n_frames, workers=8):
-    """frames[r][k]: robot r's k-th frame of the served fleet, rendered in
-    worker processes before the GPU is touched."""
-    import multiprocessing as mp
+def served_frames(n_robots, n_frames):
+    """frames[r][k]: robot r's k-th frame of the served fleet."""
     if n_robots <= 0 or n_frames <= 0:
         return {}
     args = [(n_robots, n_frames, r, k) for r in range(n_robots) for k in range(n_frames)]
-    with mp.get_context("fork").Pool(max(1, min(workers, os.cpu_count() or 1))) as pool:
-        flat = pool.map(_fleet_frame, args, chunksize=8)
+    flat = _pool_map(_fleet_frame, args, 8)
     return {r: flat[r * n_frames:(r + 1) * n_frames] for r in range(n_robots)}
 
 
-def run_served(frames, torch, vg, serve, rate_hz=30.0):
-    """Continuous-batching server over the fleet's frames: real-time Poisson
-    arrivals with room for every grid, the same with a budget of three
-    quarters of the grids (evictions), and every frame at once (capacity)."""
-    n_robots = len(frames)
-    n_frames = len(frames[0])
-    f0 = frames[0][0]
-    sensor = vg.pinhole_sensor(f0.intr)
-    backend = serve.GpuBackend(torch, vg, frames, sensor, streams=2, max_batch=64)
-    gbytes = backend.grid_bytes(f0.dims, f0.vox_inf)
-    fbytes = f0.depth.nbytes
-    fixed = 2 * backend.workspace_bytes(64)
-    out = {}
-    for name, grids, speed in [("realtime", n_robots, 1.0),
-                               ("realtime, tight budget", (3 * n_robots) // 4, 1.0),
-                               ("all at once", n_robots, float("inf"))]:
-        robots = [serve.Robot(r, f0.dims, f0.vox_size, frames[r][0].origin, f0.vox_inf)
-                  for r in range(n_robots)]
-        budget = fixed + grids * gbytes + 16 * fbytes
-        srv = serve.Server(backend, robots, fbytes, budget, max_batch=64, streams=2)
-        arrivals = serve.poisson_arrivals(n_robots, n_frames, rate_hz,
-                                          np.random.default_rng([2112131694, n_robots]))
+def _pool_frame(arg):
+    from paper_2112_13169_amd import scenes
+    workload, i = arg
+    return scenes.make_frame(workload, i)
+
+
+def pool_frames(workload, n):
+    return _pool_map(_pool_frame, [(workload, i) for i in range(n)]) if n > 0 else []
+
+
+# ------------------------------------------------------------ GPU sequences
+
+class Sequence:
+    """Frames of one grid on the GPU: depth resident, sensor and poses built
+    once, fresh grids on demand."""
+
+    def __init__(self, frames, torch, vg):
+        self.frames, self.torch, self.vg = frames, torch, vg
+        f0 = frames[0]
+        self.f0 = f0
+        self.dev = [torch.from_numpy(f.depth).cuda() for f in frames]
+        if f0.kind == "spinning":
+            self.tabs = (torch.from_numpy(f0.col_tab).cuda(), torch.from_numpy(f0.row_tab).cuda())
+            H, W = f0.depth.shape
+            self.sensor = vg.spinning_sensor(W, H, *self.tabs, f0.intr["vfov"],
+                                             f0.intr["depth_min"], f0.intr["depth_max"])
+        else:
+            self.sensor = vg.pinhole_sensor(f0.intr)
+        self.poses = [vg.make_pose(f.R, f.t) for f in frames]
+        self.n = len(frames)
+        self.nvox = int(np.prod(f0.dims))
+        self.tile = 3
+        self.keep = []
+
+    def new_grid(self):
+        vg = self.vg
+        b = vg.GridBuffers(self.f0.dims, self.f0.vox_inf)
+        h = vg.vg_create_grid(self.f0.dims, self.f0.vox_size, self.f0.origin, self.f0.vox_inf,
+                              b.loc, b.spare, b.scratch)
+        vg.vg_set_ray_tile(h, self.tile)
+        self.keep.append((h, b))
+        return h
+
+    def drop(self, h):
+        self.vg.vg_destroy_grid(h)
+        self.keep = [(g, b) for g, b in self.keep if g is not h]
+
+    def step(self, h, k):
+        """Frame k mod n: re-centre on its camera and integrate it (one call)."""
+        i = k % self.n
+        self.vg.vg_integrate_frame_shifted(h, self.dev[i], self.sensor, self.poses[i],
+                                           self.vg.vg_center_offset(h, self.frames[i].t))
+
+    def batch(self, h, i0, m, ws):
+        """Frames i0 .. i0+m-1 as one batch, each re-centring the grid."""
+        idx = list(range(i0, min(i0 + m, self.n)))
+        sh = self.vg.sequence_shifts(h, [self.frames[i].t for i in idx])
+        self.vg.vg_integrate_batch([self.vg.frame_image(h, self.dev[i], self.sensor,
+                                                        self.poses[i], d)
+                                    for i, d in zip(idx, sh)], ws)
+
+    def read(self, h):
+        out = self.torch.empty(self.nvox, dtype=self.torch.uint8, device="cuda")
+        self.vg.vg_read_grid(h, out)
+        return out
+
+
+def run_sequence(seq, K, W, B, torch, vg, timed=True, pass_steps=None):
+    """The plain path (one frame per call) and B-frame batches over a
+    sequence.  The stage, walk and latency passes each run pass_steps steps
+    (default: the whole sequence once) from a fresh grid.  Returns the figures
+    and the plain path's grid after those steps."""
+    E = vg.PROFILE_EVENTS
+    names = list(vg.PROFILE_STAGES)
+    n = seq.n if pass_steps is None else pass_steps
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    res = {}
+    # timed region: K steps continuing the sequence after W warm-up steps
+    if timed:
+        h = seq.new_grid()
+        for k in range(W):
+            seq.step(h, k)
         torch.cuda.synchronize()
         w0 = time.perf_counter()
-        done = srv.run(arrivals, speed=speed)
+        for k in range(W, W + K):
+            seq.step(h, k)
         torch.cuda.synchronize()
         wall = time.perf_counter() - w0
-        entry = {"frames": len(done), "wall_s": round(wall, 4),
-                 "frames_per_s": round(len(done) / wall, 1),
-                 "latency": serve.latency_summary(done),
-                 "batches": srv.stats.batches,
-                 "mean_batch": round(float(np.mean(srv.stats.batch_sizes)), 2),
-                 "max_batch": int(max(srv.stats.batch_sizes)),
-                 "evictions": srv.stats.evictions, "restores": srv.stats.restores,
-                 "budget_MB": round(budget / 2 ** 20, 1),
-                 "peak_MB": round(srv.stats.peak_bytes / 2 ** 20, 1)}
-        if name == "realtime, tight budget":
-            # two robots' served grids against the same frames alone
-            same = True
-            for r in (0, n_robots - 1):
-                b = vg.GridBuffers(f0.dims, f0.vox_inf)
-                h = vg.vg_create_grid(f0.dims, f0.vox_size, frames[r][0].origin, f0.vox_inf,
-                                      b.loc, b.spare, b.scratch)
-                for f in frames[r]:
-                    vg.vg_shift_grid(h, *vg.vg_center_offset(h, f.t))
-                    vg.vg_integrate_frame(h, torch.from_numpy(f.depth).cuda(), sensor,
-                                          vg.make_pose(f.R, f.t))
-                alone = torch.empty(int(np.prod(f0.dims)), dtype=torch.uint8, device="cuda")
-                vg.vg_read_grid(h, alone)
-                torch.cuda.synchronize()
-                same = same and bool(np.array_equal(backend.read(srv.robots[r]),
-                                                    alone.cpu().numpy()))
-                vg.vg_destroy_grid(h)
-            entry["bit_exact_vs_alone"] = same
-        for rb in srv.robots.values():
-            vg.vg_destroy_grid(rb.handle)
-        out[name] = entry
+        res["timed"] = {"steps": K, "warmup": W, "wall_s": wall,
+                        "ms_per_step": wall * 1e3 / K, "frames_per_s": K / wall}
+        seq.drop(h)
+
+    # stage pass: every stage timed by its own launches, every frame
+    h = seq.new_grid()
+    st_ev = [ev() for _ in range(E * n)]
+    vg.vg_set_profile_events(h, st_ev)
+    for k in range(n):
+        seq.step(h, k)
+    torch.cuda.synchronize()
+    vg.vg_set_profile_events(h, [])
+    stage = {}
+    for j, nm in enumerate(names):
+        if nm != "shift":     # its clear runs inside the walk launch (markers only)
+            stage["k_" + nm] = np.array([st_ev[E * k + 2 * j].elapsed_time(st_ev[E * k + 2 * j + 1])
+                                         for k in range(n)])
+    res["stage_ms"] = {k: round(float(v.mean()), 5) for k, v in stage.items()}
+    seq.drop(h)
+
+    # walk pass: only the walk's own launches record events (every frame)
+    h = seq.new_grid()
+    j = names.index("rays")
+    row_ev = []
+    for k in range(n):
+        row = [None] * E
+        row[2 * j], row[2 * j + 1] = ev(), ev()
+        row_ev += row
+    vg.vg_set_profile_events(h, row_ev)
+    for k in range(n):
+        seq.step(h, k)
+    torch.cuda.synchronize()
+    vg.vg_set_profile_events(h, [])
+    res["walk_ms"] = np.array([row_ev[E * k + 2 * j].elapsed_time(row_ev[E * k + 2 * j + 1])
+                               for k in range(n)])
+    plain_grid = seq.read(h)
+    torch.cuda.synchronize()
+    seq.drop(h)
+
+    # latency pass: start of the frame's call (shift marker) .. end of its merge
+    h = seq.new_grid()
+    i_shift, i_res = names.index("shift"), names.index("resolve")
+    lat_ev = []
+    for k in range(n):
+        row = [None] * E
+        row[2 * i_shift], row[2 * i_res + 1] = ev(), ev()
+        lat_ev += row
+    vg.vg_set_profile_events(h, lat_ev)
+    for k in range(n):
+        seq.step(h, k)
+    torch.cuda.synchronize()
+    vg.vg_set_profile_events(h, [])
+    res["latency_ms"] = pct([lat_ev[E * k + 2 * i_shift].elapsed_time(lat_ev[E * k + 2 * i_res + 1])
+                             for k in range(n)])
+    seq.drop(h)
+
+    # the whole sequence, plain, wall clock (no events)
+    h = seq.new_grid()
+    for k in range(n):
+        seq.step(h, k)
+    torch.cuda.synchronize()
+    seq.drop(h)
+    h = seq.new_grid()
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for k in range(n):
+        seq.step(h, k)
+    torch.cuda.synchronize()
+    plain_wall = time.perf_counter() - w0
+    seq.drop(h)
+
+    # B-frame batches over the whole sequence: a warm pass, a timed pass (wall
+    # clock) whose final grid is compared with the plain path's, and a pass
+    # with an event pair around every batch (latency)
+    if B > 0:
+        ws = torch.empty(vg.vg_batch_workspace_bytes(B), dtype=torch.uint8, device="cuda")
+        h = seq.new_grid()
+        for i0 in range(0, n, B):
+            seq.batch(h, i0, B, ws)
+        torch.cuda.synchronize()
+        seq.drop(h)
+        h = seq.new_grid()
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        for i0 in range(0, n, B):
+            seq.batch(h, i0, B, ws)
+        torch.cuda.synchronize()
+        batch_wall = time.perf_counter() - w0
+        same = bool(torch.equal(seq.read(h), plain_grid))
+        seq.drop(h)
+        h = seq.new_grid()
+        pairs = []
+        for i0 in range(0, n, B):
+            a, b = ev(), ev()
+            a.record()
+            seq.batch(h, i0, B, ws)
+            b.record()
+            pairs.append((a, b))
+        torch.cuda.synchronize()
+        seq.drop(h)
+        res["batched"] = {
+            "frames_per_batch": B, "frames": n,
+            "frames_per_s": round(n / batch_wall, 1),
+            "ms_per_frame": round(batch_wall * 1e3 / n, 5),
+            "plain_frames_per_s_same_pass": round(n / plain_wall, 1),
+            "speedup_vs_plain": round(plain_wall / batch_wall, 4),
+            "batch_latency_ms": pct([a.elapsed_time(b) for a, b in pairs]),
+            "bit_exact_vs_plain": same,
+            "note": "the whole sequence as consecutive batches of frames_per_batch frames, "
+                    "each frame re-centring the grid (vg_integrate_batch); a frame's latency "
+                    "in a batch is its batch's latency; plain_frames_per_s_same_pass is the "
+                    "one-frame-per-call path over the same frames, wall clock"}
+    res["plain_sequence"] = {"frames": n, "frames_per_s": round(n / plain_wall, 1),
+                             "ms_per_frame": round(plain_wall * 1e3 / n, 5)}
+    return res, plain_grid
+
+
+# ------------------------------------------------------------- oracle legs
+
+def recentre_plan(frames, oracle):
+    """Per frame of a sequence started on a fresh grid at frames[0].origin:
+    the re-centring shift and the grid origin the frame is integrated at."""
+    f0 = frames[0]
+    base = f0.origin.astype(np.float32)
+    total = np.zeros(3, np.int32)
+    plan = []
+    for f in frames:
+        d = oracle.center_offset(f0.dims, f0.vox_size, oracle.origin(base, total, f0.vox_size), f.t)
+        total = total + np.asarray(d, np.int32)
+        plan.append((d, oracle.origin(base, total, f0.vox_size)))
+    return plan
+
+
+def oracle_step(loc, f, d, org, oracle):
+    loc = oracle.shift(loc, d)
+    if f.kind == "spinning":
+        _, st = oracle.integrate_spinning(loc, org, f.vox_size, f.vox_inf, f.depth, f.col_tab,
+                                          f.row_tab, f.intr["vfov"], f.intr["depth_min"],
+                                          f.intr["depth_max"],
+                                          np.asarray(f.R, np.float32).reshape(-1),
+                                          np.asarray(f.t, np.float32), want_ms=False)
+    else:
+        _, st = oracle.integrate_pinhole(loc, org, f.vox_size, f.vox_inf, f.depth, f.intr, f.R,
+                                         f.t, want_ms=False)
+    return loc, st
+
+
+def oracle_sequence(frames, plan, seconds, oracle, min_frames=2):
+    """The oracle on the first frames of a sequence, one after another on one
+    thread (re-centre + integrate), until `seconds` of CPU time (at least
+    min_frames).  Returns (frames run, per-frame seconds, final grid)."""
+    f0 = frames[0]
+    loc = np.zeros(f0.dims[::-1], np.uint8)
+    times = []
+    for i, f in enumerate(frames):
+        if i >= min_frames and sum(times) >= seconds:
+            break
+        c0 = time.perf_counter()
+        loc, _ = oracle_step(loc, f, *plan[i], oracle)
+        times.append(time.perf_counter() - c0)
+    return len(times), times, loc
+
+
+def oracle_stats(frames, plan, idx, oracle):
+    """Voxel updates and in-grid walk steps of the sampled frames (they depend
+    on the frame and the grid origin, not on the grid's content), from the
+    oracle on every host thread (one frame per thread at a time)."""
+    from concurrent.futures import ThreadPoolExecutor
+    threads = host_workers()
+
+    def one(i):
+        f = frames[i]
+        loc = np.zeros(f.dims[::-1], np.uint8)
+        c0 = time.perf_counter()
+        _, st = oracle_step(loc, f, (0, 0, 0), plan[i][1], oracle)
+        return st, time.perf_counter() - c0
+
+    w0 = time.perf_counter()
+    with ThreadPoolExecutor(threads) as pool:
+        got = list(pool.map(one, idx))
+    wall = time.perf_counter() - w0
+    return [g[0] for g in got], [g[1] for g in got], wall, threads
+
+
+def walk_roofline(steps, walk_ms, kernel, traffic, note):
+    units = float(np.mean(steps))
+    achieved = float(np.sum(steps)) * OPS_PER_STEP / (float(np.sum(walk_ms)) * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 1),
+            "unit": "TOP/s", "frac": round(achieved / ALU_PEAK_TOPS, 4), "traffic": traffic,
+            "kernel": kernel, "units_per_launch": round(units, 1),
+            "unit_kind": "in-grid walk steps", "ops_per_unit": OPS_PER_STEP,
+            "kernel_ms": round(float(np.mean(walk_ms)), 5), "note": note}
+
+
+# ------------------------------------------------------------------ headline
+
+def run_headline(frames, args, torch, vg, autotune):
+    import oracle
+    seq = Sequence(frames, torch, vg)
+    f0 = seq.f0
+    vd, hw, hh, rays = vg.vg_fan_sizes(seq.sensor, f0.vox_size)
+    # ray-bundle shape from the autotuner (one fan class), on a scratch grid
+    if not args.no_tune:
+        th = seq.new_grid()
+        table = autotune.tune([(seq.sensor, f0.vox_size, th,
+                                lambda: vg.vg_integrate_frame(th, seq.dev[0], seq.sensor,
+                                                              seq.poses[0]))], vg, torch, reps=3)
+        seq.tile = autotune.choose(table, seq.sensor, f0.vox_size, vg)
+        seq.drop(th)
+    log(f"headline: {seq.n} frames, ray tile {1 << seq.tile}x{64 >> seq.tile}")
+    res, plain_grid = run_sequence(seq, args.steps, args.warmup, args.seq_batch, torch, vg)
+    log("headline GPU passes done")
+
+    out = {"plain_grid": plain_grid, "res": res}
+    plan = recentre_plan(frames, oracle)
+    # parity and the single-thread CPU baseline: the first frames, in order
+    if args.cpu_seconds > 0:
+        nc, times, ref = oracle_sequence(frames, plan, args.cpu_seconds, oracle)
+        h = seq.new_grid()
+        for k in range(nc):
+            seq.step(h, k)
+        got = seq.read(h).cpu().numpy()
+        seq.drop(h)
+        out["bit_exact"] = bool(np.array_equal(got, ref.reshape(-1)))
+        out["oracle_frames"] = nc
+        out["cpu_baseline"] = {
+            "value": round(nc / sum(times), 4), "unit": "frames/s", "cores": 1, "kind": "oracle",
+            "sample": f"the first {nc} frames of the same sequence (re-centre + integrate), "
+                      f"one after another on one thread, {sum(times):.1f} s; the GPU grid "
+                      f"after the same frames is compared with the oracle's",
+            **host_info()}
+        log(f"oracle: {nc} frames in {sum(times):.1f} s, bit-exact={out['bit_exact']}")
+    # voxel updates and walk steps of sampled frames, on every host thread
+    if args.stat_frames > 0:
+        S = min(args.stat_frames, seq.n)
+        idx = sorted({int(round(j * (seq.n - 1) / max(S - 1, 1))) for j in range(S)})
+        stats, secs, wall, threads = oracle_stats(frames, plan, idx, oracle)
+        out["stats_idx"] = idx
+        out["stats"] = stats
+        out["cpu_baseline_parallel"] = {
+            "value": round(len(idx) / wall, 4), "unit": "frames/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{len(idx)} frames spread over the sequence, each integrated into a "
+                      f"fresh grid at its re-centred origin, {threads} threads (one frame "
+                      f"each at a time), {wall:.1f} s wall",
+            **host_info()}
+        log(f"oracle stats: {len(idx)} frames on {threads} threads in {wall:.1f} s")
+    # PCIe-inclusive rate: each frame uploaded from pinned host memory first
+    host = [torch.from_numpy(f.depth).pin_memory() for f in frames]
+    stage_dev = torch.empty_like(seq.dev[0])
+    h = seq.new_grid()
+    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+             for _ in range(seq.n)]
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for k, (a, b) in enumerate(pairs):
+        a.record()
+        stage_dev.copy_(host[k], non_blocking=True)
+        vg.vg_integrate_frame_shifted(h, stage_dev, seq.sensor, seq.poses[k],
+                                      vg.vg_center_offset(h, frames[k].t))
+        b.record()
+    torch.cuda.synchronize()
+    out["with_h2d"] = {"frames_per_s": round(seq.n / (time.perf_counter() - w0), 1),
+                       "latency_ms": pct([a.elapsed_time(b) for a, b in pairs]),
+                       "note": "each frame's 3.7 MB depth image is first copied from pinned host "
+                               "memory on the same stream; not the headline value"}
+    seq.drop(h)
+    out.update(vd=vd, hw=hw, hh=hh, rays=rays, tile=seq.tile, n=seq.n)
     return out
 
 
-def _large_frame(arg):
-    from paper_2112_13169_amd import scenes
-    name, n, k = arg
-    return scenes.trajectory_frame(scenes.make_trajectory(name, n_frames=n), k)
+# ------------------------------------------------------- other workloads
 
-
-def large_frames(n, workers=8):
-    """n consecutive frames of each large sequence (1280x720 pinhole and
-    128x2048 spinning, 400x400x200 grids), rendered in worker processes."""
-    import multiprocessing as mp
-    if n <= 0:
-        return {}
-    names = ["large-pinhole", "large-spinning"]
-    with mp.get_context("fork").Pool(max(1, min(workers, os.cpu_count() or 1))) as pool:
-        flat = pool.map(_large_frame, [(nm, n, k) for nm in names for k in range(n)])
-    return {nm: flat[i * n:(i + 1) * n] for i, nm in enumerate(names)}
-
-
-# The paper's own GPU times for its standard parameters (RTX 2060, Table II):
-# populate occupied 7 us, ray-trace to free 44 us, merge 7 us; 58 us of
-# kernels per frame in all (Sec. V), next to 0.1 / 2.2 / 0.2 ms on one core of
-# an i7-9750H.
-PAPER_STANDARD_US = {"populate": 7.0, "raytrace": 44.0, "merge": 7.0, "kernels": 58.0}
-PAPER_STANDARD_CPU_MS = {"populate": 0.1, "raytrace": 2.2, "merge": 0.2}
-
-
-def run_paper_standard(K, warmup, torch, vg, oracle, scenes):
-    """The paper's standard parameters on the synthetic scene (its Gazebo world
-    is not available): 8 seeded frames of random pose cycled through one grid,
-    re-centred each frame, one frame per call; per-stage times from the
-    stages' own launches beside the paper's Table II, and the grid after one
-    cycle against the oracle."""
-    frames = [scenes.make_frame("paper-standard", k) for k in range(8)]
-    f0 = frames[0]
-    sensor = vg.pinhole_sensor(f0.intr)
-    dev = [torch.from_numpy(f.depth).cuda() for f in frames]
-    poses = [vg.make_pose(f.R, f.t) for f in frames]
-    buf = vg.GridBuffers(f0.dims, f0.vox_inf)
-    h = vg.vg_create_grid(f0.dims, f0.vox_size, f0.origin, f0.vox_inf, buf.loc, buf.spare,
-                          buf.scratch)
-
-    def step(k):
-        i = k % len(frames)
-        vg.vg_integrate_frame_shifted(h, dev[i], sensor, poses[i],
-                                      vg.vg_center_offset(h, frames[i].t))
-
-    # one cycle on the fresh grid against the oracle's shift + integrate
-    ref = np.zeros(f0.dims[::-1], np.uint8)
-    base = f0.origin.astype(np.float32)
-    total = np.zeros(3, np.int32)
-    for k, f in enumerate(frames):
-        d = oracle.center_offset(f0.dims, f0.vox_size, oracle.origin(base, total, f0.vox_size),
-                                 f.t)
-        ref = oracle.shift(ref, d)
-        total = total + np.asarray(d, np.int32)
-        oracle.integrate_pinhole(ref, oracle.origin(base, total, f0.vox_size), f0.vox_size,
-                                 f0.vox_inf, f.depth, f.intr, f.R, f.t, want_ms=False)
-        step(k)
-    got = torch.empty(ref.size, dtype=torch.uint8, device="cuda")
-    vg.vg_read_grid(h, got)
-    torch.cuda.synchronize()
-    same = bool(np.array_equal(got.cpu().numpy(), ref.reshape(-1)))
-
-    # stages timed by their own launches
-    E = vg.PROFILE_EVENTS
-    evs = [torch.cuda.Event(enable_timing=True) for _ in range(E * K)]
-    for k in range(warmup):
-        step(k)
-    vg.vg_set_profile_events(h, evs)
-    for k in range(K):
-        step(k)
-    torch.cuda.synchronize()
-    vg.vg_set_profile_events(h, [])
-    stage_us = {}
-    for j, name in enumerate(vg.PROFILE_STAGES):
-        if name != "shift":
-            stage_us[name] = round(float(np.mean([evs[E * k + 2 * j].elapsed_time(
-                evs[E * k + 2 * j + 1]) for k in range(K)])) * 1e3, 2)
-    # whole steps, no events
-    for k in range(warmup):
-        step(k)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    for k in range(K):
-        step(k)
-    torch.cuda.synchronize()
-    us = (time.perf_counter() - w0) * 1e6 / K
-    vg.vg_destroy_grid(h)
-    rays = vg.vg_fan_sizes(sensor, f0.vox_size)[3]
-    ours = {"populate": round(stage_us["seed"] + stage_us["dilate"], 2),
-            "raytrace": stage_us["rays"], "merge": stage_us["resolve"]}
+def run_pool(workload, frames, K, W, torch, vg, oracle, check=8):
+    """A pool of seeded frames of random pose cycled through one resident
+    grid, each frame re-centring it (one call per frame): frames/s, latency
+    over every step, stage times; the first `check` frames against the
+    oracle."""
+    seq = Sequence(frames, torch, vg)
+    res, _ = run_sequence(seq, K, W, 0, torch, vg, pass_steps=K)
+    plan = recentre_plan(frames, oracle)
+    nc = min(check, len(frames))
+    ref = np.zeros(seq.f0.dims[::-1], np.uint8)
+    for i in range(nc):
+        ref, _ = oracle_step(ref, frames[i], *plan[i], oracle)
+    h = seq.new_grid()
+    for k in range(nc):
+        seq.step(h, k)
+    same = bool(np.array_equal(seq.read(h).cpu().numpy(), ref.reshape(-1)))
+    seq.drop(h)
+    # walk steps and updates of the first frames (fresh grids at their origins)
+    stats = [oracle_step(np.zeros(seq.f0.dims[::-1], np.uint8), frames[i], (0, 0, 0),
+                         plan[i][1], oracle)[1] for i in range(nc)]
+    walk = res["walk_ms"][:nc]
+    t = res["timed"]
     return {
-        "workload": "the paper's standard parameters: 320x240 depth, 85x101 deg as printed, "
-                    "0.3-6.5 m, 100x100x20 voxels of 0.15 m (200 000), vox_inf 2, "
-                    f"{rays} rays; synthetic scene (ground + 20 boxes, 2 % invalid pixels) "
-                    "for its Gazebo world; each frame re-centres the grid",
-        "steps": K,
-        "us_per_frame": round(us, 2),
-        "frames_per_s": round(1e6 / us, 1),
-        "stage_us": ours,
-        "stage_us_kernels_sum": round(sum(ours.values()), 2),
-        "paper_rtx2060_us": PAPER_STANDARD_US,
-        "paper_i7_one_core_ms": PAPER_STANDARD_CPU_MS,
-        "note": "stage_us: populate = seed + dilation launches, raytrace = walk launch (it "
-                "also runs the re-centring clear), merge = merge launch; each from the "
-                "start of its first launch to the end of its last",
-        "bit_exact": same,
+        "workload": workload, "frame_pool": len(frames),
+        "frames_per_s": round(t["frames_per_s"], 1), "ms_per_step": round(t["ms_per_step"], 5),
+        "steps": K, "warmup": W,
+        "latency_ms": res["latency_ms"],
+        "stage_ms": res["stage_ms"],
+        "walk_ms": pct(res["walk_ms"]),
+        "voxel_updates_per_frame": round(float(np.mean([s["updates"] for s in stats])), 1),
+        "walk_steps_per_frame": round(float(np.mean([s["steps"] for s in stats])), 1),
+        "walk_roofline": walk_roofline([s["steps"] for s in stats], walk,
+                                       "k_rays", None, f"first {nc} frames of the pool"),
+        "bit_exact": same, "oracle_frames": nc,
     }
 
 
-def run_large(seqs, torch, vg, passes=3):
-    """Each large sequence into its own 400x400x200 grid, re-centred before
-    every frame: one frame per call (shift + integrate) against the whole
-    sequence as one batch; both end bit-identical."""
-    out = {}
-    for name, frames in seqs.items():
-        f0 = frames[0]
-        dev = [torch.from_numpy(f.depth).cuda() for f in frames]
-        if f0.kind == "spinning":
-            tabs = (torch.from_numpy(f0.col_tab).cuda(), torch.from_numpy(f0.row_tab).cuda())
-            H, W = f0.depth.shape
-            sensor = vg.spinning_sensor(W, H, *tabs, f0.intr["vfov"], f0.intr["depth_min"],
-                                        f0.intr["depth_max"])
-        else:
-            sensor = vg.pinhole_sensor(f0.intr)
-        poses = [vg.make_pose(f.R, f.t) for f in frames]
-        grids = []
-        for _ in range(2):
-            b = vg.GridBuffers(f0.dims, f0.vox_inf)
-            grids.append((b, vg.vg_create_grid(f0.dims, f0.vox_size, f0.origin, f0.vox_inf, b.loc,
-                                               b.spare, b.scratch)))
-        (_, ha), (_, hb) = grids
-        ws = torch.empty(vg.vg_batch_workspace_bytes(len(frames)), dtype=torch.uint8,
-                         device="cuda")
-
-        def plain_pass():
-            for f, d, p in zip(frames, dev, poses):
-                vg.vg_integrate_frame_shifted(ha, d, sensor, p, vg.vg_center_offset(ha, f.t))
-
-        def batch_pass():
-            shifts = vg.sequence_shifts(hb, [f.t for f in frames])
-            vg.vg_integrate_batch([vg.frame_image(hb, d, sensor, p, sh)
-                                   for d, p, sh in zip(dev, poses, shifts)], ws)
-
-        def timed(step):
-            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-                  for _ in range(passes)]
-            for a, b in ev:
-                a.record()
-                step()
-                b.record()
-            torch.cuda.synchronize()
-            return np.array([a.elapsed_time(b) for a, b in ev])
-
-        plain_pass()
-        batch_pass()
-        torch.cuda.synchronize()
-        n = int(np.prod(f0.dims))
-        ga = torch.empty(n, dtype=torch.uint8, device="cuda")
-        gb = torch.empty(n, dtype=torch.uint8, device="cuda")
-        vg.vg_read_grid(ha, ga)
-        vg.vg_read_grid(hb, gb)
-        torch.cuda.synchronize()
-        same = bool(torch.equal(ga, gb))
-        tp = timed(plain_pass)
-        tb = timed(batch_pass)
-        rays = vg.vg_fan_sizes(sensor, f0.vox_size)[3]
-        out[name] = {"frames_per_pass": len(frames), "passes": passes, "rays_per_frame": rays,
-                     "plain_ms_per_frame": round(float(np.median(tp)) / len(frames), 4),
-                     "batched_ms_per_frame": round(float(np.median(tb)) / len(frames), 4),
-                     "plain_frames_per_s": round(len(frames) * 1e3 / float(np.median(tp)), 1),
-                     "batched_frames_per_s": round(len(frames) * 1e3 / float(np.median(tb)), 1),
-                     "bit_exact_batched_vs_plain": same}
-        for _, h in grids:
-            vg.vg_destroy_grid(h)
-    return out
-
-
 def run_batched(frames, K, warmup, torch, vg, oracle, autotune, sample_oracle=(),
-                walk_steps=None, tune=True):
+                walk_steps=None, tune=True, graph=False):
     """Batched vs plain on the same frames, each frame with its own grid: one
     vg_integrate_batch call per step against len(frames) vg_integrate_frame
-    calls per step.  Returns the figures of both and whether they agree."""
+    calls per step.  graph: the batch call is also captured into a HIP graph
+    and replayed (the same frames each replay).  Returns the figures of both
+    and whether they agree."""
     n = len(frames)
     dev = [torch.from_numpy(f.depth).cuda() for f in frames]
     sensors = [vg.pinhole_sensor(f.intr) for f in frames]
@@ -453,12 +712,14 @@ def run_batched(frames, K, warmup, torch, vg, oracle, autotune, sample_oracle=()
             vg.vg_integrate_batch_timed(descs, ws, row)
             rows.append(row)
         torch.cuda.synchronize()
-        return float(np.mean([r[2 * j].elapsed_time(r[2 * j + 1]) for r in rows]))
+        return [r[2 * j].elapsed_time(r[2 * j + 1]) for r in rows]
 
     classes = {}
     for (_, ha), s, f in zip(A, sensors, frames):
         classes.setdefault(autotune.fan_class(s, f.vox_size, vg), []).append(ha)
-    btable = autotune.tune_batch(classes, vg.vg_set_ray_tile, batch_rays_ms, reps=3) if tune else {}
+    btable = autotune.tune_batch(classes, vg.vg_set_ray_tile,
+                                 lambda reps=1: float(np.mean(batch_rays_ms(reps))),
+                                 reps=3) if tune else {}
 
     def timed(step):
         for _ in range(warmup):
@@ -478,6 +739,36 @@ def run_batched(frames, K, warmup, torch, vg, oracle, autotune, sample_oracle=()
 
     wb, lb = timed(batch_step)
     wp, lp = timed(plain_step)
+    graph_res = None
+    if graph:
+        # the batch call captured into a HIP graph and replayed: a replay
+        # repeats the captured frames (same images, poses, shifts, stamps)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            vg.vg_integrate_batch(descs, ws, s)
+        torch.cuda.synchronize()
+        for _ in range(warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(K)]
+        w0 = time.perf_counter()
+        for a, b in ev:
+            a.record()
+            g.replay()
+            b.record()
+        torch.cuda.synchronize()
+        wg = time.perf_counter() - w0
+        lg = np.array([a.elapsed_time(b) for a, b in ev])
+        same_g = all(bool(torch.equal(read(ha, f), read(hb, f)))
+                     for (_, ha), (_, hb), f in zip(A, B, frames))
+        graph_res = {"graph_replay_frames_per_s": round(n * K / wg, 1),
+                     "graph_replay_ms_per_step": round(wg * 1e3 / K, 4),
+                     "graph_replay_step_latency_ms": pct(lg, 4),
+                     "graph_replay_bit_exact": same_g}
+        del g
 
     # the batched walk kernel's live time: events its own launches record
     rays_ms = batch_rays_ms(K)
@@ -496,55 +787,191 @@ def run_batched(frames, K, warmup, torch, vg, oracle, autotune, sample_oracle=()
         "speedup": round(wp / wb, 3),
         "batched_ms_per_step": round(wb * 1e3 / K, 4),
         "plain_ms_per_step": round(wp * 1e3 / K, 4),
-        "batched_step_latency_ms": {"p50": round(float(np.percentile(lb, 50)), 4),
-                                    "p99": round(float(np.percentile(lb, 99)), 4)},
-        "plain_step_latency_ms": {"p50": round(float(np.percentile(lp, 50)), 4),
-                                  "p99": round(float(np.percentile(lp, 99)), 4)},
+        "batched_step_latency_ms": pct(lb, 4),
+        "plain_step_latency_ms": pct(lp, 4),
         "bit_exact": same,
         "oracle_sampled_frames": list(sample_oracle),
         "ray_tiles_plain": tiles_of(table),
         "ray_tiles_batched": tiles_of(btable),
-        "kb_rays_ms": round(rays_ms, 5),
+        "kb_rays_ms": round(float(np.mean(rays_ms)), 5),
     }
+    if graph_res:
+        result.update(graph_res)
     if walk_steps is not None:
-        units = float(np.sum(walk_steps))
-        achieved = units * OPS_PER_STEP / (rays_ms * 1e-3) / 1e12
-        result["roofline"] = {"bound": "alu", "achieved": round(achieved, 3),
-                              "peak": round(ALU_PEAK_TOPS, 1), "unit": "TOP/s",
-                              "frac": round(achieved / ALU_PEAK_TOPS, 4),
-                              "traffic": measured_traffic("kb_rays", TRAFFIC_FILE_BATCHED,
-                                                          "batched-x16"),
-                              "kernel": "kb_rays", "units_per_launch": units,
-                              "unit_kind": "in-grid walk steps", "ops_per_unit": OPS_PER_STEP,
-                              "kernel_ms": round(rays_ms, 5)}
+        result["roofline"] = walk_roofline([float(np.sum(walk_steps))] * len(rays_ms), rays_ms,
+                                           "kb_rays",
+                                           measured_traffic("kb_rays", TRAFFIC_FILE_BATCHED,
+                                                            "batched-x16"),
+                                           "one batched walk launch over every frame of the step")
     return result
 
+
+def run_served(frames, torch, vg, serve, rate_hz=30.0):
+    """Continuous-batching server over the fleet's frames: real-time Poisson
+    arrivals with room for every grid, the same with a budget of three
+    quarters of the grids (evictions), and every frame at once (capacity)."""
+    n_robots = len(frames)
+    n_frames = len(frames[0])
+    f0 = frames[0][0]
+    sensor = vg.pinhole_sensor(f0.intr)
+    backend = serve.GpuBackend(torch, vg, frames, sensor, streams=2, max_batch=64)
+    gbytes = backend.grid_bytes(f0.dims, f0.vox_inf)
+    fbytes = f0.depth.nbytes
+    fixed = 2 * backend.workspace_bytes(64) + backend.fixed_bytes()
+    reserve = backend.frame_reserve_bytes(fbytes)
+    out = {}
+    for name, grids, speed in [("realtime", n_robots, 1.0),
+                               ("realtime, tight budget", (3 * n_robots) // 4, 1.0),
+                               ("all at once", n_robots, float("inf"))]:
+        robots = [serve.Robot(r, f0.dims, f0.vox_size, frames[r][0].origin, f0.vox_inf)
+                  for r in range(n_robots)]
+        budget = fixed + grids * gbytes + 16 * reserve
+        srv = serve.Server(backend, robots, fbytes, budget, max_batch=64, streams=2)
+        arrivals = serve.poisson_arrivals(n_robots, n_frames, rate_hz,
+                                          np.random.default_rng([2112131694, n_robots]))
+        torch.cuda.synchronize()
+        w0 = time.perf_counter()
+        done = srv.run(arrivals, speed=speed)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - w0
+        entry = {"frames": len(done), "wall_s": round(wall, 4),
+                 "frames_per_s": round(len(done) / wall, 1),
+                 "latency": serve.latency_summary(done),
+                 "batches": srv.stats.batches,
+                 "mean_batch": round(float(np.mean(srv.stats.batch_sizes)), 2),
+                 "max_batch": int(max(srv.stats.batch_sizes)),
+                 "evictions": srv.stats.evictions, "restores": srv.stats.restores,
+                 "budget_MB": round(budget / 2 ** 20, 1),
+                 "peak_MB": round(srv.stats.peak_bytes / 2 ** 20, 1)}
+        if name == "realtime, tight budget":
+            # two robots' served grids against the same frames alone
+            same = True
+            for r in (0, n_robots - 1):
+                b = vg.GridBuffers(f0.dims, f0.vox_inf)
+                h = vg.vg_create_grid(f0.dims, f0.vox_size, frames[r][0].origin, f0.vox_inf,
+                                      b.loc, b.spare, b.scratch)
+                for f in frames[r]:
+                    vg.vg_shift_grid(h, *vg.vg_center_offset(h, f.t))
+                    vg.vg_integrate_frame(h, torch.from_numpy(f.depth).cuda(), sensor,
+                                          vg.make_pose(f.R, f.t))
+                alone = torch.empty(int(np.prod(f0.dims)), dtype=torch.uint8, device="cuda")
+                vg.vg_read_grid(h, alone)
+                torch.cuda.synchronize()
+                same = same and bool(np.array_equal(backend.read(srv.robots[r]),
+                                                    alone.cpu().numpy()))
+                vg.vg_destroy_grid(h)
+            entry["bit_exact_vs_alone"] = same
+        for rb in srv.robots.values():
+            vg.vg_destroy_grid(rb.handle)
+        out[name] = entry
+    return out
+
+
+# The paper's own GPU times for its standard parameters (RTX 2060, Table II):
+# populate occupied 7 us, ray-trace to free 44 us, merge 7 us; 58 us of
+# kernels per frame in all (Sec. V), next to 0.1 / 2.2 / 0.2 ms on one core of
+# an i7-9750H.
+PAPER_STANDARD_US = {"populate": 7.0, "raytrace": 44.0, "merge": 7.0, "kernels": 58.0}
+PAPER_STANDARD_CPU_MS = {"populate": 0.1, "raytrace": 2.2, "merge": 0.2}
+
+
+def run_paper_standard(K, warmup, torch, vg, oracle, scenes):
+    """The paper's standard parameters on the synthetic scene (its Gazebo world
+    is not available): 8 seeded frames of random pose cycled through one grid,
+    re-centred each frame, one frame per call; per-stage times from the
+    stages' own launches beside the paper's Table II, and the grid after one
+    cycle against the oracle."""
+    frames = [scenes.make_frame("paper-standard", k) for k in range(8)]
+    f0 = frames[0]
+    seq = Sequence(frames, torch, vg)
+    h = seq.new_grid()
+    plan = recentre_plan(frames, oracle)
+    ref = np.zeros(f0.dims[::-1], np.uint8)
+    for k, f in enumerate(frames):
+        ref, _ = oracle_step(ref, f, *plan[k], oracle)
+        seq.step(h, k)
+    same = bool(np.array_equal(seq.read(h).cpu().numpy(), ref.reshape(-1)))
+
+    # stages timed by their own launches
+    E = vg.PROFILE_EVENTS
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(E * K)]
+    for k in range(warmup):
+        seq.step(h, k)
+    vg.vg_set_profile_events(h, evs)
+    for k in range(K):
+        seq.step(h, k)
+    torch.cuda.synchronize()
+    vg.vg_set_profile_events(h, [])
+    stage_us = {}
+    for j, name in enumerate(vg.PROFILE_STAGES):
+        if name != "shift":
+            stage_us[name] = round(float(np.mean([evs[E * k + 2 * j].elapsed_time(
+                evs[E * k + 2 * j + 1]) for k in range(K)])) * 1e3, 2)
+    # whole steps, no events
+    for k in range(warmup):
+        seq.step(h, k)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for k in range(K):
+        seq.step(h, k)
+    torch.cuda.synchronize()
+    us = (time.perf_counter() - w0) * 1e6 / K
+    seq.drop(h)
+    rays = vg.vg_fan_sizes(seq.sensor, f0.vox_size)[3]
+    ours = {"populate": round(stage_us["seed"] + stage_us["dilate"], 2),
+            "raytrace": stage_us["rays"], "merge": stage_us["resolve"]}
+    return {
+        "workload": "the paper's standard parameters: 320x240 depth, 85x101 deg as printed, "
+                    "0.3-6.5 m, 100x100x20 voxels of 0.15 m (200 000), vox_inf 2, "
+                    f"{rays} rays; synthetic scene (ground + 20 boxes, 2 % invalid pixels) "
+                    "for its Gazebo world; each frame re-centres the grid",
+        "steps": K,
+        "us_per_frame": round(us, 2),
+        "frames_per_s": round(1e6 / us, 1),
+        "stage_us": ours,
+        "stage_us_kernels_sum": round(sum(ours.values()), 2),
+        "paper_rtx2060_us": PAPER_STANDARD_US,
+        "paper_i7_one_core_ms": PAPER_STANDARD_CPU_MS,
+        "note": "stage_us: populate = seed + dilation launches, raytrace = walk launch (it "
+                "also runs the re-centring clear), merge = merge launch; each from the "
+                "start of its first launch to the end of its last",
+        "bit_exact": same,
+    }
+
+
+# ---------------------------------------------------------------------- main
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--steps", type=int, default=300,
+                    help="timed steps (frames) of the headline sequence")
     ap.add_argument("--warmup", type=int, default=30)
-    ap.add_argument("--frames", type=int, default=16, help="size of the seeded frame pool")
+    ap.add_argument("--only", default=",".join(SECTIONS),
+                    help="comma-separated sections to run: " + ", ".join(SECTIONS))
+    ap.add_argument("--seq-frames", type=int, default=300,
+                    help="frames of the large sequences (pinhole headline, spinning)")
+    ap.add_argument("--seq-batch", type=int, default=8, help="frames per sequence batch")
+    ap.add_argument("--frames-cache", default=None,
+                    help="directory holding (or to receive) the rendered large sequences")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="CPU oracle sample length (0 skips the CPU baseline)")
+                    help="single-thread oracle sample length (0 skips it)")
+    ap.add_argument("--stat-frames", type=int, default=16,
+                    help="sampled headline frames run through the oracle on every host thread "
+                         "for voxel-update and walk-step counts (0 skips them)")
+    ap.add_argument("--pool-steps", type=int, default=300,
+                    help="timed steps of the medium and small frame pools")
     ap.add_argument("--batch", type=int, default=64,
-                    help="frames per batch of the batch recipe (0 skips the batched runs)")
+                    help="frames per batch of the batch recipe (0 skips the recipe)")
     ap.add_argument("--batch-steps", type=int, default=10)
-    ap.add_argument("--no-recipe", action="store_true",
-                    help="batched runs: the 16 medium frames only (for a counter run of them)")
     ap.add_argument("--no-tune", action="store_true",
-                    help="batched runs: the default 8x8 ray tile, no tuning runs")
-    ap.add_argument("--serve-robots", type=int, default=16,
-                    help="robots of the served runs (0 skips them)")
-    ap.add_argument("--serve-frames", type=int, default=60, help="frames per robot")
-    ap.add_argument("--large-frames", type=int, default=8,
-                    help="frames per large sequence (0 skips the large runs)")
-    ap.add_argument("--paper-steps", type=int, default=200,
-                    help="steps of the paper's standard parameters (0 skips them)")
+                    help="the default 8x8 ray tile, no tuning runs")
+    ap.add_argument("--serve-robots", type=int, default=16)
+    ap.add_argument("--serve-frames", type=int, default=300, help="frames per robot")
+    ap.add_argument("--paper-steps", type=int, default=200)
     ap.add_argument("--paper-only", action="store_true",
-                    help="run the paper's standard parameters alone (for a kernel trace of "
-                         "that workload) and print their section")
+                    help="the paper's standard parameters alone (--only paper), printing "
+                         "their section")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -552,25 +979,25 @@ def main():
                           "has no multi-GPU mode (independent grids shard by robot)",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    only = set(s.strip() for s in ("paper" if args.paper_only else args.only).split(","))
+    unknown = only - set(SECTIONS)
+    if unknown:
+        print(json.dumps({"error": f"unknown sections {sorted(unknown)}"}))
+        sys.exit(2)
 
-    # batch-recipe frames are rendered in worker processes before the GPU is used
+    # every input is rendered in worker processes before the GPU is touched
     t0 = time.time()
-    recipe = batch_recipe_frames(0 if args.no_recipe else args.batch)
-    if recipe:
-        print(f"# generated {len(recipe)} batch-recipe frames in {time.time() - t0:.1f}s",
-              file=sys.stderr, flush=True)
-
-    t0 = time.time()
-    fleet = served_frames(args.serve_robots, args.serve_frames)
-    if fleet:
-        print(f"# generated {args.serve_robots}x{args.serve_frames} served frames in "
-              f"{time.time() - t0:.1f}s", file=sys.stderr, flush=True)
-
-    t0 = time.time()
-    large = large_frames(args.large_frames)
-    if large:
-        print(f"# generated 2x{args.large_frames} large frames in {time.time() - t0:.1f}s",
-              file=sys.stderr, flush=True)
+    pin = (sequence_frames("large-pinhole", args.seq_frames, args.frames_cache)
+           if "headline" in only else [])
+    spin = (sequence_frames("large-spinning", args.seq_frames, args.frames_cache)
+            if "spinning" in only else [])
+    medium = pool_frames("plain-medium", 16) if ("medium" in only or "batched" in only) else []
+    small = pool_frames("plain-small", 64) if "small" in only else []
+    recipe = batch_recipe_frames(args.batch) if "batched" in only else []
+    fleet = served_frames(args.serve_robots, args.serve_frames) if "served" in only else {}
+    log(f"inputs rendered in {time.time() - t0:.1f}s on {host_workers()} workers: "
+        f"{len(pin)} + {len(spin)} large, {len(medium)} medium, {len(small)} small, "
+        f"{len(recipe)} recipe, {sum(len(v) for v in fleet.values())} served")
 
     import torch
     from paper_2112_13169_amd import autotune, scenes, serve, vg
@@ -579,418 +1006,145 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(2)
     torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
+    import oracle
+
     if args.paper_only:
-        import oracle
         out = run_paper_standard(max(args.paper_steps, 1), 20, torch, vg, oracle, scenes)
         calibration_copy(torch)
         print(json.dumps({"paper_standard": out}))
         return
 
-    # ---- inputs: seeded frame pool, resident on the GPU
-    t0 = time.time()
-    frames = [scenes.make_frame(WORKLOAD, i) for i in range(args.frames)]
-    print(f"# generated {len(frames)} frames in {time.time() - t0:.1f}s", file=sys.stderr,
-          flush=True)
-    fr0 = frames[0]
-    sensor = vg.pinhole_sensor(fr0.intr)
-    vd, hw, hh, rays = vg.vg_fan_sizes(sensor, fr0.vox_size)
-    depth_dev = [torch.from_numpy(f.depth).cuda() for f in frames]
-    poses = [vg.make_pose(f.R, f.t) for f in frames]
-    gx, gy, gz = fr0.dims
-    nvox = gx * gy * gz
-
-    def new_grid():
-        buf = vg.GridBuffers(fr0.dims, fr0.vox_inf)
-        h = vg.vg_create_grid(fr0.dims, fr0.vox_size, fr0.origin, fr0.vox_inf, buf.loc, buf.spare,
-                              buf.scratch)
-        return buf, h
-
-    def step(h, k, origins=None):
-        i = k % len(frames)
-        d = vg.vg_center_offset(h, frames[i].t)
-        vg.vg_integrate_frame_shifted(h, depth_dev[i], sensor, poses[i], d)
-        if origins is not None:
-            origins.append((i, vg.vg_grid_origin(h).tobytes()))
-
-    # ---- parity pass: one cycle of the pool on a fresh grid vs the oracle
-    import oracle
-    buf, h = new_grid()
-    par_origins = []
-    for k in range(len(frames)):
-        step(h, k, par_origins)
-    got = torch.empty(nvox, dtype=torch.uint8, device="cuda")
-    vg.vg_read_grid(h, got)
-    torch.cuda.synchronize()
-    got = got.cpu().numpy()
-    vg.vg_destroy_grid(h)
-    del buf
-
-    ref = np.zeros((gz, gy, gx), np.uint8)
-    base = fr0.origin.astype(np.float32)
-    shift_total = np.zeros(3, np.int32)
-    stats_cache = {}
-    cpu_times = []
-
-    def oracle_step(k, loc, shift_total):
-        i = k % len(frames)
-        f = frames[i]
-        org = oracle.origin(base, shift_total, f.vox_size)
-        d = oracle.center_offset(f.dims, f.vox_size, org, f.t)
-        loc = oracle.shift(loc, d)
-        shift_total = shift_total + np.asarray(d, np.int32)
-        org = oracle.origin(base, shift_total, f.vox_size)
-        _, st = oracle.integrate_pinhole(loc, org, f.vox_size, f.vox_inf, f.depth, f.intr, f.R,
-                                         f.t, want_ms=False)
-        stats_cache.setdefault((i, org.tobytes()), st)
-        return loc, shift_total
-
-    for k in range(len(frames)):
-        c0 = time.perf_counter()
-        ref, shift_total = oracle_step(k, ref, shift_total)
-        cpu_times.append(time.perf_counter() - c0)
-    bit_exact = bool(np.array_equal(got, ref.reshape(-1)))
-    print(f"# parity pass: {len(frames)} frames, bit-exact={bit_exact}", file=sys.stderr,
-          flush=True)
-
-    # ---- CPU baseline: keep stepping the oracle until the sample is long enough
-    k = len(frames)
-    while args.cpu_seconds > 0 and sum(cpu_times) < args.cpu_seconds:
-        c0 = time.perf_counter()
-        ref, shift_total = oracle_step(k, ref, shift_total)
-        cpu_times.append(time.perf_counter() - c0)
-        k += 1
-
-    # ---- CPU baseline, frame-parallel: every host thread steps a grid of its
-    # own through the same frames (independent robots); the oracle stays
-    # single-threaded per frame.  At most 16 threads (one GPU's share of the host).
-    cpu_par = None
-    if args.cpu_seconds > 0:
-        from concurrent.futures import ThreadPoolExecutor
-        threads = max(1, min(16, os.cpu_count() or 1))
-        per = 3
-
-        def robot(j):
-            loc = np.zeros((gz, gy, gx), np.uint8)
-            tot = np.zeros(3, np.int32)
-            for k in range(per):
-                loc, tot = oracle_step(j + k, loc, tot)
-            return per
-
-        w0 = time.perf_counter()
-        with ThreadPoolExecutor(threads) as pool:
-            done = sum(pool.map(robot, range(threads)))
-        wall = time.perf_counter() - w0
-        cpu_par = {"value": round(done / wall, 3), "unit": "frames/s", "cores": threads,
-                   "kind": "oracle",
-                   "sample": f"{threads} threads, each stepping its own grid through {per} frames "
-                             f"(re-centre + integrate) of the same workload, {wall:.1f} s wall",
-                   "host_cpu": cpu_model()}
-
-    # ---- GPU: warmup; a stage pass (every stage timed by events its kernel
-    # dispatches record) picks the dominant kernel; a latency pass (start of the
-    # shift to end of the resolve pass); then the timed region, where only the
-    # dominant kernel's dispatches record events.
-    # ray-bundle shape from the autotuner (one fan class: every frame of the
-    # pool has the same sensor and voxel size), timed on a scratch grid
-    tbuf, th = new_grid()
-    tune_table = autotune.tune(
-        [(sensor, fr0.vox_size, th,
-          lambda: vg.vg_integrate_frame(th, depth_dev[0], sensor, poses[0]))], vg, torch, reps=5)
-    tile = autotune.choose(tune_table, sensor, fr0.vox_size, vg)
-    vg.vg_destroy_grid(th)
-    del tbuf
-    buf, h = new_grid()
-    vg.vg_set_ray_tile(h, tile)
-    for k in range(args.warmup):
-        step(h, k)
-    K = args.steps
-    E = vg.PROFILE_EVENTS
-    names = ["k_" + n for n in vg.PROFILE_STAGES]
-
-    def run(k0, profile, origins=None):
-        vg.vg_set_profile_events(h, profile)
-        torch.cuda.synchronize()
-        w0 = time.perf_counter()
-        for k in range(K):
-            step(h, k0 + k, origins)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - w0
-        vg.vg_set_profile_events(h, [])
-        return wall
-
-    def ev():
-        return torch.cuda.Event(enable_timing=True)
-
-    def pair_ms(evs, j):
-        return np.array([evs[E * k + 2 * j].elapsed_time(evs[E * k + 2 * j + 1])
-                         for k in range(K)])
-
-    # stage pass: every stage timed by its own kernel dispatches
-    st_ev = [ev() for _ in range(E * K)]
-    run(args.warmup, st_ev)
-    stage_ms = {name: pair_ms(st_ev, j) for j, name in enumerate(names)}
-    # the shift launches no kernel of its own (its clear runs inside k_rays):
-    # its pair brackets two markers only
-    kernels = {k: float(v.mean()) for k, v in stage_ms.items() if k != "k_shift"}
-    dominant = max(kernels, key=kernels.get)
-
-    # latency pass: start of the shift .. end of the resolve pass
-    lat_start = [ev() for _ in range(K)]
-    lat_end = [ev() for _ in range(K)]
-    prof = []
-    i_shift, i_resolve = names.index("k_shift"), names.index("k_resolve")
-    for k in range(K):
-        row = [None] * E
-        row[2 * i_shift] = lat_start[k]
-        row[2 * i_resolve + 1] = lat_end[k]
-        prof += row
-    run(args.warmup + K, prof)
-    lat = np.array([lat_start[k].elapsed_time(lat_end[k]) for k in range(K)])
-
-    # with the frame's upload: each step first copies its depth image from
-    # pinned host memory into a device buffer on the same stream (PCIe)
-    host_frames = [torch.from_numpy(f.depth).pin_memory() for f in frames]
-    stage_dev = torch.empty_like(depth_dev[0])
-    buf_h, h_h = new_grid()
-    h2d_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(K)]
-
-    def h2d_step(k):
-        i = k % len(frames)
-        stage_dev.copy_(host_frames[i], non_blocking=True)
-        vg.vg_integrate_frame_shifted(h_h, stage_dev, sensor, poses[i],
-                                      vg.vg_center_offset(h_h, frames[i].t))
-
-    for k in range(args.warmup):
-        h2d_step(k)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    for k, (a, b) in enumerate(h2d_ev):
-        a.record()
-        h2d_step(k)
-        b.record()
-    torch.cuda.synchronize()
-    h2d_wall = time.perf_counter() - w0
-    lat_h2d = np.array([a.elapsed_time(b) for a, b in h2d_ev])
-
-    # the same with the uploads overlapped: a copy stream fills one of two
-    # device buffers while this stream integrates the other; events order each
-    # copy after the frame that last read its buffer, and each frame after its
-    # copy.  Latency: from the copy's start to the frame's end.
-    main_st = torch.cuda.current_stream()
-    copy_st = torch.cuda.Stream()
-    slots = [torch.empty_like(depth_dev[0]) for _ in range(2)]
-    copied = [torch.cuda.Event() for _ in range(2)]
-    freed = [torch.cuda.Event() for _ in range(2)]
-    ovl_ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-              for _ in range(K)]
-    buf_o, h_o = new_grid()
-
-    def ovl_step(k, ev=None):
-        i, j = k % len(frames), k % 2
-        with torch.cuda.stream(copy_st):
-            copy_st.wait_event(freed[j])
-            if ev is not None:
-                ev[0].record(copy_st)
-            slots[j].copy_(host_frames[i], non_blocking=True)
-            copied[j].record(copy_st)
-        main_st.wait_event(copied[j])
-        vg.vg_integrate_frame_shifted(h_o, slots[j], sensor, poses[i],
-                                      vg.vg_center_offset(h_o, frames[i].t))
-        freed[j].record(main_st)
-        if ev is not None:
-            ev[1].record(main_st)
-
-    for k in range(args.warmup):
-        ovl_step(k)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    for k in range(K):
-        ovl_step(k)
-    torch.cuda.synchronize()
-    ovl_wall = time.perf_counter() - w0
-    # both grids have now taken the same frames in the same order
-    g_serial = torch.empty(nvox, dtype=torch.uint8, device="cuda")
-    g_ovl = torch.empty(nvox, dtype=torch.uint8, device="cuda")
-    vg.vg_read_grid(h_h, g_serial)
-    vg.vg_read_grid(h_o, g_ovl)
-    torch.cuda.synchronize()
-    same_ovl = bool(torch.equal(g_serial, g_ovl))
-    # host time to enqueue one step (the loop above is bound by the larger of
-    # this and the device's time per step)
-    w0 = time.perf_counter()
-    for k in range(K):
-        ovl_step(k)
-    ovl_host = time.perf_counter() - w0
-    torch.cuda.synchronize()
-    for k in range(K):
-        ovl_step(k, ovl_ev[k])
-    torch.cuda.synchronize()
-    lat_ovl = np.array([a.elapsed_time(b) for a, b in ovl_ev])
-    vg.vg_destroy_grid(h_h)
-    vg.vg_destroy_grid(h_o)
-    del buf_h, buf_o, slots, g_serial, g_ovl
-
-    # timed region: K steps; the dominant kernel's dispatches record events on
-    # every SAMPLE-th step (a dispatch that records timestamps costs the stream
-    # several microseconds, which would otherwise slow the measured throughput)
-    SAMPLE = 8
-    dom_ev = []
-    j = names.index(dominant)
-    sampled = [k for k in range(K) if k % SAMPLE == 0]
-    for k in range(K):
-        row = [None] * E
-        if k % SAMPLE == 0:
-            row[2 * j], row[2 * j + 1] = ev(), ev()
-        dom_ev += row
-    origins = []
-    wall = run(args.warmup + 2 * K, dom_ev, origins)
-    kernel_live_ms = float(np.mean([dom_ev[E * k + 2 * j].elapsed_time(dom_ev[E * k + 2 * j + 1])
-                                    for k in sampled]))
-    ms_per_step = wall * 1e3 / K
-    fps = 1e3 / ms_per_step
-
-    calibration_copy(torch)
-
-    # ---- per-frame work, from the oracle on the same (frame, grid origin)
-    for i, ob in origins:
-        if (i, ob) not in stats_cache:
-            f = frames[i]
-            tmp = np.zeros((gz, gy, gx), np.uint8)
-            _, st = oracle.integrate_pinhole(tmp, np.frombuffer(ob, np.float32), f.vox_size,
-                                             f.vox_inf, f.depth, f.intr, f.R, f.t, want_ms=False)
-            stats_cache[(i, ob)] = st
-    st_steps = [stats_cache[key] for key in origins]
-    upd = np.array([s["updates"] for s in st_steps], float)
-    walk = np.array([s["steps"] for s in st_steps], float)
-    after = np.array([s["steps_after_hit"] for s in st_steps], float)
-    before = walk - after
-
-    if dominant == "k_rays":
-        units = walk.mean()
-        achieved = units * OPS_PER_STEP / (kernel_live_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 1),
-                "unit": "TOP/s", "frac": round(achieved / ALU_PEAK_TOPS, 4),
-                "traffic": measured_traffic(dominant),
-                "kernel": dominant, "units_per_launch": float(units),
-                "unit_kind": "in-grid walk steps", "ops_per_unit": OPS_PER_STEP,
-                "kernel_ms": round(kernel_live_ms, 5),
-                "launch_also_runs": "the re-centring shift's slab clear (extra workgroups)"}
-    else:
-        # algorithmic HBM bytes of the streaming stages
-        nbytes = {"k_shift": 0.02 * nvox,                  # ring slabs: ~1 % of the grid
-                  "k_seed": 5.0 * fr0.depth.size,           # depth in, stamp out
-                  "k_dilate": nvox / 8.0 * 2 + nvox,        # seeds in, bit planes out
-                  "k_resolve": nvox * (1 + 1 / 8.0) + 2.0 * upd.mean()}[dominant]
-        achieved = nbytes / (kernel_live_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(dominant),
-                "kernel": dominant, "bytes_per_launch": float(nbytes),
-                "kernel_ms": round(kernel_live_ms, 5)}
-
-    cpu = None
-    if cpu_times:
-        n = len(cpu_times)
-        cpu = {"value": round(n / sum(cpu_times), 3), "unit": "frames/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"{n} steps (re-centre + integrate) of the same workload on the CPU "
-                         f"oracle, single thread, {sum(cpu_times):.1f} s",
-               "host_cpu": cpu_model()}
-
-    out = {
-        "metric": METRIC,
-        "value": round(fps, 2),
-        "unit": "frames/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 5),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {
-            "workload": f"{WORKLOAD}: 640x480 f32 depth, 90x60 deg, 0.3-8 m, 200 boxes + 50 "
-                        "spheres, grid 200x200x100 u8 at 0.05 m, vox_inf 2; step = re-centre "
-                        "shift + integrate",
-            "rays": rays, "vox_depth": vd, "fan": f"{2 * hw + 1}x{2 * hh + 1}",
-            "frame_pool": len(frames), "path": "plain (one frame per call)",
-            "ray_tile": f"{1 << tile}x{64 >> tile} (autotuned)",
-        },
-        "voxel_updates_per_s": round(float(upd.mean()) * fps, 1),
-        "voxel_updates_per_frame": round(float(upd.mean()), 1),
-        "walk_steps_per_frame": round(float(walk.mean()), 1),
-        "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 5),
-                       "p99": round(float(np.percentile(lat, 99)), 5),
-                       "mean": round(float(lat.mean()), 5)},
-        "stage_ms": {k: round(v, 5) for k, v in kernels.items()},
-        "bit_exact": bit_exact,
-        "roofline": roof,
-        "cpu_baseline": cpu,
-        "cpu_baseline_parallel": cpu_par,
-        "with_h2d": {"frames_per_s": round(K / h2d_wall, 1),
-                     "latency_ms": {"p50": round(float(np.percentile(lat_h2d, 50)), 5),
-                                    "p99": round(float(np.percentile(lat_h2d, 99)), 5)},
-                     "note": "each step first uploads its 1.2 MB depth image from pinned "
-                             "host memory on the same stream; not the headline value"},
-        "with_h2d_overlapped": {
-            "frames_per_s": round(K / ovl_wall, 1),
-            "latency_ms": {"p50": round(float(np.percentile(lat_ovl, 50)), 5),
-                           "p99": round(float(np.percentile(lat_ovl, 99)), 5)},
-            "host_enqueue_ms_per_step": round(1e3 * ovl_host / K, 5),
-            "bit_exact_vs_serial": same_ovl,
-            "note": "uploads on a second stream into two alternating device buffers, "
-                    "overlapping the previous frame's integration; not the headline value"},
-    }
-    if args.batch > 0:
+    out = {"metric": METRIC}
+    if pin:
+        hl = run_headline(pin, args, torch, vg, autotune)
+        res = hl["res"]
+        t = res["timed"]
+        fps = t["frames_per_s"]
+        stats = hl.get("stats")
+        upd = float(np.mean([s["updates"] for s in stats])) if stats else None
+        steps = [s["steps"] for s in stats] if stats else None
+        roof = None
+        if stats:
+            walk_s = res["walk_ms"][hl["stats_idx"]]
+            roof = walk_roofline(steps, walk_s, "k_rays<false, false, true>",
+                                 measured_traffic("k_rays", TRAFFIC_FILE, WORKLOAD),
+                                 f"walk launch live time (events its own dispatches record) on "
+                                 f"the {len(steps)} sampled frames of a dedicated pass over the "
+                                 f"sequence, against their in-grid walk steps counted by the "
+                                 f"oracle; the launch also runs the re-centring shift's slab "
+                                 f"clear (extra workgroups)")
+            roof["kernel_ms_all_frames"] = round(float(np.mean(res["walk_ms"])), 5)
+        f0 = pin[0]
+        out.update({
+            "value": round(fps, 2),
+            "unit": "frames/s",
+            "n_gpus": 1,
+            "steps": t["steps"],
+            "warmup": t["warmup"],
+            "ms_per_step": round(t["ms_per_step"], 5),
+            "higher_is_better": True,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "f32",
+            "data": "synthetic",
+            "config": {
+                "workload": f"{WORKLOAD} sequence: 1280x720 f32 z-depth, 90x60 deg, 0.3-12 m, "
+                            "2 m/s walk at 30 Hz through a 30x30x8 m world of 1500 boxes + 500 "
+                            "spheres; grid 400x400x200 u8 (32 M voxels) at 0.025 m, vox_inf 3; "
+                            "step = re-centre shift + integrate one frame (one call)",
+                "sequence_frames": hl["n"], "rays": hl["rays"], "vox_depth": hl["vd"],
+                "fan": f"{2 * hl['hw'] + 1}x{2 * hl['hh'] + 1}",
+                "path": "plain (one frame per call); batched in 'batched'",
+                "ray_tile": f"{1 << hl['tile']}x{64 >> hl['tile']}"
+                            + (" (autotuned)" if not args.no_tune else ""),
+                "stats_sample": (f"voxel updates and walk steps: oracle on {len(steps)} frames "
+                                 f"spread over the sequence" if stats else None),
+            },
+            "voxel_updates_per_s": round(upd * fps, 1) if upd else None,
+            "voxel_updates_per_frame": round(upd, 1) if upd else None,
+            "walk_steps_per_frame": round(float(np.mean(steps)), 1) if steps else None,
+            "latency_ms": res["latency_ms"],
+            "stage_ms": res["stage_ms"],
+            "walk_ms": pct(res["walk_ms"]),
+            "plain_sequence": res["plain_sequence"],
+            "batched": res.get("batched"),
+            "bit_exact": hl.get("bit_exact"),
+            "oracle_frames": hl.get("oracle_frames"),
+            "roofline": roof,
+            "cpu_baseline": hl.get("cpu_baseline"),
+            "cpu_baseline_parallel": hl.get("cpu_baseline_parallel"),
+            "with_h2d": hl["with_h2d"],
+        })
+        del hl, res
+        torch.cuda.empty_cache()
+    extra = {}
+    if spin:
         t0 = time.time()
-        x16 = frames[:16]
+        seq = Sequence(spin, torch, vg)
+        res, _ = run_sequence(seq, 0, 0, args.seq_batch, torch, vg, timed=False)
+        extra["large-spinning"] = {
+            "workload": "128x2048 spinning range images (vfov 45 deg, 0.3-12 m) of a 2 m/s walk "
+                        "through the same world, into the same 400x400x200 grid at 0.025 m, "
+                        "vox_inf 3, re-centred before every frame",
+            "rays": vg.vg_fan_sizes(seq.sensor, seq.f0.vox_size)[3],
+            "plain_sequence": res["plain_sequence"], "latency_ms": res["latency_ms"],
+            "stage_ms": res["stage_ms"], "walk_ms": pct(res["walk_ms"]),
+            "batched": res["batched"]}
+        del seq
+        torch.cuda.empty_cache()
+        log(f"spinning sequence in {time.time() - t0:.1f}s")
+    if medium and "medium" in only:
+        t0 = time.time()
+        extra["plain-medium"] = run_pool("640x480 f32, 90x60 deg, 0.3-8 m, 200 boxes + 50 "
+                                         "spheres, grid 200x200x100 at 0.05 m, vox_inf 2",
+                                         medium, args.pool_steps, 30, torch, vg, oracle)
+        extra["plain-medium"]["roofline_traffic_k_rays"] = measured_traffic(
+            "k_rays", TRAFFIC_FILE_MEDIUM, "plain-medium")
+        log(f"medium pool in {time.time() - t0:.1f}s")
+    if small:
+        t0 = time.time()
+        extra["plain-small"] = run_pool("160x120 f32, 90x60 deg, 0.3-5 m, 20 boxes, grid "
+                                        "100x100x50 at 0.1 m, vox_inf 1", small,
+                                        max(args.pool_steps, 1000), 30, torch, vg, oracle)
+        log(f"small pool in {time.time() - t0:.1f}s")
+    if "batched" in only and medium:
+        t0 = time.time()
         walk16 = []
-        for f in x16:       # in-grid walk steps do not depend on the grid's content
+        for f in medium[:16]:   # in-grid walk steps do not depend on the grid's content
             _, st = oracle.integrate_pinhole(np.zeros(f.dims[::-1], np.uint8), f.origin,
                                              f.vox_size, f.vox_inf, f.depth, f.intr, f.R, f.t,
                                              want_ms=False)
             walk16.append(st["steps"])
-        out["batched"] = {
-            "plain-medium x16": dict(
-                workload="16 plain-medium frames per step, each into its own 200x200x100 grid",
-                **run_batched(x16, args.batch_steps * 4, 3, torch, vg, oracle, autotune,
-                              walk_steps=walk16, tune=not args.no_tune)),
-        }
+        extra["batched"] = {"plain-medium x16": dict(
+            workload="16 plain-medium frames per step, each into its own 200x200x100 grid",
+            **run_batched(medium[:16], args.batch_steps * 4, 3, torch, vg, oracle, autotune,
+                          walk_steps=walk16, tune=not args.no_tune))}
         if recipe:
-            out["batched"]["batch-recipe"] = dict(
+            extra["batched"]["batch-recipe"] = dict(
                 workload=f"{len(recipe)} independent frames per step: 320x240..1280x720, range "
                          "to U[4,10] m, random 6-DoF poses, own grids of gx=gy in 100..256, gz "
                          "in 100..128 at 0.05-0.1 m, vox_inf 1-3",
                 **run_batched(recipe, args.batch_steps, 2, torch, vg, oracle, autotune,
-                              sample_oracle=(0, len(recipe) - 1), tune=not args.no_tune))
-        print(f"# batched runs in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+                              sample_oracle=(0, len(recipe) - 1), tune=not args.no_tune,
+                              graph=True))
+        torch.cuda.empty_cache()
+        log(f"batched runs in {time.time() - t0:.1f}s")
     if fleet:
         t0 = time.time()
-        out["served"] = dict(
+        extra["served"] = dict(
             workload=f"{args.serve_robots} robots x {args.serve_frames} frames (2 m/s walks at "
                      "30 Hz through a 40x40x10 m world of 800 boxes + 200 spheres), 640x480 "
                      "frames as the medium workload, each robot's 200x200x100 grid at 0.05 m "
                      "re-centred every frame; Poisson arrivals at 30 Hz per robot",
             **run_served(fleet, torch, vg, serve))
-        print(f"# served runs in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
-    if large:
+        log(f"served runs in {time.time() - t0:.1f}s")
+    if "paper" in only and args.paper_steps > 0:
         t0 = time.time()
-        out["large"] = dict(
-            workload=f"{args.large_frames} consecutive frames of a 2 m/s walk through a 30x30x8 m "
-                     "world of 1500 boxes + 500 spheres: 1280x720 pinhole (0.3-12 m) and 128x2048 "
-                     "spinning (vfov 45 deg, 0.3-12 m); 400x400x200 grid at 0.025 m, vox_inf 3, "
-                     "re-centred before every frame",
-            **run_large(large, torch, vg))
-        print(f"# large runs in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
-    if args.paper_steps > 0:
-        t0 = time.time()
-        import oracle
-        out["paper_standard"] = run_paper_standard(args.paper_steps, 20, torch, vg, oracle, scenes)
-        print(f"# paper-standard runs in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+        extra["paper_standard"] = run_paper_standard(args.paper_steps, 20, torch, vg, oracle,
+                                                     scenes)
+        log(f"paper-standard runs in {time.time() - t0:.1f}s")
+    calibration_copy(torch)
+    out.update(extra)
     print(json.dumps(out))
 
 

@@ -20,7 +20,10 @@
  *    are independent.
  *  - Errors: argument errors are detected before any device work is enqueued,
  *    return VG_ERR_ARG and leave the grid unchanged.  HIP launch / copy errors
- *    return VG_ERR_HIP.  Nothing throws across the ABI.
+ *    return VG_ERR_HIP; the grid's content is then undefined (launches of
+ *    the failed call may have run), and its next frame first clears the
+ *    per-frame planes, so no stamp of the failed call is taken for its own.
+ *    Nothing throws across the ABI.
  *  - Layout: vg_read_grid / vg_write_grid exchange grids as
  *    uint8[grid_size_z][grid_size_y][grid_size_x] with the paper's linear index
  *    idx = x + y*grid_size_x + z*grid_size_x*grid_size_y (Sec. IV-D); grid
@@ -172,8 +175,10 @@ vg_status vg_integrate_points(vg_grid *g, const float *points, int64_t n_points,
  * |dz|*gx*gy voxels at most).  Enqueued on `stream`; (0,0,0) does nothing. */
 vg_status vg_shift_grid(vg_grid *g, int32_t dx, int32_t dy, int32_t dz, void *stream);
 
-/* Offset that re-centres the grid on a camera at t_w_c (metres):
- * delta = floor((t_w_c - origin_w) / vox_size) - grid_size / 2.  Host-only. */
+/* Offset that re-centres the grid on a camera at t_w_c (metres), the shift
+ * of Sec. IV-E that keeps the robot at the centre of its local grid:
+ * delta = floor((t_w_c - origin_w) / vox_size) - grid_size / 2 (fp32 as
+ * written, integer halving).  Host-only. */
 vg_status vg_center_offset(const vg_grid *g, const float t_w_c[3], int32_t delta_out[3]);
 
 /* vg_center_offset as it will be once shifts totalling pending[3] voxels
@@ -182,16 +187,24 @@ vg_status vg_center_offset(const vg_grid *g, const float t_w_c[3], int32_t delta
 vg_status vg_center_offset_after(const vg_grid *g, const int32_t pending[3], const float t_w_c[3],
                                  int32_t delta_out[3]);
 
-/* Current grid origin in the world frame (host-only). */
+/* Current grid origin in the world frame: the corner of voxel (0,0,0), the
+ * translation of T^v_w (Table I; Sec. IV-A), moved by vox_size per voxel of
+ * accumulated shift (Sec. IV-E): origin = origin_w + (float)shift * vox_size
+ * per axis, in fp32.  Host-only. */
 vg_status vg_grid_origin(const vg_grid *g, float origin_w_out[3]);
 
-/* Copy the local grid (linear layout) to dst: device memory if dst_is_device,
- * else host memory; enqueued on `stream` -- synchronise the stream before
- * reading a host destination. */
+/* Copy the local grid (Sec. IV-A: occupied / free / unknown voxels) to dst
+ * in the linear layout of Sec. IV-D (idx = x + y*gx + z*gx*gy, whatever the
+ * ring offsets of the device buffer): dst holds gx*gy*gz bytes, device
+ * memory if dst_is_device, else host memory.  Enqueued on `stream` --
+ * synchronise the stream before reading a host destination. */
 vg_status vg_read_grid(const vg_grid *g, uint8_t *dst, int32_t dst_is_device, void *stream);
 
-/* Overwrite the local grid (restore a checkpoint) from src (linear layout);
- * the ring offsets restart at 0. */
+/* Overwrite the local grid from src (gx*gy*gz bytes, the linear layout of
+ * vg_read_grid; device memory if src_is_device, else host memory), e.g. to
+ * restore a checkpoint; the ring offsets restart at 0.  Not a step of the
+ * paper: it lets a server release an idle grid's device memory and resume
+ * it later (see vg_rebind_grid). */
 vg_status vg_write_grid(vg_grid *g, const uint8_t *src, int32_t src_is_device, void *stream);
 
 /* One frame of a batch. */
@@ -228,8 +241,15 @@ size_t vg_batch_workspace_bytes(int32_t max_frames);
  *     same stream at once.
  * Every frame is checked before anything is enqueued (VG_ERR_ARG: no grid
  * changes).  The call enqueues kernels only, so it can be captured into a
- * HIP graph; a replay repeats the captured frames with their captured poses
- * and stamps (the image buffers are read at replay time). */
+ * HIP graph.  A replay repeats the captured call exactly: the same poses,
+ * shifts, per-frame stamps and ring offsets, taken from the kernel
+ * arguments, with the image buffers read at replay time.  The host state of
+ * the grids (origin, ring offsets, stamp) advances once, at capture.  So a
+ * replay gives the eager call's result only when it repeats that call's
+ * inputs -- the same image contents, and no call on its grids in between
+ * (the marks a replay leaves then carry the stamps the replay itself
+ * writes); a replay after new image contents, or after other calls on the
+ * grids, is not a valid integration. */
 vg_status vg_integrate_batch(const vg_frame *frames, int32_t n_frames, void *workspace,
                              size_t workspace_bytes, void *stream);
 

@@ -557,19 +557,6 @@ hipError_t prepare_frame(const vg_grid *g, const FramePlan &p, hipStream_t st)
     return e;
 }
 
-// Batch frame tables: per round, kBatchStages block prefixes of m + 1
-// entries (16-byte aligned), then m frame descriptors.
-constexpr int32_t kMaxBatch = 4096;
-
-size_t batch_starts_bytes(int32_t m)
-{
-    return ((size_t)kBatchStages * (m + 1) * sizeof(int32_t) + 15) / 16 * 16;
-}
-
-size_t batch_table_bytes(int32_t m)
-{
-    return (batch_starts_bytes(m) + (size_t)m * sizeof(FrameDesc) + 15) / 16 * 16;
-}
 
 // Blocks of 256 lanes each batch stage launches for a planned frame.
 void batch_blocks(const vg_grid *g, const FramePlan &p, bool moved, int tile_w,
@@ -652,8 +639,13 @@ vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_float
         e = launch_resolve(p.sp.pl, g->loc, p.rows, p.ring, st, stage(kStageResolve));
     if (ev)
         ++g->prof_next;
-    if (e != hipSuccess)
+    if (e != hipSuccess) {
+        // launches already enqueued may have written this frame's stamp: the
+        // next frame must not take it again, so it starts by clearing the
+        // planes (the stamp wraps)
+        g->epoch = 255;
         return VG_ERR_HIP;
+    }
     advance(gs, p, sensor);
     store_state(g, gs);
     return VG_OK;
@@ -932,8 +924,7 @@ size_t vg_batch_workspace_bytes(int32_t max_frames)
 {
     if (max_frames < 0 || max_frames > kMaxBatch)
         return 0;
-    // a round of m frames needs at most m times a one-frame round
-    return align_up((size_t)max_frames * batch_table_bytes(1) + kAlign);
+    return batch_workspace_bytes(max_frames);
 }
 
 vg_status vg_integrate_batch(const vg_frame *frames, int32_t n_frames, void *workspace,
@@ -1139,8 +1130,12 @@ vg_status vg_integrate_batch_timed(const vg_frame *frames, int32_t n_frames, voi
                                    yz ? round_tile[(size_t)r] : 0, yz ? round_lds[(size_t)r] : 0);
         }
     }
-    if (e != hipSuccess)
+    if (e != hipSuccess) {
+        // as for one frame: stamps of this batch may already be in the planes
+        for (vg_grid *g : grids)
+            g->epoch = 255;
         return VG_ERR_HIP;
+    }
     for (size_t k = 0; k < grids.size(); ++k)
         store_state(grids[k], states[k]);
     return VG_OK;

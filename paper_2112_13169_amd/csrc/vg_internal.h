@@ -161,6 +161,27 @@ inline int64_t dilate_tiles(const Planes &pl, int kw)
 enum { kBatchShift, kBatchSeed, kBatchDilateX, kBatchDilateYZ, kBatchRays, kBatchResolve,
        kBatchStages };
 
+// Batch frame tables: per round, kBatchStages block prefixes of m + 1
+// entries (16-byte aligned), then m frame descriptors.
+constexpr int32_t kMaxBatch = 4096;
+
+constexpr size_t batch_starts_bytes(int32_t m)
+{
+    return ((size_t)kBatchStages * (m + 1) * sizeof(int32_t) + 15) / 16 * 16;
+}
+
+constexpr size_t batch_table_bytes(int32_t m)
+{
+    return (batch_starts_bytes(m) + (size_t)m * sizeof(FrameDesc) + 15) / 16 * 16;
+}
+
+// Workspace of a batch of up to m frames: a round of k frames needs at most
+// k times a one-frame round (256-byte aligned, plus slack).
+constexpr size_t batch_workspace_bytes(int32_t m)
+{
+    return ((size_t)m * batch_table_bytes(1) + 256 + 255) / 256 * 256;
+}
+
 // Bytes to copy into device memory, carried as a kernel argument (so that a
 // batch needs no host staging buffer that must outlive the call).
 constexpr int kUploadWords = 1016;

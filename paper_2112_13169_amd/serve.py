@@ -79,10 +79,15 @@ class Server:
         self.busy = [None] * self.n_streams       # (event, requests) in flight per stream
         self.ws_bytes = self.b.workspace_bytes(self.max_batch)
         self.budget = int(budget_bytes)
-        self.used = self.n_streams * self.ws_bytes
+        # memory the backend holds whatever is admitted (e.g. per-stream frame
+        # slots), and what each admitted frame adds on top of it
+        fixed = getattr(self.b, "fixed_bytes", lambda: 0)()
+        self.frame_reserve = getattr(self.b, "frame_reserve_bytes", lambda n: n)(self.frame_bytes)
+        self.used = self.n_streams * self.ws_bytes + int(fixed)
         self.grid_bytes = {r.rid: self.b.grid_bytes(r.dims, r.vox_inf) for r in robots}
-        if self.used + max(self.grid_bytes.values()) + self.frame_bytes > self.budget:
-            raise ValueError("budget below one grid, one frame and the batch workspaces")
+        if self.used + max(self.grid_bytes.values()) + self.frame_reserve > self.budget:
+            raise ValueError("budget below one grid, one frame, the batch workspaces and the "
+                             "backend's fixed memory")
         self.queue = collections.deque()           # arrived, not admitted (arrival order)
         self.done = []
         self.tick_no = 0
@@ -141,7 +146,7 @@ class Server:
                 q.done = now
                 r = self.robots[q.robot]
                 r.inflight -= 1
-                self._release(self.frame_bytes)
+                self._release(self.frame_reserve)
                 self.b.finish_frame(q)
                 self.done.append(q)
                 n += 1
@@ -174,7 +179,7 @@ class Server:
                   and q.robot not in in_batch)
             if ok and r.buffers is None:
                 ok = self._make_resident(r, protected)
-            if ok and not self._reserve(self.frame_bytes):
+            if ok and not self._reserve(self.frame_reserve):
                 ok = False
             if not ok:
                 skipped_robots.add(q.robot)      # keep this robot's later frames behind it
@@ -290,6 +295,17 @@ class GpuBackend:
 
     def grid_bytes(self, dims, vox_inf):
         return self.vg.vg_grid_bytes(*dims) + self.vg.vg_scratch_bytes(*dims, vox_inf)
+
+    def fixed_bytes(self):
+        """Device memory held whatever is admitted: the per-stream frame slots."""
+        if self.slots is None:
+            return 0
+        return sum(t.numel() * t.element_size() for t in self.slots)
+
+    def frame_reserve_bytes(self, frame_bytes):
+        """Device memory an admitted frame adds: none with slots (they are
+        charged once, in fixed_bytes), else its own device copy."""
+        return 0 if self.slots is not None else frame_bytes
 
     def _event(self):
         ev = self.torch.cuda.Event()

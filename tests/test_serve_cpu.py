@@ -193,3 +193,39 @@ def test_admission_stops_scanning_once_no_frame_can_join():
     assert len(rest) == 4 * 199
     for rid in range(4):
         assert [q.index for q in rest if q.robot == rid] == list(range(1, 200))
+
+
+class SlotBackend(FakeBackend):
+    """A backend that holds per-stream frame slots: fixed memory charged once,
+    nothing per admitted frame."""
+
+    def __init__(self, rng, slot_bytes):
+        super().__init__(rng)
+        self.slot_bytes = slot_bytes
+
+    def fixed_bytes(self):
+        return self.slot_bytes
+
+    def frame_reserve_bytes(self, frame_bytes):
+        return 0
+
+
+def test_backend_fixed_memory_counts_against_the_budget():
+    """Fixed device memory of the backend (frame slots) is charged at start-up
+    and per-frame reservations follow the backend: the budget covers what is
+    really resident, and a budget without room for the slots is refused."""
+    rng = np.random.default_rng(5)
+    be = SlotBackend(rng, slot_bytes=700)
+    streams, frame_bytes = 2, 10
+    budget = streams * be._ws + 700 + 3 * be._grid
+    srv = serve.Server(be, _robots(6), frame_bytes, budget, max_batch=4, streams=streams)
+    assert srv.used == streams * be._ws + 700
+    done = srv.run(serve.poisson_arrivals(6, 12, 30.0, rng), clock=FakeClock(2e-4),
+                   speed=float("inf"), spin=0, sleep=lambda s: None)
+    assert len(done) == 6 * 12 and srv.stats.peak_bytes <= budget
+    assert srv.stats.evictions > 0
+    assert srv.used == streams * be._ws + 700 + sum(
+        be._grid for r in srv.robots.values() if r.buffers is not None)
+    with pytest.raises(ValueError):
+        serve.Server(SlotBackend(rng, slot_bytes=5000), _robots(2), frame_bytes, budget,
+                     max_batch=4, streams=streams)
