@@ -262,6 +262,23 @@ vg_status vg_integrate_batch(const vg_frame *frames, int32_t n_frames, void *wor
 vg_status vg_integrate_batch_timed(const vg_frame *frames, int32_t n_frames, void *workspace,
                                    size_t workspace_bytes, void *const *events, void *stream);
 
+/* Most frames one vg_integrate_batch_static call takes. */
+#define VG_STATIC_BATCH_MAX_FRAMES 256
+
+/* vg_integrate_batch for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no workspace argument -- the frame tables go to a device array
+ * the library holds, one per GPU (143 616 bytes, VG_STATIC_BATCH_MAX_FRAMES
+ * frames' worth, held until the process ends).  The call allocates no device
+ * memory.  n_frames > VG_STATIC_BATCH_MAX_FRAMES returns VG_ERR_BUDGET and
+ * enqueues nothing.  Every call on one GPU shares that GPU's array, and each
+ * call overwrites it before reading it: calls enqueued one after another on
+ * one stream are safe, while calls whose work can overlap on one GPU (other
+ * streams, or other host threads' calls not ordered with this one) race and
+ * give undefined grids.  Everything else -- results, errors, HIP-graph
+ * capture and its replays -- is as for vg_integrate_batch. */
+vg_status vg_integrate_batch_static(const vg_frame *frames, int32_t n_frames, void *stream);
+
 /* Shape of the ray bundle one wavefront walks: tiles of (1 << log2_width)
  * fan targets along the fan's width (pinhole columns, or ring columns of a
  * spinning fan) by (64 >> log2_width) along its height; log2_width in

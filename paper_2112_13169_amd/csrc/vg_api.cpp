@@ -1141,6 +1141,20 @@ vg_status vg_integrate_batch_timed(const vg_frame *frames, int32_t n_frames, voi
     return VG_OK;
 }
 
+vg_status vg_integrate_batch_static(const vg_frame *frames, int32_t n_frames, void *stream)
+{
+    if (n_frames > kStaticBatchFrames)
+        return VG_ERR_BUDGET;
+    if (n_frames < 0 || (n_frames > 0 && !frames))
+        return VG_ERR_ARG;
+    if (n_frames == 0)
+        return VG_OK;
+    void *ws = nullptr;
+    if (static_batch_workspace(&ws) != hipSuccess)
+        return VG_ERR_HIP;
+    return vg_integrate_batch_timed(frames, n_frames, ws, kStaticBatchBytes, nullptr, stream);
+}
+
 vg_status vg_destroy_grid(vg_grid *g)
 {
     if (!g)

@@ -182,6 +182,12 @@ constexpr size_t batch_workspace_bytes(int32_t m)
     return ((size_t)m * batch_table_bytes(1) + 256 + 255) / 256 * 256;
 }
 
+// Frames per call of the batch entry point whose frame tables live in a
+// device array of the library (for callers that cannot allocate), and that
+// array's size.
+constexpr int32_t kStaticBatchFrames = 256;
+constexpr size_t kStaticBatchBytes = batch_workspace_bytes(kStaticBatchFrames);
+
 // Bytes to copy into device memory, carried as a kernel argument (so that a
 // batch needs no host staging buffer that must outlive the call).
 constexpr int kUploadWords = 1016;
@@ -216,6 +222,9 @@ hipError_t launch_clear(const SlabClear &c, hipStream_t st, const StageEvents &e
 // Records the events of a stage that launches no kernel.
 hipError_t record_empty_stage(const StageEvents &ev, hipStream_t st);
 
+// The library's own batch workspace on the current device (kStaticBatchBytes,
+// 256-byte aligned): its device address, looked up once per device.
+hipError_t static_batch_workspace(void **ptr);
 // Batch: copy host words to device memory through kernel arguments.
 hipError_t launch_upload(uint32_t *dst, const uint32_t *src, size_t words, hipStream_t st);
 // Batch: one launch of stage `stage` (kBatch*) over the n frames of a round;

@@ -32,8 +32,15 @@
 #include <hip/hip_ext.h>
 
 #include <algorithm>
+#include <mutex>
 
 #pragma clang fp contract(off)
+
+// Frame tables of vg_integrate_batch_static: one copy per GPU, held until the
+// process ends.  Host code never passes this name to a kernel (on the host it
+// is only a stand-in for the symbol); it uses the device address that
+// static_batch_workspace() looks up per device.
+static __device__ __align__(256) uint8_t scratch[vg::kStaticBatchBytes];
 
 namespace vg {
 
@@ -810,6 +817,31 @@ hipError_t launch_clear(const SlabClear &c, hipStream_t st, const StageEvents &e
     hipExtLaunchKernelGGL(k_clear, dim3(blocks_for(lanes)), dim3(kBlock), 0, st, ev.start,
                           ev.stop, 0, c);
     return hipGetLastError();
+}
+
+hipError_t static_batch_workspace(void **ptr)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        if (!p || ((uintptr_t)p % 256) != 0)
+            return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_upload(uint32_t *dst, const uint32_t *src, size_t words, hipStream_t st)

@@ -87,6 +87,7 @@ def lib():
         L.vg_integrate_batch.argtypes = [ctypes.POINTER(vg_frame), i32, P, ctypes.c_size_t, P]
         L.vg_integrate_batch_timed.argtypes = [ctypes.POINTER(vg_frame), i32, P, ctypes.c_size_t,
                                                P, P]
+        L.vg_integrate_batch_static.argtypes = [ctypes.POINTER(vg_frame), i32, P]
         L.vg_set_ray_tile.argtypes = [P, i32]
         L.vg_rebind_grid.argtypes = [P, P, P, ctypes.c_size_t, P, ctypes.c_size_t, P]
         L.vg_status_str.argtypes = [i32]
@@ -96,7 +97,8 @@ def lib():
                      "vg_integrate_points", "vg_shift_grid", "vg_center_offset",
                      "vg_grid_origin", "vg_read_grid", "vg_write_grid", "vg_destroy_grid",
                      "vg_set_profile_events", "vg_integrate_batch", "vg_set_ray_tile",
-                     "vg_rebind_grid", "vg_center_offset_after", "vg_integrate_batch_timed"):
+                     "vg_rebind_grid", "vg_center_offset_after", "vg_integrate_batch_timed",
+                     "vg_integrate_batch_static"):
             getattr(L, name).restype = i32
         _lib = L
     return _lib
@@ -331,6 +333,18 @@ def vg_integrate_batch(frames, workspace, stream=None):
     _check(lib().vg_integrate_batch(arr, n, _ptr(workspace),
                                     workspace.numel() * workspace.element_size(),
                                     _stream(stream)), "vg_integrate_batch")
+
+
+VG_STATIC_BATCH_MAX_FRAMES = 256
+
+
+def vg_integrate_batch_static(frames, stream=None):
+    """vg_integrate_batch with the library's own device tables (no workspace
+    argument, nothing allocated): at most VG_STATIC_BATCH_MAX_FRAMES frames."""
+    n = len(frames)
+    arr = (vg_frame * max(n, 1))(*frames)
+    _check(lib().vg_integrate_batch_static(arr, n, _stream(stream)),
+           "vg_integrate_batch_static")
 
 
 BATCH_STAGES = ("shift", "seed", "dilate_x", "dilate_yz", "rays", "resolve")
