@@ -186,11 +186,15 @@ def load_frames(path):
     from paper_2112_13169_amd import scenes
     with open(path + ".json") as fh:
         meta = json.load(fh)
-    a = np.load(path + ".npz")
-    col, row = (a["col_tab"], a["row_tab"]) if meta["kind"] == "spinning" else (None, None)
-    return [scenes.Frame(depth=a["depth"][k], R=a["R"][k], t=a["t"][k], intr=meta["intr"],
+    # each array read once (indexing the archive itself would decompress the
+    # whole array again for every frame)
+    with np.load(path + ".npz") as a:
+        arr = {k: a[k] for k in a.files}
+    col, row = ((arr["col_tab"], arr["row_tab"]) if meta["kind"] == "spinning"
+                else (None, None))
+    return [scenes.Frame(depth=arr["depth"][k], R=arr["R"][k], t=arr["t"][k], intr=meta["intr"],
                          dims=tuple(meta["dims"]), vox_size=meta["vox_size"],
-                         vox_inf=meta["vox_inf"], origin=a["origin"][k], kind=meta["kind"],
+                         vox_inf=meta["vox_inf"], origin=arr["origin"][k], kind=meta["kind"],
                          col_tab=col, row_tab=row) for k in range(meta["n"])]
 
 
@@ -276,9 +280,11 @@ class Sequence:
         self.tile = 3
         self.keep = []
 
-    def new_grid(self):
+    def new_grid(self, sets=1):
+        """A fresh grid; sets > 1: its scratch holds that many plane sets, so
+        a batch runs up to `sets` consecutive frames together."""
         vg = self.vg
-        b = vg.GridBuffers(self.f0.dims, self.f0.vox_inf)
+        b = vg.GridBuffers(self.f0.dims, self.f0.vox_inf, sets=sets)
         h = vg.vg_create_grid(self.f0.dims, self.f0.vox_size, self.f0.origin, self.f0.vox_inf,
                               b.loc, b.spare, b.scratch)
         vg.vg_set_ray_tile(h, self.tile)
@@ -409,12 +415,12 @@ def run_sequence(seq, K, W, B, torch, vg, timed=True, pass_steps=None):
     # with an event pair around every batch (latency)
     if B > 0:
         ws = torch.empty(vg.vg_batch_workspace_bytes(B), dtype=torch.uint8, device="cuda")
-        h = seq.new_grid()
+        h = seq.new_grid(sets=B)
         for i0 in range(0, n, B):
             seq.batch(h, i0, B, ws)
         torch.cuda.synchronize()
         seq.drop(h)
-        h = seq.new_grid()
+        h = seq.new_grid(sets=B)
         torch.cuda.synchronize()
         w0 = time.perf_counter()
         for i0 in range(0, n, B):
@@ -423,7 +429,7 @@ def run_sequence(seq, K, W, B, torch, vg, timed=True, pass_steps=None):
         batch_wall = time.perf_counter() - w0
         same = bool(torch.equal(seq.read(h), plain_grid))
         seq.drop(h)
-        h = seq.new_grid()
+        h = seq.new_grid(sets=B)
         pairs = []
         for i0 in range(0, n, B):
             a, b = ev(), ev()
@@ -441,8 +447,11 @@ def run_sequence(seq, K, W, B, torch, vg, timed=True, pass_steps=None):
             "speedup_vs_plain": round(plain_wall / batch_wall, 4),
             "batch_latency_ms": pct([a.elapsed_time(b) for a, b in pairs]),
             "bit_exact_vs_plain": same,
+            "plane_sets": B,
             "note": "the whole sequence as consecutive batches of frames_per_batch frames, "
-                    "each frame re-centring the grid (vg_integrate_batch); a frame's latency "
+                    "each frame re-centring the grid (vg_integrate_batch) on a grid with "
+                    "plane_sets plane sets, so each batch is one round: steps 2-3 of its "
+                    "frames in one launch per stage and one merge; a frame's latency "
                     "in a batch is its batch's latency; plain_frames_per_s_same_pass is the "
                     "one-frame-per-call path over the same frames, wall clock"}
     res["plain_sequence"] = {"frames": n, "frames_per_s": round(n / plain_wall, 1),
@@ -535,7 +544,9 @@ def run_headline(frames, args, torch, vg, autotune):
     f0 = seq.f0
     vd, hw, hh, rays = vg.vg_fan_sizes(seq.sensor, f0.vox_size)
     # ray-bundle shape from the autotuner (one fan class), on a scratch grid
-    if not args.no_tune:
+    if args.ray_tile is not None:
+        seq.tile = int(args.ray_tile)
+    elif not args.no_tune:
         th = seq.new_grid()
         table = autotune.tune([(seq.sensor, f0.vox_size, th,
                                 lambda: vg.vg_integrate_frame(th, seq.dev[0], seq.sensor,
@@ -966,6 +977,9 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--no-tune", action="store_true",
                     help="the default 8x8 ray tile, no tuning runs")
+    ap.add_argument("--ray-tile", type=int, default=None,
+                    help="headline ray tile as log2 of its width (0..6), no tuning runs "
+                         "(a profiled run then holds only the headline's own walk launches)")
     ap.add_argument("--serve-robots", type=int, default=16)
     ap.add_argument("--serve-frames", type=int, default=300, help="frames per robot")
     ap.add_argument("--paper-steps", type=int, default=200)
@@ -1054,9 +1068,11 @@ def main():
                             "step = re-centre shift + integrate one frame (one call)",
                 "sequence_frames": hl["n"], "rays": hl["rays"], "vox_depth": hl["vd"],
                 "fan": f"{2 * hl['hw'] + 1}x{2 * hl['hh'] + 1}",
-                "path": "plain (one frame per call); batched in 'batched'",
+                "path": "plain (one frame per call); 8-frame sequence batches in "
+                    "'sequence_batched'",
                 "ray_tile": f"{1 << hl['tile']}x{64 >> hl['tile']}"
-                            + (" (autotuned)" if not args.no_tune else ""),
+                            + (" (autotuned)" if not args.no_tune and args.ray_tile is None
+                               else ""),
                 "stats_sample": (f"voxel updates and walk steps: oracle on {len(steps)} frames "
                                  f"spread over the sequence" if stats else None),
             },
@@ -1067,7 +1083,7 @@ def main():
             "stage_ms": res["stage_ms"],
             "walk_ms": pct(res["walk_ms"]),
             "plain_sequence": res["plain_sequence"],
-            "batched": res.get("batched"),
+            "sequence_batched": res.get("batched"),
             "bit_exact": hl.get("bit_exact"),
             "oracle_frames": hl.get("oracle_frames"),
             "roofline": roof,
@@ -1089,7 +1105,7 @@ def main():
             "rays": vg.vg_fan_sizes(seq.sensor, seq.f0.vox_size)[3],
             "plain_sequence": res["plain_sequence"], "latency_ms": res["latency_ms"],
             "stage_ms": res["stage_ms"], "walk_ms": pct(res["walk_ms"]),
-            "batched": res["batched"]}
+            "sequence_batched": res["batched"]}
         del seq
         torch.cuda.empty_cache()
         log(f"spinning sequence in {time.time() - t0:.1f}s")

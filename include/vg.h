@@ -102,9 +102,16 @@ vg_status vg_fan_sizes(const vg_sensor *sensor, float vox_size, int64_t out[4]);
 size_t vg_grid_bytes(int32_t grid_size_x, int32_t grid_size_y, int32_t grid_size_z);
 
 /* Bytes of device scratch workspace a grid of this size and vox_inf needs
- * (per-frame stamp and bit planes).  Host-only; 0 for invalid sizes. */
+ * for one set of per-frame planes (stamp and bit planes of steps 2-3, Alg. 1
+ * and 2).  A scratch of k times this size (k <= VG_MAX_PLANE_SETS) holds k
+ * sets: vg_integrate_batch then runs up to k consecutive frames of the grid
+ * together (see there).  Host-only; 0 for invalid sizes. */
 size_t vg_scratch_bytes(int32_t grid_size_x, int32_t grid_size_y, int32_t grid_size_z,
                         int32_t vox_inf);
+
+/* Most plane sets a grid's scratch is used for (scratch beyond that many
+ * sets is left alone). */
+#define VG_MAX_PLANE_SETS 16
 
 /* Step 1 (Sec. IV-A): bind caller buffers to a new grid and set every voxel
  * of loc_grid to unknown (enqueued on `stream`).
@@ -113,6 +120,8 @@ size_t vg_scratch_bytes(int32_t grid_size_x, int32_t grid_size_y, int32_t grid_s
  *   loc_spare: unused (may be NULL).
  *   scratch: device, scratch_bytes >= vg_scratch_bytes(..., vox_inf), 256-byte
  *     aligned; it is cleared here and owned by the grid until destroyed.
+ *     floor(scratch_bytes / vg_scratch_bytes(...)) plane sets, at most
+ *     VG_MAX_PLANE_SETS, are used.
  *   origin_w: world position (m) of the grid corner (voxel (0,0,0)'s minimum
  *     corner); vox_size > 0 m; vox_inf in [0, 16] voxels of inflation.
  *   Dimensions in [1, 65535] with vg_grid_bytes(...) < 2^30.
@@ -227,13 +236,19 @@ size_t vg_batch_workspace_bytes(int32_t max_frames);
  * for i = 0 .. n_frames-1 in order, vg_shift_grid(frames[i].grid,
  * frames[i].shift) followed by vg_integrate_frame (or vg_integrate_points)
  * of frames[i] -- voxel for voxel.  Frames may target any mix of grids on the
- * current device; frames of one grid are applied in their order.  Frames of
- * distinct grids run together: frame i belongs to round k if k earlier
- * frames target its grid, and each round is one launch per stage over all
- * its frames, whatever their image sizes, sensors, poses and grid sizes.  A
- * round of a single frame runs the one-frame launches instead (the shift's
- * clear inside its walk launch, as vg_integrate_frame_shifted), unless
- * stage events are given (vg_integrate_batch_timed).
+ * current device; frames of one grid are applied in their order.  Frames
+ * run together in rounds: a grid whose scratch holds S plane sets (see
+ * vg_create_grid) puts its k-th frame of the batch into round floor(k / S),
+ * on plane set k mod S, and each round is one launch per stage over all its
+ * frames, whatever their image sizes, sensors, poses and grid sizes.  Steps
+ * 2-3 of a round's frames of one grid run in parallel, each frame on its own
+ * planes in its own (shifted) grid coordinates, since they read only their
+ * own measurements (Alg. 1, 2); the round's merge then takes each grid's
+ * frames in order, every frame's shift clear (Sec. IV-E) and marks (Alg. 3)
+ * applied in turn, so the latest frame that saw a voxel decides it.  A round
+ * of a single frame runs the one-frame launches instead (the shift's clear
+ * inside its walk launch, as vg_integrate_frame_shifted), unless stage
+ * events are given (vg_integrate_batch_timed).
  *   workspace: device, 256-byte aligned, workspace_bytes >=
  *     vg_batch_workspace_bytes(n_frames) (else VG_ERR_BUDGET).  The frame
  *     tables are written into it through kernel arguments (no host staging

@@ -143,9 +143,10 @@ struct vg_grid {
     Layout lay;
     uint32_t epoch;          // stamp of the last frame, 0 = none yet
     int device;
-    // spinning fan table currently in scratch
-    int32_t hz_vd = 0;
-    double hz_fov = -1.0;
+    int32_t sets = 1;        // plane sets in scratch, lay.fixed bytes apart
+    // spinning fan table currently in each set
+    int32_t hz_vd[kMaxPlaneSets] = {};
+    double hz_fov[kMaxPlaneSets] = {};
     int32_t tile_log2w = 3;  // ray tiles of (1 << tile_log2w) x (64 >> tile_log2w) targets
     // measurement hook: sets of kStages (start, stop) pairs, one set per frame
     std::vector<StageEvents> prof;
@@ -336,8 +337,8 @@ struct GridState {
     int32_t shift[3];
     int32_t ring[3];
     uint32_t epoch;
-    int32_t hz_vd;
-    double hz_fov;
+    int32_t hz_vd[kMaxPlaneSets];
+    double hz_fov[kMaxPlaneSets];
 };
 
 GridState state_of(const vg_grid *g)
@@ -346,8 +347,8 @@ GridState state_of(const vg_grid *g)
     std::memcpy(s.shift, g->shift, sizeof s.shift);
     std::memcpy(s.ring, g->ring, sizeof s.ring);
     s.epoch = g->epoch;
-    s.hz_vd = g->hz_vd;
-    s.hz_fov = g->hz_fov;
+    std::memcpy(s.hz_vd, g->hz_vd, sizeof s.hz_vd);
+    std::memcpy(s.hz_fov, g->hz_fov, sizeof s.hz_fov);
     return s;
 }
 
@@ -356,8 +357,17 @@ void store_state(vg_grid *g, const GridState &s)
     std::memcpy(g->shift, s.shift, sizeof s.shift);
     std::memcpy(g->ring, s.ring, sizeof s.ring);
     g->epoch = s.epoch;
-    g->hz_vd = s.hz_vd;
-    g->hz_fov = s.hz_fov;
+    std::memcpy(g->hz_vd, s.hz_vd, sizeof s.hz_vd);
+    std::memcpy(g->hz_fov, s.hz_fov, sizeof s.hz_fov);
+}
+
+// No fan table in any set: the next spinning frame writes its own.
+void forget_fan_tables(vg_grid *g)
+{
+    for (int k = 0; k < kMaxPlaneSets; ++k) {
+        g->hz_vd[k] = 0;
+        g->hz_fov[k] = -1.0;
+    }
 }
 
 // Step 5 on the ring buffer (Sec. IV-E): grid coordinate x now holds what
@@ -396,6 +406,26 @@ void plan_shift(const vg_grid *g, GridState &gs, const int32_t d[3], SlabClear &
             gs.ring[a] = c.ring[a] = 0;
 }
 
+// The regions of vg_frustum.h for one frame: the pinhole fan (images and
+// point clouds), and the image's pyramid for pinhole images whose valid
+// depths are not negative.  The corner pixels' slopes are the fp32 slopes the
+// seed pass uses (rounding is monotonic, so every pixel's lies between).
+void row_limits(const vg_grid *g, int kind, const vg_sensor &s, const Fan &fan, const vg_pose &T,
+                const float o[3], int32_t W, int32_t H, RowLimits &L)
+{
+    const bool img = kind == kPinhole && s.depth_min >= 0.0f && W > 0 && H > 0;
+    float ku[2] = {0.0f, 0.0f}, kv[2] = {0.0f, 0.0f};
+    if (img) {
+        ku[0] = (float)((0.0 - s.cx) / s.fx);
+        ku[1] = (float)(((double)W - 1.0 - s.cx) / s.fx);
+        kv[0] = (float)((0.0 - s.cy) / s.fy);
+        kv[1] = (float)(((double)H - 1.0 - s.cy) / s.fy);
+    }
+    make_row_limits(T.R, o, kind != kSpinning, fan.vd, fan.hw, fan.hh, img,
+                    std::min(ku[0], ku[1]), std::max(ku[0], ku[1]), std::min(kv[0], kv[1]),
+                    std::max(kv[0], kv[1]), g->r, g->n[0], L);
+}
+
 // Host plan of steps 2-4 for one frame: every per-frame constant and launch
 // size.  Nothing is launched and no state changes.
 struct FramePlan {
@@ -408,6 +438,7 @@ struct FramePlan {
     bool wrap;        // the stamp planes must be cleared first (stamp wrapped)
     bool upload_hz;   // the spinning fan table must be (re)written
     bool direct;      // occupied cubes stamped directly into bytes (no dilation)
+    int32_t set;      // plane set of the grid's scratch the frame uses
     uint32_t epoch;
     int32_t ring[3];  // ring offsets of the grid when the frame merges
 };
@@ -420,9 +451,11 @@ constexpr int64_t kDirectStores = 16 << 20;
 
 vg_status plan_frame(const vg_grid *g, const GridState &gs, int kind, const float *data,
                      int64_t pitch_floats, int32_t W, int32_t H, const vg_sensor *sensor,
-                     const vg_pose *T, FramePlan &p, bool allow_direct = false)
+                     const vg_pose *T, FramePlan &p, bool allow_direct = false, int32_t set = 0)
 {
     p.kind = kind;
+    p.set = set;
+    uint8_t *const sc = g->scratch + (size_t)set * g->lay.fixed;   // the set's planes
     if (!fan_for(*sensor, g->s, p.fan))
         return VG_ERR_ARG;
     if ((W > 0 && H > 0) && !data)
@@ -455,7 +488,8 @@ vg_status plan_frame(const vg_grid *g, const GridState &gs, int kind, const floa
     // Per-frame stamp 1..255; the stamp planes are cleared when it wraps.
     p.wrap = gs.epoch == 255;
     p.epoch = p.wrap ? 1 : gs.epoch + 1;
-    p.upload_hz = kind == kSpinning && (gs.hz_vd != fan.vd || gs.hz_fov != sensor->fov_y);
+    p.upload_hz =
+        kind == kSpinning && (gs.hz_vd[set] != fan.vd || gs.hz_fov[set] != sensor->fov_y);
     std::memcpy(p.ring, gs.ring, sizeof p.ring);
 
     Planes pl;
@@ -465,13 +499,14 @@ vg_status plan_frame(const vg_grid *g, const GridState &gs, int kind, const floa
     pl.py = g->lay.py;
     pl.pz = g->lay.pz;
     pl.seed_pitch = g->lay.seed_pitch;
-    pl.seed = g->scratch + g->lay.seed;
-    pl.bitx = reinterpret_cast<uint32_t *>(g->scratch + g->lay.bitx);
-    pl.occ = reinterpret_cast<uint32_t *>(g->scratch + g->lay.occ);
-    pl.marks = g->scratch + g->lay.marks;
+    pl.seed = sc + g->lay.seed;
+    pl.bitx = reinterpret_cast<uint32_t *>(sc + g->lay.bitx);
+    pl.occ = reinterpret_cast<uint32_t *>(sc + g->lay.occ);
+    pl.marks = sc + g->lay.marks;
     pl.nbytes = (uint32_t)((size_t)g->lay.gxp * g->n[1] * g->n[2]);
     seed_box(g, kind, *sensor, *T, tv, pl.lo, pl.hi);
     pl.epoch = p.epoch;
+    row_limits(g, kind, *sensor, fan, *T, o, W, H, pl.lim);
     const int64_t side = 2 * g->r + 1;
     p.direct = allow_direct && (int64_t)W * H * side * side * side <= kDirectStores;
     pl.occb = p.direct ? pl.seed : nullptr;   // grid-layout stamps in the seed plane's place
@@ -510,7 +545,7 @@ vg_status plan_frame(const vg_grid *g, const GridState &gs, int kind, const floa
     rp.tile_log2w = g->tile_log2w;
     rp.tiles_a = (fan_a + tw - 1) / tw;
     rp.tiles = (int32_t)tiles;
-    rp.hz = reinterpret_cast<const int32_t *>(g->scratch + g->lay.hz);
+    rp.hz = reinterpret_cast<const int32_t *>(sc + g->lay.hz);
     rp.occ = p.direct ? static_cast<const void *>(pl.occb) : static_cast<const void *>(pl.occ);
     rp.occ_bytes = p.direct ? pl.nbytes : pl.nbytes / 8;
     rp.occ_is_bytes = p.direct ? 1 : 0;
@@ -535,25 +570,27 @@ void advance(GridState &gs, const FramePlan &p, const vg_sensor *sensor)
 {
     gs.epoch = p.epoch;
     if (p.upload_hz) {
-        gs.hz_vd = p.fan.vd;
-        gs.hz_fov = sensor->fov_y;
+        gs.hz_vd[p.set] = p.fan.vd;
+        gs.hz_fov[p.set] = sensor->fov_y;
     }
 }
 
-// Work done before a planned frame's stages: the stamp planes cleared on a
-// wrap, the spinning fan table written.
+// Work done before a planned frame's stages: the stamp planes of every set
+// cleared on a wrap (stamps restart at 1, so no set may keep an old one),
+// the spinning fan table of the frame's set written.
 hipError_t prepare_frame(const vg_grid *g, const FramePlan &p, hipStream_t st)
 {
     hipError_t e = hipSuccess;
-    if (p.wrap) {
-        e = launch_fill(g->scratch + g->lay.seed, 0, g->lay.bitx - g->lay.seed, st);
+    for (int32_t k = 0; p.wrap && k < g->sets && e == hipSuccess; ++k) {
+        uint8_t *const sc = g->scratch + (size_t)k * g->lay.fixed;
+        e = launch_fill(sc + g->lay.seed, 0, g->lay.bitx - g->lay.seed, st);
         if (e == hipSuccess)
-            e = launch_fill(g->scratch + g->lay.marks, 0, g->lay.hz - g->lay.marks, st);
+            e = launch_fill(sc + g->lay.marks, 0, g->lay.hz - g->lay.marks, st);
     }
     if (e == hipSuccess && p.upload_hz)
-        e = launch_upload(reinterpret_cast<uint32_t *>(g->scratch + g->lay.hz),
-                          reinterpret_cast<const uint32_t *>(p.fan.hz.data()), p.fan.hz.size(),
-                          st);
+        e = launch_upload(
+            reinterpret_cast<uint32_t *>(g->scratch + (size_t)p.set * g->lay.fixed + g->lay.hz),
+            reinterpret_cast<const uint32_t *>(p.fan.hz.data()), p.fan.hz.size(), st);
     return e;
 }
 
@@ -728,6 +765,8 @@ vg_status vg_create_grid(int32_t gx, int32_t gy, int32_t gz, float vox_size,
     g->scratch = static_cast<uint8_t *>(scratch);
     g->scratch_bytes = scratch_bytes;
     g->lay = lay;
+    g->sets = (int32_t)std::min<size_t>(scratch_bytes / lay.fixed, kMaxPlaneSets);
+    forget_fan_tables(g);
     g->epoch = 0;
     if (hipGetDevice(&g->device) != hipSuccess) {
         delete g;
@@ -736,7 +775,7 @@ vg_status vg_create_grid(int32_t gx, int32_t gy, int32_t gz, float vox_size,
     hipStream_t st = static_cast<hipStream_t>(stream);
     // Step 1: every voxel of the local grid starts unknown; stamps start clear.
     if (launch_fill(loc_grid, VG_UNKNOWN, n, st) != hipSuccess ||
-        launch_fill(scratch, 0, lay.fixed, st) != hipSuccess) {
+        launch_fill(scratch, 0, (size_t)g->sets * lay.fixed, st) != hipSuccess) {
         delete g;
         return VG_ERR_HIP;
     }
@@ -758,14 +797,16 @@ vg_status vg_rebind_grid(vg_grid *g, uint8_t *loc_grid, uint8_t *loc_spare, size
     if (!same_device(g))
         return VG_ERR_STATE;
     // fresh stamp planes: no stamp of an earlier frame is left to match
-    if (launch_fill(scratch, 0, g->lay.fixed, static_cast<hipStream_t>(stream)) != hipSuccess)
+    const int32_t sets = (int32_t)std::min<size_t>(scratch_bytes / g->lay.fixed, kMaxPlaneSets);
+    if (launch_fill(scratch, 0, (size_t)sets * g->lay.fixed, static_cast<hipStream_t>(stream)) !=
+        hipSuccess)
         return VG_ERR_HIP;
     g->loc = loc_grid;
     g->scratch = static_cast<uint8_t *>(scratch);
     g->scratch_bytes = scratch_bytes;
+    g->sets = sets;
     g->epoch = 0;
-    g->hz_vd = 0;
-    g->hz_fov = -1.0;
+    forget_fan_tables(g);
     return VG_OK;
 }
 
@@ -949,11 +990,12 @@ vg_status vg_integrate_batch_timed(const vg_frame *frames, int32_t n_frames, voi
     // Plan every frame against the state its grid will have by then.
     std::vector<vg_grid *> grids;
     std::vector<GridState> states;
-    std::vector<int32_t> grid_rounds;
+    std::vector<int32_t> grid_frames;   // frames planned so far per grid
     std::vector<FramePlan> plans((size_t)n_frames);
     std::vector<int32_t> grid_of((size_t)n_frames), round_of((size_t)n_frames);
     std::vector<uint8_t> moved_of((size_t)n_frames);
     std::vector<SlabClear> clears((size_t)n_frames);
+    std::vector<std::array<int32_t, 3>> shift_at((size_t)n_frames);   // grid shift after the frame's
     for (int32_t i = 0; i < n_frames; ++i) {
         const vg_frame &f = frames[i];
         vg_grid *g = f.grid;
@@ -983,7 +1025,7 @@ vg_status vg_integrate_batch_timed(const vg_frame *frames, int32_t n_frames, voi
         if (k == grids.size()) {
             grids.push_back(g);
             states.push_back(state_of(g));
-            grid_rounds.push_back(0);
+            grid_frames.push_back(0);
         }
         GridState &gs = states[k];
         bool moved = false;
@@ -999,12 +1041,17 @@ vg_status vg_integrate_batch_timed(const vg_frame *frames, int32_t n_frames, voi
             plan_shift(g, gs, f.shift, clears[i]);
             clears[i].loc = g->loc;
         }
-        vg_status rc = plan_frame(g, gs, kind, f.data, pitch, W, H, &f.sensor, &f.T_w_c, plans[i]);
+        // the grid's k-th frame of the batch runs in round k / sets on plane
+        // set k mod sets: a round holds up to `sets` consecutive frames of a grid
+        const int32_t kth = grid_frames[k]++;
+        vg_status rc = plan_frame(g, gs, kind, f.data, pitch, W, H, &f.sensor, &f.T_w_c, plans[i],
+                                  false, kth % g->sets);
         if (rc != VG_OK)
             return rc;
         advance(gs, plans[i], &f.sensor);
         grid_of[i] = (int32_t)k;
-        round_of[i] = grid_rounds[k]++;
+        round_of[i] = kth / g->sets;
+        std::memcpy(shift_at[i].data(), gs.shift, sizeof gs.shift);
     }
     for (vg_grid *g : grids)
         if (!same_device(g))
@@ -1012,11 +1059,24 @@ vg_status vg_integrate_batch_timed(const vg_frame *frames, int32_t n_frames, voi
 
     // Frame tables, one per round, packed into the workspace.
     int32_t rounds = 0;
-    for (int32_t r : grid_rounds)
-        rounds = std::max(rounds, r);
+    for (int32_t i = 0; i < n_frames; ++i)
+        rounds = std::max(rounds, round_of[i] + 1);
     std::vector<std::vector<int32_t>> members((size_t)rounds);
     for (int32_t i = 0; i < n_frames; ++i)
         members[(size_t)round_of[i]].push_back(i);
+    // a grid's frames of a round contiguous and in batch order (the merge
+    // takes them as one run)
+    for (std::vector<int32_t> &mem : members)
+        std::stable_sort(mem.begin(), mem.end(),
+                         [&](int32_t a, int32_t b) { return grid_of[a] < grid_of[b]; });
+    // rounds with a run of several frames of one grid merge run by run
+    std::vector<uint8_t> seq_round((size_t)rounds, 0);
+    for (int32_t r = 0; r < rounds; ++r) {
+        const std::vector<int32_t> &mem = members[(size_t)r];
+        for (size_t j = 1; j < mem.size(); ++j)
+            if (grid_of[mem[j]] == grid_of[mem[j - 1]])
+                seq_round[(size_t)r] = 1;
+    }
     std::vector<size_t> table_at((size_t)rounds);
     size_t used = 0;
     for (int32_t r = 0; r < rounds; ++r) {
@@ -1057,6 +1117,38 @@ vg_status vg_integrate_batch_timed(const vg_frame *frames, int32_t n_frames, voi
             const vg_grid *g = grids[(size_t)grid_of[i]];
             int64_t blocks[kBatchStages];
             batch_blocks(g, p, moved_of[i] != 0, round_tile[(size_t)r], blocks);
+            // a run of frames of one grid: its first frame carries the run and
+            // the merge's rows -- the union of the frames' row boxes moved into
+            // the grid coordinates of the run's last frame (a row a frame's
+            // box holds that has left the grid by then was cleared by a later
+            // shift of the run, which the merge re-applies in order)
+            int32_t group = 0;
+            RowBox dom{1, 0, 1, 0};
+            if (seq_round[(size_t)r] && (j == 0 || grid_of[mem[(size_t)j - 1]] != grid_of[i])) {
+                int32_t e = j;
+                while (e < m && grid_of[mem[(size_t)e]] == grid_of[i])
+                    ++e;
+                group = e - j;
+                const std::array<int32_t, 3> &last = shift_at[(size_t)mem[(size_t)e - 1]];
+                for (int32_t t = j; t < e; ++t) {
+                    const int32_t it = mem[(size_t)t];
+                    const RowBox &b = plans[(size_t)it].rows;
+                    if (b.y0 > b.y1 || b.z0 > b.z1)
+                        continue;
+                    const int32_t dy = last[1] - shift_at[(size_t)it][1];
+                    const int32_t dz = last[2] - shift_at[(size_t)it][2];
+                    const RowBox moved{std::max(b.y0 - dy, 0), std::min(b.y1 - dy, g->n[1] - 1),
+                                       std::max(b.z0 - dz, 0), std::min(b.z1 - dz, g->n[2] - 1)};
+                    dom = row_union(dom, moved);
+                }
+                blocks[kBatchResolve] =
+                    (dom.y0 <= dom.y1 && dom.z0 <= dom.z1)
+                        ? (2 * (int64_t)p.sp.pl.wx * (dom.y1 - dom.y0 + 1) *
+                               (int64_t)(dom.z1 - dom.z0 + 1) + 255) / 256
+                        : 0;
+            } else if (seq_round[(size_t)r]) {
+                blocks[kBatchResolve] = 0;
+            }
             FrameDesc d;
             std::memset(&d, 0, sizeof d);
             d.sp = p.sp;
@@ -1067,6 +1159,8 @@ vg_status vg_integrate_batch_timed(const vg_frame *frames, int32_t n_frames, voi
             std::memcpy(d.ring, p.ring, sizeof d.ring);
             d.inside = p.inside ? 1 : 0;
             d.seed_bx = p.kind == kPoints ? 0 : std::max((p.sp.W + 63) / 64, 1);
+            d.group = group;
+            d.dom = dom;
             std::memcpy(&fd[j], &d, sizeof d);
             for (int s = 0; s < kBatchStages; ++s) {
                 start[s * (m + 1) + j] = (int32_t)acc[s];
@@ -1127,7 +1221,8 @@ vg_status vg_integrate_batch_timed(const vg_frame *frames, int32_t n_frames, voi
             }
             const bool yz = s == kBatchDilateYZ;
             e = launch_batch_stage(s, fd, start + s * (m + 1), m, totals[(size_t)r][s], st, ev,
-                                   yz ? round_tile[(size_t)r] : 0, yz ? round_lds[(size_t)r] : 0);
+                                   yz ? round_tile[(size_t)r] : 0, yz ? round_lds[(size_t)r] : 0,
+                                   s == kBatchResolve && seq_round[(size_t)r]);
         }
     }
     if (e != hipSuccess) {

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "vg_frustum.h"
 #include "vg_walk.h"
 
 namespace vg {
@@ -34,6 +35,10 @@ constexpr int kPoints = 2;
 // Largest supported vox_inf: the x dilation works on a 64-bit window of
 // 32 output voxels plus 2 * vox_inf neighbours.
 constexpr int kMaxInflation = 16;
+
+// Most per-frame plane sets one grid's scratch may hold: a batch runs up to
+// that many consecutive frames of one grid together, each on its own set.
+constexpr int32_t kMaxPlaneSets = 16;
 
 // Row pitch of the device grid layout.
 inline int32_t grid_pitch(int32_t gx) { return 32 * ((gx + 31) / 32); }
@@ -63,6 +68,7 @@ struct Planes {
     uint32_t nbytes;     // bytes of the device-layout grid
     int32_t lo[3], hi[3];  // padded box that holds every seed (lo > hi: none)
     uint32_t epoch;      // stamp of this frame (1..255)
+    RowLimits lim;       // columns of each row the frame can change or seed
 };
 
 // Step 2a: transform and quantise every measured point, stamp its voxel (or,
@@ -123,6 +129,12 @@ struct FrameDesc {
     int32_t ring[3];            // ring offsets the frame's merge uses
     int32_t inside;             // the camera voxel lies in the grid
     int32_t seed_bx;            // image seed blocks along x (points: 0)
+    // Merge of a round that holds several consecutive frames of one grid:
+    // on the first frame of each grid's run of frames (in order, contiguous
+    // in the table), the run's length and the rows the merge covers, in the
+    // grid coordinates of the run's last frame; 0 on the run's other frames.
+    int32_t group;
+    RowBox dom;
 };
 
 // The y/z dilation runs on tiles staged through LDS when a row's words fit a
@@ -232,9 +244,12 @@ hipError_t launch_upload(uint32_t *dst, const uint32_t *src, size_t words, hipSt
 // tile_w > 0 (kBatchDilateYZ only): the tiled y/z dilation of that slot width
 // with `lds` bytes of LDS per block; the block prefixes then count
 // dilate_tiles(pl, tile_w) per frame.
+// seq (kBatchResolve only): the merge takes each grid's run of frames
+// together (FrameDesc::group), and the block prefixes count its domain's
+// blocks on the run's first frame and none on the others.
 hipError_t launch_batch_stage(int stage, const FrameDesc *fd, const int32_t *start, int32_t n,
                               int32_t blocks, hipStream_t st, const StageEvents &ev = {},
-                              int tile_w = 0, size_t lds = 0);
+                              int tile_w = 0, size_t lds = 0, bool seq = false);
 // Linear (pitch gx) <-> device layout (pitch gxp) copies of a whole grid.
 hipError_t copy_grid(uint8_t *dst, int64_t dst_pitch, const uint8_t *src, int64_t src_pitch,
                      const int32_t n[3], hipMemcpyKind kind, hipStream_t st);

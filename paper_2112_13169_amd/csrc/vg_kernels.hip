@@ -243,13 +243,18 @@ __device__ __forceinline__ void dilate_x_body(const Planes &pl, int64_t gid)
     const int32_t nz = pl.hi[2] - pl.lo[2] + 1;
     if (pl.lo[0] > pl.hi[0] || ny <= 0 || nz <= 0 || gid >= (int64_t)pl.wx * ny * nz)
         return;
-    const int32_t w = (int32_t)(gid % pl.wx);
-    const int64_t row = gid / pl.wx;
-    const int32_t y = pl.lo[1] + (int32_t)(row % ny);
-    const int32_t z = pl.lo[2] + (int32_t)(row / ny);
+    // fewer words than a padded grid has bytes: 32-bit index arithmetic
+    const uint32_t g32 = (uint32_t)gid, wx = (uint32_t)pl.wx;
+    const int32_t w = (int32_t)(g32 % wx);
+    const uint32_t row = g32 / wx;
+    const int32_t y = pl.lo[1] + (int32_t)(row % (uint32_t)ny);
+    const int32_t z = pl.lo[2] + (int32_t)(row / (uint32_t)ny);
     const int32_t x0 = 32 * w;
     uint32_t out = 0;
-    if (x0 <= pl.hi[0] && x0 + 31 + 2 * pl.r >= pl.lo[0]) {
+    // read the seeds of padded columns x0 .. x0 + 31 + 2r only if the seed box
+    // and the image's region of this row (grid coordinates = padded - r) reach them
+    if (x0 <= pl.hi[0] && x0 + 31 + 2 * pl.r >= pl.lo[0] &&
+        row_run_seeded(pl.lim, y - pl.r, z - pl.r, x0 - pl.r, x0 + 31 + pl.r)) {
         const uint4 *src = reinterpret_cast<const uint4 *>(
             pl.seed + (int64_t)pl.seed_pitch * (y + (int64_t)pl.py * z) + x0);
         const uint32_t rep = (pl.epoch & 0xFFu) * 0x01010101u;
@@ -278,10 +283,11 @@ __device__ __forceinline__ void dilate_yz_body(const Planes &pl, int64_t gid)
 {
     if (gid >= (int64_t)pl.wx * pl.n[1] * pl.n[2])
         return;
-    const int32_t w = (int32_t)(gid % pl.wx);
-    const int64_t row = gid / pl.wx;
-    const int32_t y = (int32_t)(row % pl.n[1]);
-    const int32_t z = (int32_t)(row / pl.n[1]);
+    const uint32_t g32 = (uint32_t)gid, wx = (uint32_t)pl.wx;   // < 2^26 words
+    const int32_t w = (int32_t)(g32 % wx);
+    const uint32_t row = g32 / wx;
+    const int32_t y = (int32_t)(row % (uint32_t)pl.n[1]);
+    const int32_t z = (int32_t)(row / (uint32_t)pl.n[1]);
     const int32_t y0 = max(y, pl.lo[1]), y1 = min(y + 2 * pl.r, pl.hi[1]);
     const int32_t z0 = max(z, pl.lo[2]), z1 = min(z + 2 * pl.r, pl.hi[2]);
     uint32_t out = 0;
@@ -391,10 +397,17 @@ __device__ __forceinline__ int32_t wrap_add(int32_t v, int32_t r, int32_t n)
     return s >= n ? s - n : s;
 }
 
-// Stamp matches of the 16 bytes at any byte address p: five aligned dword
-// loads from p rounded down to 4 (so up to 4 bytes past p + 16 are read),
-// realigned with v_alignbyte.
-__device__ __forceinline__ uint32_t stamp_mask16(const uint8_t *p, uint32_t rep)
+// Bit j (j < 16) set iff byte j of q equals the byte replicated in rep.
+__device__ __forceinline__ uint32_t byte_eq_mask16(const uint4 &q, uint32_t rep)
+{
+    return byte_eq_mask(q.x, rep) | (byte_eq_mask(q.y, rep) << 4) |
+           (byte_eq_mask(q.z, rep) << 8) | (byte_eq_mask(q.w, rep) << 12);
+}
+
+// The 16 bytes at any byte address p: five aligned dword loads from p
+// rounded down to 4 (so up to 4 bytes past p + 16 are read), realigned with
+// v_alignbyte.
+__device__ __forceinline__ uint4 load16_unaligned(const uint8_t *p)
 {
     const uintptr_t a = (uintptr_t)p;
     const uint32_t *w = reinterpret_cast<const uint32_t *>(a & ~(uintptr_t)3);
@@ -403,11 +416,106 @@ __device__ __forceinline__ uint32_t stamp_mask16(const uint8_t *p, uint32_t rep)
 #pragma unroll
     for (int k = 0; k < 5; ++k)
         v[k] = w[k];
-    uint32_t m = 0;
+    return make_uint4(__builtin_amdgcn_alignbyte(v[1], v[0], sh),
+                      __builtin_amdgcn_alignbyte(v[2], v[1], sh),
+                      __builtin_amdgcn_alignbyte(v[3], v[2], sh),
+                      __builtin_amdgcn_alignbyte(v[4], v[3], sh));
+}
+
+// Masks of 16 grid columns of one plane row (bit j: column x0 + j, wrapping
+// at the grid's width; nvalid columns): the frame's occupied voxels, traced
+// stamps and free stamps.  The columns' bytes are one aligned 16-byte run,
+// one unaligned run (aligned dwords + v_alignbyte), or a run that wraps (per
+// byte); the stamps are compared once, after the loads.
+template <bool kBytes>
+__device__ __forceinline__ void gather16(const Planes &pl, int64_t prow, int32_t x0,
+                                         int32_t nvalid, uint32_t &occ16, uint32_t &tr16,
+                                         uint32_t &fr16)
+{
+    const int32_t gx = pl.n[0];
+    const uint32_t rep = (pl.epoch & 0xFFu) * 0x01010101u;
+    uint4 fr, tr, oc = make_uint4(0u, 0u, 0u, 0u);
+    uint32_t obits = 0;
+    if ((x0 & 15) == 0 && x0 + nvalid <= gx) {
+        // one run of grid columns starting on a 16-column boundary
+        const int64_t b = prow + x0;
+        fr = *reinterpret_cast<const uint4 *>(pl.marks + b);
+        tr = *reinterpret_cast<const uint4 *>(pl.marks + pl.nbytes + b);
+        if (kBytes)
+            oc = *reinterpret_cast<const uint4 *>(pl.occb + b);
+        else
+            obits = (pl.occ[b >> 5] >> (b & 16)) & 0xFFFFu;
+    } else if (x0 + nvalid <= gx) {
+        const int64_t b = prow + x0;
+        fr = load16_unaligned(pl.marks + b);
+        tr = load16_unaligned(pl.marks + pl.nbytes + b);
+        if (kBytes) {
+            oc = load16_unaligned(pl.occb + b);
+        } else {
+            const uint64_t two =
+                (uint64_t)pl.occ[b >> 5] | ((uint64_t)pl.occ[(b >> 5) + 1] << 32);
+            obits = (uint32_t)(two >> (b & 31)) & 0xFFFFu;
+        }
+    } else {
+        uint32_t f[4] = {0u, 0u, 0u, 0u}, t[4] = {0u, 0u, 0u, 0u}, o[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-        m |= byte_eq_mask(__builtin_amdgcn_alignbyte(v[k + 1], v[k], sh), rep) << (4 * k);
-    return m;
+        for (int j = 0; j < 16; ++j) {
+            if (j >= nvalid)
+                break;
+            int32_t x = x0 + j;
+            if (x >= gx)
+                x -= gx;
+            const int64_t b = prow + x;
+            f[j >> 2] |= (uint32_t)pl.marks[b] << (8 * (j & 3));
+            t[j >> 2] |= (uint32_t)pl.marks[pl.nbytes + b] << (8 * (j & 3));
+            if (kBytes)
+                o[j >> 2] |= (uint32_t)pl.occb[b] << (8 * (j & 3));
+            else
+                obits |= ((pl.occ[b >> 5] >> (b & 31)) & 1u) << j;
+        }
+        fr = make_uint4(f[0], f[1], f[2], f[3]);
+        tr = make_uint4(t[0], t[1], t[2], t[3]);
+        oc = make_uint4(o[0], o[1], o[2], o[3]);
+    }
+    const uint32_t valid = nvalid >= 16 ? 0xFFFFu : (1u << nvalid) - 1u;
+    occ16 = (kBytes ? byte_eq_mask16(oc, rep) : obits) & valid;
+    tr16 = byte_eq_mask16(tr, rep) & valid;
+    fr16 = byte_eq_mask16(fr, rep) & valid;
+}
+
+// 16 voxels of the local grid: the columns of clr16 become unknown (a
+// shift's clear), then Alg. 3 -- an occupied voxel becomes occupied, else a
+// traced one unknown, else a free one free; the others keep their value.
+__device__ __forceinline__ void apply16(uint4 &v, uint32_t clr16, uint32_t occ16, uint32_t tr16,
+                                        uint32_t fr16)
+{
+    uint32_t *vw = reinterpret_cast<uint32_t *>(&v);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        // spread 4 mask bits to 4 byte masks
+        uint32_t cm = (((clr16 >> (4 * j)) & 0xFu) * 0x00204081u & 0x01010101u) * 0xFFu;
+        uint32_t om = (((occ16 >> (4 * j)) & 0xFu) * 0x00204081u & 0x01010101u) * 0xFFu;
+        uint32_t tm = (((tr16 >> (4 * j)) & 0xFu) * 0x00204081u & 0x01010101u) * 0xFFu;
+        uint32_t fm = (((fr16 >> (4 * j)) & 0xFu) * 0x00204081u & 0x01010101u) * 0xFFu;
+        tm &= ~om;
+        fm &= ~(om | tm);
+        vw[j] = (vw[j] & ~(cm | om | tm | fm)) | (0x02020202u & om) | (0x01010101u & fm);
+    }
+}
+
+// Whether the frame may change one of the nvalid grid columns x0 .. (wrapping
+// at gx) of grid row (y, z): outside the frame's regions (vg_frustum.h) its
+// planes hold no mark and no occupied voxel, and the merge reads nothing.
+__device__ __forceinline__ bool chunk_touched(const Planes &pl, int32_t y, int32_t z, int32_t x0,
+                                              int32_t nvalid)
+{
+    const int32_t gx = pl.n[0], e = x0 + nvalid - 1;
+    int32_t run[4];
+    if (!row_runs(pl.lim, y, z, gx, run))
+        return true;
+    if (e < gx)
+        return runs_meet(run, x0, e);
+    return runs_meet(run, x0, gx - 1) || runs_meet(run, 0, e - gx);
 }
 
 // Alg. 3: the frame's marks merged into the local grid.  One lane per 16
@@ -423,10 +531,11 @@ __device__ __forceinline__ void resolve_body(const Planes &pl, uint8_t *loc, con
     const int32_t chunks = pl.wx * 2;   // 16-column chunks per row
     if (ny <= 0 || nz <= 0 || gid >= (int64_t)chunks * ny * nz)
         return;
-    const int32_t k = (int32_t)(gid % chunks);
-    const int64_t row = gid / chunks;
-    const int32_t y = rows.y0 + (int32_t)(row % ny);
-    const int32_t z = rows.z0 + (int32_t)(row / ny);
+    const uint32_t g32 = (uint32_t)gid;   // < 2^26 chunks in a grid
+    const int32_t k = (int32_t)(g32 % (uint32_t)chunks);
+    const uint32_t row = g32 / (uint32_t)chunks;
+    const int32_t y = rows.y0 + (int32_t)(row % (uint32_t)ny);
+    const int32_t z = rows.z0 + (int32_t)(row / (uint32_t)ny);
     const int32_t gx = pl.n[0];
     const int32_t c0 = 16 * k;               // buffer column of the chunk
     if (c0 >= gx)
@@ -438,69 +547,102 @@ __device__ __forceinline__ void resolve_body(const Planes &pl, uint8_t *loc, con
     int32_t x0 = c0 - ring[0];               // grid column of buffer column c0
     if (x0 < 0)
         x0 += gx;
-    const uint32_t rep = (pl.epoch & 0xFFu) * 0x01010101u;
+    if (!chunk_touched(pl, y, z, x0, nvalid))
+        return;
     uint32_t occ16, tr16, fr16;
-    if ((x0 & 15) == 0 && x0 + nvalid <= gx) {
-        // one run of grid columns starting on a 16-column boundary
-        const int64_t b = prow + x0;
-        if (kBytes) {
-            const uint4 oc = *reinterpret_cast<const uint4 *>(pl.occb + b);
-            occ16 = byte_eq_mask(oc.x, rep) | (byte_eq_mask(oc.y, rep) << 4) |
-                    (byte_eq_mask(oc.z, rep) << 8) | (byte_eq_mask(oc.w, rep) << 12);
-        } else {
-            occ16 = (pl.occ[b >> 5] >> (b & 16)) & 0xFFFFu;
-        }
-        const uint4 fr = *reinterpret_cast<const uint4 *>(pl.marks + b);
-        const uint4 tr = *reinterpret_cast<const uint4 *>(pl.marks + pl.nbytes + b);
-        tr16 = byte_eq_mask(tr.x, rep) | (byte_eq_mask(tr.y, rep) << 4) |
-               (byte_eq_mask(tr.z, rep) << 8) | (byte_eq_mask(tr.w, rep) << 12);
-        fr16 = byte_eq_mask(fr.x, rep) | (byte_eq_mask(fr.y, rep) << 4) |
-               (byte_eq_mask(fr.z, rep) << 8) | (byte_eq_mask(fr.w, rep) << 12);
-    } else if (x0 + nvalid <= gx) {
-        const int64_t b = prow + x0;
-        if (kBytes) {
-            occ16 = stamp_mask16(pl.occb + b, rep);
-        } else {
-            const uint64_t two =
-                (uint64_t)pl.occ[b >> 5] | ((uint64_t)pl.occ[(b >> 5) + 1] << 32);
-            occ16 = (uint32_t)(two >> (b & 31)) & 0xFFFFu;
-        }
-        fr16 = stamp_mask16(pl.marks + b, rep);
-        tr16 = stamp_mask16(pl.marks + pl.nbytes + b, rep);
-    } else {
-        occ16 = tr16 = fr16 = 0;
-        const uint8_t e = (uint8_t)pl.epoch;
-        for (int j = 0; j < nvalid; ++j) {
-            int32_t x = x0 + j;
-            if (x >= gx)
-                x -= gx;
-            const int64_t b = prow + x;
-            occ16 |= (kBytes ? (uint32_t)(pl.occb[b] == e) : (pl.occ[b >> 5] >> (b & 31)) & 1u)
-                     << j;
-            tr16 |= (uint32_t)(pl.marks[pl.nbytes + b] == e) << j;
-            fr16 |= (uint32_t)(pl.marks[b] == e) << j;
-        }
-    }
-    const uint32_t valid = nvalid >= 16 ? 0xFFFFu : (1u << nvalid) - 1u;
-    occ16 &= valid;
-    tr16 &= valid;
-    fr16 &= valid;
+    gather16<kBytes>(pl, prow, x0, nvalid, occ16, tr16, fr16);
     if ((occ16 | tr16 | fr16) == 0)
         return;
     uint8_t *dst = loc + brow + c0;
     uint4 v = *reinterpret_cast<const uint4 *>(dst);
-    uint32_t *vw = reinterpret_cast<uint32_t *>(&v);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        // spread 4 mask bits to 4 byte masks
-        uint32_t om = (((occ16 >> (4 * j)) & 0xFu) * 0x00204081u & 0x01010101u) * 0xFFu;
-        uint32_t tm = (((tr16 >> (4 * j)) & 0xFu) * 0x00204081u & 0x01010101u) * 0xFFu;
-        uint32_t fm = (((fr16 >> (4 * j)) & 0xFu) * 0x00204081u & 0x01010101u) * 0xFFu;
-        tm &= ~om;
-        fm &= ~(om | tm);
-        vw[j] = (vw[j] & ~(om | tm | fm)) | (0x02020202u & om) | (0x01010101u & fm);
-    }
+    apply16(v, 0u, occ16, tr16, fr16);
     *reinterpret_cast<uint4 *>(dst) = v;
+}
+
+// Columns of 16 grid columns (x0 .. , wrapping; nvalid of them) in row (y, z)
+// that a frame's shift clears (clear_body's rule); none if it does not shift.
+__device__ __forceinline__ uint32_t clear_mask16(const SlabClear &c, int32_t y, int32_t z,
+                                                 int32_t x0, int32_t nvalid)
+{
+    if (!c.loc)
+        return 0u;
+    const uint32_t valid = nvalid >= 16 ? 0xFFFFu : (1u << nvalid) - 1u;
+    if ((y >= c.lo[1] && y < c.hi[1]) || (z >= c.lo[2] && z < c.hi[2]) ||
+        c.hi[0] - c.lo[0] >= c.n[0])
+        return valid;
+    if (c.lo[0] >= c.hi[0])
+        return 0u;
+    uint32_t m = 0;
+    for (int j = 0; j < nvalid; ++j) {
+        int32_t x = x0 + j;
+        if (x >= c.n[0])
+            x -= c.n[0];
+        if (x >= c.lo[0] && x < c.hi[0])
+            m |= 1u << j;
+    }
+    return m;
+}
+
+// Alg. 3 for a run of consecutive frames of one grid (fd[0 .. group), in
+// order), each walked into its own planes in its own grid coordinates, with
+// the shifts between them (Sec. IV-E): every voxel ends as if the frames had
+// been merged one after another -- per frame, first its shift's clear, then
+// its marks, so the latest frame that saw the voxel decides.  The shifts'
+// clears have already run over the whole grid (the batch's shift stage);
+// here they are applied again in order, so that they also undo the marks of
+// earlier frames of the run.  One lane per 16 buffer columns of a buffer row
+// that holds a grid row (in the coordinates of the run's last frame) of the
+// merge's domain; each frame's planes are read at its own grid coordinates of
+// those voxels, where its row box holds them.
+__device__ __forceinline__ void resolve_seq_body(const FrameDesc *fd, int64_t gid)
+{
+    const FrameDesc &f0 = fd[0];
+    const int32_t m = f0.group;
+    const RowBox &dom = f0.dom;
+    const Planes &pl0 = f0.sp.pl;
+    const int32_t ny = dom.y1 - dom.y0 + 1, nz = dom.z1 - dom.z0 + 1;
+    const int32_t chunks = pl0.wx * 2;
+    if (m <= 0 || ny <= 0 || nz <= 0 || gid >= (int64_t)chunks * ny * nz)
+        return;
+    const uint32_t g32 = (uint32_t)gid;   // < 2^26 chunks in a grid
+    const int32_t k = (int32_t)(g32 % (uint32_t)chunks);
+    const uint32_t row = g32 / (uint32_t)chunks;
+    const int32_t gx = pl0.n[0], gy = pl0.n[1], gz = pl0.n[2];
+    const int32_t c0 = 16 * k;
+    if (c0 >= gx)
+        return;
+    const int32_t nvalid = min(16, gx - c0);
+    const FrameDesc &fl = fd[m - 1];
+    const int32_t by = wrap_add(dom.y0 + (int32_t)(row % (uint32_t)ny), fl.ring[1], gy);
+    const int32_t bz = wrap_add(dom.z0 + (int32_t)(row / (uint32_t)ny), fl.ring[2], gz);
+    uint8_t *dst = f0.loc + 32 * (int64_t)pl0.wx * (by + (int64_t)gy * bz) + c0;
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    bool loaded = false;
+    for (int32_t j = 0; j < m; ++j) {
+        const FrameDesc &f = fd[j];
+        int32_t y = by - f.ring[1], z = bz - f.ring[2], x0 = c0 - f.ring[0];
+        if (y < 0)
+            y += gy;
+        if (z < 0)
+            z += gz;
+        if (x0 < 0)
+            x0 += gx;
+        const uint32_t clr16 = clear_mask16(f.clear, y, z, x0, nvalid);
+        uint32_t occ16 = 0, tr16 = 0, fr16 = 0;
+        if (y >= f.rows.y0 && y <= f.rows.y1 && z >= f.rows.z0 && z <= f.rows.z1 &&
+            chunk_touched(f.sp.pl, y, z, x0, nvalid))
+            gather16<false>(f.sp.pl, 32 * (int64_t)pl0.wx * (y + (int64_t)gy * z), x0, nvalid,
+                            occ16, tr16, fr16);
+        if ((clr16 | occ16 | tr16 | fr16) == 0)
+            continue;
+        if (!loaded) {
+            v = *reinterpret_cast<const uint4 *>(dst);
+            loaded = true;
+        }
+        apply16(v, clr16, occ16, tr16, fr16);
+    }
+    if (loaded)
+        *reinterpret_cast<uint4 *>(dst) = v;
 }
 
 // Sec. IV-E on the ring buffer: one lane per 16 buffer columns of a grid
@@ -512,9 +654,10 @@ __device__ __forceinline__ void clear_body(const SlabClear &c, int64_t gid)
     const int32_t cpr = c.gxp >> 4;
     if (gid >= (int64_t)cpr * c.n[1] * c.n[2])
         return;
-    const int32_t row = (int32_t)(gid / cpr);
-    const int32_t c0 = 16 * (int32_t)(gid - (int64_t)row * cpr);
-    const int32_t y = row % c.n[1], z = row / c.n[1];
+    const uint32_t g32 = (uint32_t)gid;   // < 2^26 chunks in a grid
+    const uint32_t row = g32 / (uint32_t)cpr;
+    const int32_t c0 = 16 * (int32_t)(g32 - row * (uint32_t)cpr);
+    const int32_t y = (int32_t)(row % (uint32_t)c.n[1]), z = (int32_t)(row / (uint32_t)c.n[1]);
     const int32_t by = wrap_add(y, c.ring[1], c.n[1]), bz = wrap_add(z, c.ring[2], c.n[2]);
     uint8_t *dst = c.loc + (int64_t)c.gxp * (by + (int64_t)c.n[1] * bz) + c0;
     const bool whole = (y >= c.lo[1] && y < c.hi[1]) || (z >= c.lo[2] && z < c.hi[2]) ||
@@ -693,6 +836,17 @@ __global__ __launch_bounds__(kBlock) void kb_resolve(const FrameDesc *__restrict
     resolve_body<false>(f.sp.pl, f.loc, f.rows, f.ring, (int64_t)local * kBlock + threadIdx.x);
 }
 
+// The merge of a round that holds runs of frames of one grid: a block finds
+// the first frame of its run (the run's other frames have no blocks).
+__global__ __launch_bounds__(kBlock) void kb_resolve_seq(const FrameDesc *__restrict__ fd,
+                                                         const int32_t *__restrict__ start,
+                                                         int32_t n)
+{
+    int32_t local;
+    const int32_t i = frame_of(start, n, blockIdx.x, local);
+    resolve_seq_body(fd + i, (int64_t)local * kBlock + threadIdx.x);
+}
+
 uint32_t blocks_for(int64_t threads) { return (uint32_t)((threads + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -861,7 +1015,7 @@ hipError_t launch_upload(uint32_t *dst, const uint32_t *src, size_t words, hipSt
 
 hipError_t launch_batch_stage(int stage, const FrameDesc *fd, const int32_t *start, int32_t n,
                               int32_t blocks, hipStream_t st, const StageEvents &ev, int tile_w,
-                              size_t lds)
+                              size_t lds, bool seq)
 {
     if (blocks <= 0 || n <= 0)
         return record_empty_stage(ev, st);
@@ -890,7 +1044,10 @@ hipError_t launch_batch_stage(int stage, const FrameDesc *fd, const int32_t *sta
         hipExtLaunchKernelGGL(kb_rays, g, b, 0, st, ev.start, ev.stop, 0, fd, start, n);
         break;
     case kBatchResolve:
-        hipExtLaunchKernelGGL(kb_resolve, g, b, 0, st, ev.start, ev.stop, 0, fd, start, n);
+        if (seq)
+            hipExtLaunchKernelGGL(kb_resolve_seq, g, b, 0, st, ev.start, ev.stop, 0, fd, start, n);
+        else
+            hipExtLaunchKernelGGL(kb_resolve, g, b, 0, st, ev.start, ev.stop, 0, fd, start, n);
         break;
     default:
         return hipErrorInvalidValue;

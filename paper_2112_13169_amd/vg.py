@@ -382,13 +382,15 @@ def vg_destroy_grid(g):
 class GridBuffers:
     """Device buffers one grid needs, allocated with torch (the library itself
     never allocates): the grid's ring buffer `loc` and its scratch, sized for
-    the grid and vox_inf (`spare` is None: shifts work in place)."""
+    the grid and vox_inf (`spare` is None: shifts work in place).  sets > 1
+    gives the scratch that many plane sets, so that a batch runs up to `sets`
+    consecutive frames of the grid together."""
 
-    def __init__(self, dims, vox_inf, device="cuda"):
+    def __init__(self, dims, vox_inf, device="cuda", sets=1):
         import torch
         gx, gy, gz = dims
         n = vg_grid_bytes(gx, gy, gz)
-        nbytes = vg_scratch_bytes(gx, gy, gz, vox_inf)
+        nbytes = vg_scratch_bytes(gx, gy, gz, vox_inf) * int(sets)
         if n == 0 or nbytes == 0:
             raise ValueError("invalid grid size")
         self.dims = tuple(dims)

@@ -26,9 +26,9 @@ def _say(msg):
 class Twin:
     """A device grid and its oracle twin."""
 
-    def __init__(self, dims, vox_size, origin, vox_inf):
+    def __init__(self, dims, vox_size, origin, vox_inf, sets=1):
         self.dims = tuple(dims)
-        self.buf = vg.GridBuffers(dims, vox_inf)
+        self.buf = vg.GridBuffers(dims, vox_inf, sets=sets)
         self.h = vg.vg_create_grid(dims, vox_size, origin, vox_inf, self.buf.loc, self.buf.spare,
                                    self.buf.scratch)
         self.s = np.float32(vox_size)
@@ -125,14 +125,16 @@ def _workspace(n):
     return torch.empty(vg.vg_batch_workspace_bytes(n), dtype=torch.uint8, device="cuda")
 
 
-def test_mixed_batch_matches_oracle():
+@pytest.mark.parametrize("sets", [1, 3])
+def test_mixed_batch_matches_oracle(sets):
     """Pinhole, spinning and point-cloud frames on grids of different sizes and
     vox_inf; two grids get several frames (with shifts between them), so the
-    batch runs in rounds."""
+    batch runs in rounds -- with one plane set per grid, or with 3, where a
+    grid's frames share a round and one merge takes them in order."""
     frames = [scenes.make_frame("plain-small", 30 + i) for i in range(3)]
     frames.append(_points_frame(scenes.make_frame("plain-small", 33)))
     frames.append(_spin_frame(5))
-    twins = [Twin(f.dims, f.vox_size, f.origin, f.vox_inf) for f in frames]
+    twins = [Twin(f.dims, f.vox_size, f.origin, f.vox_inf, sets=sets) for f in frames]
     # a second and third frame for grid 0, a second for the spinning grid
     extra = [(0, scenes.make_frame("plain-small", 40), (2, -1, 0)),
              (4, _spin_frame(6), (0, 0, 1)),
@@ -171,16 +173,18 @@ def test_batch_with_cameras_inside_and_outside_their_grids():
         t.close()
 
 
-def test_sequence_batch_with_shifts_matches_oracle():
+@pytest.mark.parametrize("sets", [1, 3, 8])
+def test_sequence_batch_with_shifts_matches_oracle(sets):
     """Eight consecutive frames of one trajectory as one batch (order kept
-    across the re-centring shifts)."""
+    across the re-centring shifts); with several plane sets, up to that many
+    frames run steps 2-3 together and are merged by one launch."""
     traj = scenes.make_trajectory("served", robot=2, n_frames=8)
     frs = [scenes.trajectory_frame(traj, i, robot=2) for i in range(8)]
     dims = (96, 96, 48)
     for f in frs:
         f.dims = dims
     t = Twin(dims, frs[0].vox_size, scenes.centred_origin(frs[0].t, dims, frs[0].vox_size),
-             frs[0].vox_inf)
+             frs[0].vox_inf, sets=sets)
     shifts, origin_shift = [], np.zeros(3, np.int32)
     for f in frs:
         org = oracle.origin(t.base, origin_shift, t.s)
@@ -197,6 +201,97 @@ def test_sequence_batch_with_shifts_matches_oracle():
     t.check("sequence batch")
     assert np.allclose(vg.vg_grid_origin(t.h), t.origin())
     t.close()
+
+
+def test_sequence_batches_across_stamp_wrap_and_ring_seam():
+    """300 frames of one grid with 4 plane sets, as batches of 7 (rounds of 4
+    and 3 frames, the stamp wrapping inside a round), random shifts of up to
+    3 voxels either way between frames (the ring wraps at every seam):
+    equals the oracle after every 50 frames, and a second grid fed the same
+    frames one per call equals it too."""
+    rng = np.random.default_rng(7)
+    pool = [scenes.make_frame("plain-small", 100 + i, size=(80, 60),
+                              position=(0.3 * i - 1.5, 1.0 - 0.2 * i, 1.0)) for i in range(10)]
+    f0 = pool[0]
+    t = Twin(f0.dims, f0.vox_size, f0.origin, f0.vox_inf, sets=4)
+    plain = Twin(f0.dims, f0.vox_size, f0.origin, f0.vox_inf)
+    ws = _workspace(7)
+    done = 0
+    while done < 300:
+        m = min(7, 300 - done)
+        plan = []
+        for k in range(m):
+            fr = pool[(done + k) % len(pool)]
+            d = tuple(int(v) for v in rng.integers(-3, 4, size=3))
+            plan.append((fr, d))
+        dev = [DevFrame(t, fr, d) for fr, d in plan]
+        vg.vg_integrate_batch([x.desc for x in dev], ws)
+        for fr, d in plan:
+            x = DevFrame(plain, fr)
+            vg.vg_integrate_frame_shifted(plain.h, x.data, vg.pinhole_sensor(fr.intr),
+                                          vg.make_pose(fr.R, fr.t), d)
+            t.oracle_frame(fr, d)
+        torch.cuda.synchronize()
+        done += m
+        if done % 50 < 7 or done == 300:
+            _say(f"sequence batches: {done} frames")
+            t.check(f"after {done} frames")
+            assert np.array_equal(plain.read(), t.ref), f"one-frame path after {done} frames"
+    t.close()
+    plain.close()
+
+
+def test_large_sequence_batch_of_8_matches_plain_and_oracle():
+    """The large pinhole sequence (1280x720 into 400x400x200 at 0.025 m,
+    vox_inf 3): its first 8 frames, each re-centring the grid, as one batch on
+    a grid with 8 plane sets -- one round, one launch per stage, one merge --
+    equal the one-frame path and the oracle voxel for voxel."""
+    traj = scenes.make_trajectory("large-pinhole", n_frames=8)
+    frs = [scenes.trajectory_frame(traj, i) for i in range(8)]
+    f0 = frs[0]
+    t = Twin(f0.dims, f0.vox_size, f0.origin, f0.vox_inf, sets=8)
+    plain = Twin(f0.dims, f0.vox_size, f0.origin, f0.vox_inf)
+    shifts = [tuple(d) for d in vg.sequence_shifts(t.h, [f.t for f in frs])]
+    dev = [DevFrame(t, f, d) for f, d in zip(frs, shifts)]
+    _say(f"large sequence batch of 8, shifts {shifts}")
+    vg.vg_integrate_batch([x.desc for x in dev], _workspace(8))
+    for f, d in zip(frs, shifts):
+        x = DevFrame(plain, f)
+        vg.vg_integrate_frame_shifted(plain.h, x.data, vg.pinhole_sensor(f.intr),
+                                      vg.make_pose(f.R, f.t), d)
+    torch.cuda.synchronize()
+    got = t.read()
+    assert np.array_equal(got, plain.read()), "batch differs from the one-frame path"
+    _say("large sequence batch: oracle")
+    for f, d in zip(frs, shifts):
+        t.oracle_frame(f, d)
+    t.check("large sequence batch of 8")
+    assert np.count_nonzero(got == vg.VG_FREE) > 10 ** 6
+    t.close()
+    plain.close()
+
+
+def test_large_spinning_sequence_batch_of_8_matches_plain():
+    """The same for the spinning sequence (128x2048 range images): the
+    8-frame batch on 8 plane sets equals the one-frame path."""
+    traj = scenes.make_trajectory("large-spinning", n_frames=8)
+    frs = [scenes.trajectory_frame(traj, i) for i in range(8)]
+    f0 = frs[0]
+    t = Twin(f0.dims, f0.vox_size, f0.origin, f0.vox_inf, sets=8)
+    plain = Twin(f0.dims, f0.vox_size, f0.origin, f0.vox_inf)
+    shifts = [tuple(d) for d in vg.sequence_shifts(t.h, [f.t for f in frs])]
+    dev = [DevFrame(t, f, d) for f, d in zip(frs, shifts)]
+    _say(f"large spinning sequence batch of 8, shifts {shifts}")
+    vg.vg_integrate_batch([x.desc for x in dev], _workspace(8))
+    for f, d, x in zip(frs, shifts, dev):
+        H, W = f.depth.shape
+        sensor = vg.spinning_sensor(W, H, *x.tabs, f.intr["vfov"], f.intr["depth_min"],
+                                    f.intr["depth_max"])
+        vg.vg_integrate_frame_shifted(plain.h, x.data, sensor, vg.make_pose(f.R, f.t), d)
+    torch.cuda.synchronize()
+    assert np.array_equal(t.read(), plain.read()), "batch differs from the one-frame path"
+    t.close()
+    plain.close()
 
 
 def test_full_size_batch_of_64_matches_one_frame_path():
