@@ -67,20 +67,27 @@ TRAFFIC_FILE_MEDIUM = os.path.join(PROFILES, "traffic.json")
 TRAFFIC_FILE_BATCHED = os.path.join(PROFILES, "traffic_batched.json")
 SECTIONS = ("headline", "spinning", "medium", "small", "batched", "served", "paper")
 
-STAGE_KERNELS = {"k_dilate": ["k_dilate_x", "k_dilate_yz", "k_dilate_yz_tile<8>",
-                              "k_dilate_yz_tile<16>"],
+STAGE_KERNELS = {"k_dilate": ["k_dilate_x<false>", "k_dilate_x<true>", "k_dilate_yz",
+                              "k_dilate_yz_tile<8>", "k_dilate_yz_tile<16>"],
                  "k_rays": [f"k_rays<{g}, {b}, {l}>" for g in ("false", "true")
                             for b in ("false", "true") for l in ("false", "true")],
-                 "k_resolve": ["k_resolve<false>", "k_resolve<true>"]}
+                 "k_resolve": [f"k_resolve<{b}, {w}>" for b in ("false", "true")
+                               for w in ("false", "true")]}
 
 
 def log(msg):
     print(f"# {msg}", file=sys.stderr, flush=True)
 
 
+_WORKERS = None
+
+
 def host_workers():
     """Worker processes / threads for host work: at most 16 (one GPU's share
-    of the host) and no more than this process may use."""
+    of the host) and no more than this process may use; --host-workers sets
+    it."""
+    if _WORKERS is not None:
+        return _WORKERS
     try:
         n = len(os.sched_getaffinity(0))
     except AttributeError:
@@ -163,6 +170,16 @@ def _seq_frame(arg):
 
 
 def _pool_map(fn, args, chunksize=4):
+    """fn over args in forked worker processes, or in this process with one
+    worker (a profiler that sets up the GPU before the program starts leaves
+    no state a fork may copy)."""
+    if host_workers() == 1:
+        out = []
+        for i, a in enumerate(args):
+            out.append(fn(a))
+            if (i + 1) % 16 == 0:
+                log(f"rendered {i + 1}/{len(args)}")
+        return out
     import multiprocessing as mp
     with mp.get_context("fork").Pool(host_workers()) as pool:
         return pool.map(fn, args, chunksize=chunksize)
@@ -970,6 +987,10 @@ def main():
     ap.add_argument("--stat-frames", type=int, default=16,
                     help="sampled headline frames run through the oracle on every host thread "
                          "for voxel-update and walk-step counts (0 skips them)")
+    ap.add_argument("--host-workers", type=int, default=0,
+                    help="processes rendering inputs and threads of the CPU legs (0: the "
+                         "host's share, at most 16; 1: render in this process, as under a "
+                         "profiler that sets up the GPU first)")
     ap.add_argument("--pool-steps", type=int, default=300,
                     help="timed steps of the medium and small frame pools")
     ap.add_argument("--batch", type=int, default=64,
@@ -987,6 +1008,9 @@ def main():
                     help="the paper's standard parameters alone (--only paper), printing "
                          "their section")
     args = ap.parse_args()
+    if args.host_workers > 0:
+        global _WORKERS
+        _WORKERS = args.host_workers
 
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the voxel-grid path "

@@ -283,7 +283,7 @@ vg_status vg_integrate_batch_timed(const vg_frame *frames, int32_t n_frames, voi
 /* vg_integrate_batch for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc): no workspace argument -- the frame tables go to a device array
- * the library holds, one per GPU (143 616 bytes, VG_STATIC_BATCH_MAX_FRAMES
+ * the library holds, one per GPU (172 288 bytes, VG_STATIC_BATCH_MAX_FRAMES
  * frames' worth, held until the process ends).  The call allocates no device
  * memory.  n_frames > VG_STATIC_BATCH_MAX_FRAMES returns VG_ERR_BUDGET and
  * enqueues nothing.  Every call on one GPU shares that GPU's array, and each

@@ -25,16 +25,17 @@ constexpr size_t kHzBytes = (size_t)8 * kMaxFan * sizeof(int32_t);
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-// Scratch layout (all offsets 256-aligned):
+// Scratch layout of one plane set (all offsets 256-aligned):
 //   seed      seed stamps on the grid padded by vox_inf, rows of seed_pitch bytes
 //   bitx      seeds dilated along x, one 32-bit word per 32 voxels of a padded row
 //   occ       occupied voxels of the frame, one bit per device-layout voxel
 //   marks     free stamps, then "unknown and traced" stamps, one byte per
 //             device-layout voxel each
 //   hz        spinning fan: half height per ring column
+//   lim       the frame's row regions (vg_frustum.h), written by its seed pass
 struct Layout {
     int32_t gxp, wx, py, pz, seed_pitch;
-    size_t seed, bitx, occ, marks, hz, fixed;
+    size_t seed, bitx, occ, marks, hz, lim, fixed;
 };
 
 Layout layout_for(int32_t gx, int32_t gy, int32_t gz, int32_t r)
@@ -50,7 +51,8 @@ Layout layout_for(int32_t gx, int32_t gy, int32_t gz, int32_t r)
     l.occ = l.bitx + align_up((size_t)4 * l.wx * l.py * l.pz);
     l.marks = l.occ + align_up((size_t)4 * l.wx * gy * gz);
     l.hz = l.marks + align_up((size_t)2 * l.gxp * gy * gz);
-    l.fixed = l.hz + kHzBytes;
+    l.lim = l.hz + kHzBytes;
+    l.fixed = l.lim + align_up(sizeof(RowLimits));
     return l;
 }
 
@@ -404,26 +406,57 @@ void plan_shift(const vg_grid *g, GridState &gs, const int32_t d[3], SlabClear &
     if (all)
         for (int a = 0; a < 3; ++a)
             gs.ring[a] = c.ring[a] = 0;
+    // lanes: the buffer chunks of the exposed x slab in every row (all of
+    // them when everything is cleared), the rows of the y and z slabs whole
+    const int32_t cpr = c.gxp / 16;
+    for (int k = 0; k < 4; ++k)
+        c.xrun[k] = 0;
+    if (all) {
+        c.lo[0] = 0;
+        c.hi[0] = c.n[0];
+        c.xrun[1] = cpr;
+    } else if (c.lo[0] < c.hi[0]) {
+        const int32_t b0 = (c.lo[0] + c.ring[0]) % c.n[0], len = c.hi[0] - c.lo[0];
+        if (b0 + len <= c.n[0]) {
+            c.xrun[0] = b0 / 16;
+            c.xrun[1] = (b0 + len - 1) / 16 + 1;
+        } else {
+            c.xrun[0] = b0 / 16;
+            c.xrun[1] = (c.n[0] - 1) / 16 + 1;
+            c.xrun[2] = 0;
+            c.xrun[3] = (b0 + len - c.n[0] - 1) / 16 + 1;
+        }
+    }
+    const int64_t rows = (int64_t)c.n[1] * c.n[2];
+    c.lanes[0] = rows * ((c.xrun[1] - c.xrun[0]) + (c.xrun[3] - c.xrun[2]));
+    c.lanes[1] = all ? 0 : (int64_t)(c.hi[1] - c.lo[1]) * c.n[2] * cpr;
+    c.lanes[2] = all ? 0 : (int64_t)(c.hi[2] - c.lo[2]) * c.n[1] * cpr;
 }
 
-// The regions of vg_frustum.h for one frame: the pinhole fan (images and
-// point clouds), and the image's pyramid for pinhole images whose valid
-// depths are not negative.  The corner pixels' slopes are the fp32 slopes the
-// seed pass uses (rounding is monotonic, so every pixel's lies between).
-void row_limits(const vg_grid *g, int kind, const vg_sensor &s, const Fan &fan, const vg_pose &T,
-                const float o[3], int32_t W, int32_t H, RowLimits &L)
+// What the seed pass needs to compute the regions of vg_frustum.h for one
+// frame: the pinhole fan (images and point clouds), and the image's pyramid
+// for pinhole images whose valid depths are not negative.  The corner
+// pixels' slopes are the fp32 slopes the seed pass uses (rounding is
+// monotonic, so every pixel's lies between).
+void region_inputs(int kind, const vg_sensor &s, const Fan &fan, int32_t W, int32_t H,
+                   SeedParams &sp)
 {
-    const bool img = kind == kPinhole && s.depth_min >= 0.0f && W > 0 && H > 0;
+    sp.vd = fan.vd;
+    sp.hw = fan.hw;
+    sp.hh = fan.hh;
+    sp.lim_fan = kind != kSpinning ? 1 : 0;
+    sp.lim_img = kind == kPinhole && s.depth_min >= 0.0f && W > 0 && H > 0 ? 1 : 0;
     float ku[2] = {0.0f, 0.0f}, kv[2] = {0.0f, 0.0f};
-    if (img) {
+    if (sp.lim_img) {
         ku[0] = (float)((0.0 - s.cx) / s.fx);
         ku[1] = (float)(((double)W - 1.0 - s.cx) / s.fx);
         kv[0] = (float)((0.0 - s.cy) / s.fy);
         kv[1] = (float)(((double)H - 1.0 - s.cy) / s.fy);
     }
-    make_row_limits(T.R, o, kind != kSpinning, fan.vd, fan.hw, fan.hh, img,
-                    std::min(ku[0], ku[1]), std::max(ku[0], ku[1]), std::min(kv[0], kv[1]),
-                    std::max(kv[0], kv[1]), g->r, g->n[0], L);
+    sp.lim_k[0] = std::min(ku[0], ku[1]);
+    sp.lim_k[1] = std::max(ku[0], ku[1]);
+    sp.lim_k[2] = std::min(kv[0], kv[1]);
+    sp.lim_k[3] = std::max(kv[0], kv[1]);
 }
 
 // Host plan of steps 2-4 for one frame: every per-frame constant and launch
@@ -506,7 +539,7 @@ vg_status plan_frame(const vg_grid *g, const GridState &gs, int kind, const floa
     pl.nbytes = (uint32_t)((size_t)g->lay.gxp * g->n[1] * g->n[2]);
     seed_box(g, kind, *sensor, *T, tv, pl.lo, pl.hi);
     pl.epoch = p.epoch;
-    row_limits(g, kind, *sensor, fan, *T, o, W, H, pl.lim);
+    pl.lim = reinterpret_cast<const RowLimits *>(sc + g->lay.lim);
     const int64_t side = 2 * g->r + 1;
     p.direct = allow_direct && (int64_t)W * H * side * side * side <= kDirectStores;
     pl.occb = p.direct ? pl.seed : nullptr;   // grid-layout stamps in the seed plane's place
@@ -529,6 +562,8 @@ vg_status plan_frame(const vg_grid *g, const GridState &gs, int kind, const floa
     sp.img = data;
     sp.col_tab = sensor->col_tab;
     sp.row_tab = sensor->row_tab;
+    sp.lim_out = reinterpret_cast<RowLimits *>(sc + g->lay.lim);
+    region_inputs(kind, *sensor, fan, W, H, sp);
 
     RayParams &rp = p.rp;
     std::memcpy(rp.R, T->R, sizeof rp.R);
@@ -596,28 +631,32 @@ hipError_t prepare_frame(const vg_grid *g, const FramePlan &p, hipStream_t st)
 
 
 // Blocks of 256 lanes each batch stage launches for a planned frame.
-void batch_blocks(const vg_grid *g, const FramePlan &p, bool moved, int tile_w,
-                  int64_t blocks[kBatchStages])
+void batch_blocks(const vg_grid *g, const FramePlan &p, bool moved, const SlabClear &clear,
+                  YzTile tile, bool wide_x, bool wide_res, int64_t blocks[kBatchStages])
 {
     auto per = [](int64_t lanes) { return (lanes + 255) / 256; };
     const Planes &pl = p.sp.pl;
     const int64_t wx = pl.wx;
-    blocks[kBatchShift] = moved ? per((int64_t)(g->lay.gxp / 16) * g->n[1] * g->n[2]) : 0;
+    blocks[kBatchShift] = moved ? per(clear_lanes(clear)) : 0;
+    // at least one seed block: its first lane writes the frame's regions
     if (p.kind == kPoints)
-        blocks[kBatchSeed] = per(p.sp.W);
+        blocks[kBatchSeed] = std::max<int64_t>(per(p.sp.W), 1);
     else
         blocks[kBatchSeed] = (p.sp.W > 0 && p.sp.H > 0)
                                  ? (int64_t)((p.sp.W + 63) / 64) * ((p.sp.H + 3) / 4)
-                                 : 0;
+                                 : 1;
     const bool any = pl.lo[0] <= pl.hi[0] && pl.lo[1] <= pl.hi[1] && pl.lo[2] <= pl.hi[2];
     blocks[kBatchDilateX] =
-        any ? per(wx * (pl.hi[1] - pl.lo[1] + 1) * (int64_t)(pl.hi[2] - pl.lo[2] + 1)) : 0;
+        any ? per(dilate_x_lanes(pl.wx, wide_x) * (pl.hi[1] - pl.lo[1] + 1) *
+                  (int64_t)(pl.hi[2] - pl.lo[2] + 1))
+            : 0;
     blocks[kBatchDilateYZ] =
-        tile_w > 0 ? dilate_tiles(pl, tile_w) : per(wx * g->n[1] * (int64_t)g->n[2]);
+        tile.kw > 0 ? dilate_tiles(pl, tile) : per(wx * g->n[1] * (int64_t)g->n[2]);
     blocks[kBatchRays] = ((int64_t)p.rp.tiles + 3) / 4;
     const RowBox &b = p.rows;
     blocks[kBatchResolve] = (b.y0 <= b.y1 && b.z0 <= b.z1)
-                                ? per(2 * wx * (b.y1 - b.y0 + 1) * (int64_t)(b.z1 - b.z0 + 1))
+                                ? per(merge_lanes(g->n[0], wide_res) * (b.y1 - b.y0 + 1) *
+                                      (int64_t)(b.z1 - b.z0 + 1))
                                 : 0;
 }
 
@@ -1088,25 +1127,54 @@ vg_status vg_integrate_batch_timed(const vg_frame *frames, int32_t n_frames, voi
     std::vector<uint32_t> host(used / 4, 0u);
     std::vector<std::array<int32_t, kBatchStages>> totals((size_t)rounds);
     // tiled y/z dilation per round: the widest slot any frame needs, if every
-    // frame of the round can use tiles (0: the untiled kernel)
-    std::vector<int> round_tile((size_t)rounds, 0);
+    // frame of the round can use tiles (kw 0: the untiled kernel), 8 deep if
+    // every frame can and the round has enough 8-deep tiles
+    std::vector<YzTile> round_tile((size_t)rounds, YzTile{0, 0});
     std::vector<size_t> round_lds((size_t)rounds, 0);
+    // wide forms of the x dilation and the merge where the round's narrow
+    // forms would have many lanes
+    std::vector<uint8_t> wide_x((size_t)rounds, 0), wide_res((size_t)rounds, 0);
+    for (int32_t r = 0; r < rounds; ++r) {
+        int64_t nx = 0, nres = 0;
+        for (int32_t i : members[(size_t)r]) {
+            const Planes &pl = plans[(size_t)i].sp.pl;
+            if (pl.lo[0] <= pl.hi[0] && pl.lo[1] <= pl.hi[1] && pl.lo[2] <= pl.hi[2])
+                nx += dilate_x_lanes(pl.wx, false) * (pl.hi[1] - pl.lo[1] + 1) *
+                      (int64_t)(pl.hi[2] - pl.lo[2] + 1);
+            const RowBox &b = plans[(size_t)i].rows;
+            if (b.y0 <= b.y1 && b.z0 <= b.z1)
+                nres += merge_lanes(pl.n[0], false) * (b.y1 - b.y0 + 1) *
+                        (int64_t)(b.z1 - b.z0 + 1);
+        }
+        wide_x[(size_t)r] = dilate_x_wide(nx) ? 1 : 0;
+        wide_res[(size_t)r] = nres >= kWideLanes ? 1 : 0;
+    }
     for (int32_t r = 0; r < rounds; ++r) {
         const std::vector<int32_t> &mem = members[(size_t)r];
         const int32_t m = (int32_t)mem.size();
-        int tw = 8;
-        for (int32_t i : mem) {
-            const int k = dilate_tile_width(plans[(size_t)i].sp.pl);
-            tw = k == 0 ? 0 : (tw == 0 ? 0 : std::max(tw, k));
+        YzTile pick{0, 0};
+        size_t pick_lds = 0;
+        for (int tz : {kTileDeep, 2}) {
+            int tw = 8;
+            for (int32_t i : mem) {
+                const int k = dilate_tile_width(plans[(size_t)i].sp.pl, tz);
+                tw = k == 0 ? 0 : (tw == 0 ? 0 : std::max(tw, k));
+            }
+            size_t lds = 0;
+            int64_t tiles = 0;
+            for (int32_t i : mem)
+                if (tw > 0) {
+                    lds = std::max(lds, dilate_tile_lds(plans[(size_t)i].sp.pl, YzTile{tw, tz}));
+                    tiles += dilate_tiles(plans[(size_t)i].sp.pl, YzTile{tw, tz});
+                }
+            if (tw == 0 || lds > kMaxTileLds || (tz == kTileDeep && tiles < kDeepTileMin))
+                continue;
+            pick = YzTile{tw, tz};
+            pick_lds = lds;
+            break;
         }
-        size_t lds = 0;
-        for (int32_t i : mem)
-            if (tw > 0)
-                lds = std::max(lds, dilate_tile_lds(plans[(size_t)i].sp.pl, tw));
-        if (lds > kMaxTileLds)
-            tw = 0;
-        round_tile[(size_t)r] = tw;
-        round_lds[(size_t)r] = tw > 0 ? lds : 0;
+        round_tile[(size_t)r] = pick;
+        round_lds[(size_t)r] = pick_lds;
         uint8_t *base = reinterpret_cast<uint8_t *>(host.data()) + table_at[(size_t)r];
         int32_t *start = reinterpret_cast<int32_t *>(base);
         FrameDesc *fd = reinterpret_cast<FrameDesc *>(base + batch_starts_bytes(m));
@@ -1116,7 +1184,8 @@ vg_status vg_integrate_batch_timed(const vg_frame *frames, int32_t n_frames, voi
             const FramePlan &p = plans[(size_t)i];
             const vg_grid *g = grids[(size_t)grid_of[i]];
             int64_t blocks[kBatchStages];
-            batch_blocks(g, p, moved_of[i] != 0, round_tile[(size_t)r], blocks);
+            batch_blocks(g, p, moved_of[i] != 0, clears[i], round_tile[(size_t)r],
+                         wide_x[(size_t)r] != 0, wide_res[(size_t)r] != 0, blocks);
             // a run of frames of one grid: its first frame carries the run and
             // the merge's rows -- the union of the frames' row boxes moved into
             // the grid coordinates of the run's last frame (a row a frame's
@@ -1143,7 +1212,7 @@ vg_status vg_integrate_batch_timed(const vg_frame *frames, int32_t n_frames, voi
                 }
                 blocks[kBatchResolve] =
                     (dom.y0 <= dom.y1 && dom.z0 <= dom.z1)
-                        ? (2 * (int64_t)p.sp.pl.wx * (dom.y1 - dom.y0 + 1) *
+                        ? ((int64_t)merge_lanes_per_row(g->n[0]) * (dom.y1 - dom.y0 + 1) *
                                (int64_t)(dom.z1 - dom.z0 + 1) + 255) / 256
                         : 0;
             } else if (seq_round[(size_t)r]) {
@@ -1220,9 +1289,12 @@ vg_status vg_integrate_batch_timed(const vg_frame *frames, int32_t n_frames, voi
                 ev.stop = r == rounds - 1 ? static_cast<hipEvent_t>(events[2 * s + 1]) : nullptr;
             }
             const bool yz = s == kBatchDilateYZ;
+            const bool wide = (s == kBatchDilateX && wide_x[(size_t)r]) ||
+                              (s == kBatchResolve && wide_res[(size_t)r]);
             e = launch_batch_stage(s, fd, start + s * (m + 1), m, totals[(size_t)r][s], st, ev,
-                                   yz ? round_tile[(size_t)r] : 0, yz ? round_lds[(size_t)r] : 0,
-                                   s == kBatchResolve && seq_round[(size_t)r]);
+                                   yz ? round_tile[(size_t)r] : YzTile{0, 0},
+                                   yz ? round_lds[(size_t)r] : 0,
+                                   s == kBatchResolve && seq_round[(size_t)r], wide);
         }
     }
     if (e != hipSuccess) {

@@ -65,8 +65,9 @@ VG_FR_HD void region_columns(const Region &R, int32_t y, int32_t z, int32_t xmin
     bool none = false;
     for (int k = 0; k < 4; ++k) {
         const RowPlane &q = R.p[k];
-        const double t = (q.e + q.f * yd) + q.g * zd;
-        const double b = t * q.inv + q.c0;
+        // a conservative bound: fused multiply-adds are fine here
+        const double t = fma(q.g, zd, fma(q.f, yd, q.e));
+        const double b = fma(t, q.inv, q.c0);
         if (q.kind > 0)
             fhi = fmin(fhi, b + 1.0);
         else if (q.kind < 0)
@@ -119,13 +120,13 @@ VG_FR_HD bool row_run_seeded(const RowLimits &L, int32_t y, int32_t z, int32_t a
 // of the fp32 walk from the exact ray.
 constexpr double kFanMargin = 1.5;
 
-// Host: one plane of a region from its grid-frame normal n (any length),
-// margin m (voxels) and the apex o (voxels).  reach bounds |x + 1/2 - o_x|
-// over every column a test asks about.
-inline bool make_row_plane(const double n_in[3], double m, const float o[3], double reach,
-                           RowPlane &q)
+// One plane of a region from its grid-frame normal n (any length), margin m
+// (voxels) and the apex o (voxels).  reach bounds |x + 1/2 - o_x| over every
+// column a test asks about.
+VG_FR_HD bool make_row_plane(const double n_in[3], double m, const float o[3], double reach,
+                             RowPlane &q)
 {
-    const double len = std::sqrt(n_in[0] * n_in[0] + n_in[1] * n_in[1] + n_in[2] * n_in[2]);
+    const double len = sqrt(n_in[0] * n_in[0] + n_in[1] * n_in[1] + n_in[2] * n_in[2]);
     if (!(len > 1e-12))
         return false;
     const double n[3] = {n_in[0] / len, n_in[1] / len, n_in[2] / len};
@@ -135,7 +136,7 @@ inline bool make_row_plane(const double n_in[3], double m, const float o[3], dou
     q.e = m - n[1] * (0.5 - (double)o[1]) - n[2] * (0.5 - (double)o[2]);
     q.c0 = (double)o[0] - 0.5;
     q.pad = 0;
-    if (std::fabs(n[0]) > 1e-9) {
+    if (fabs(n[0]) > 1e-9) {
         q.kind = n[0] > 0.0 ? 1 : -1;
         q.inv = 1.0 / n[0];
     } else {
@@ -143,49 +144,60 @@ inline bool make_row_plane(const double n_in[3], double m, const float o[3], dou
         // stays below that for every column
         q.kind = 0;
         q.inv = 0.0;
-        q.e += std::fabs(n[0]) * reach + 1e-9;
+        q.e += fabs(n[0]) * reach + 1e-9;
     }
     return true;
 }
 
-// Host: the regions of one frame.  R: T^v_c's rotation (row-major); o: the
-// camera in voxel units; fan: a pinhole fan of half sizes hw x hh at
-// vox_depth vd (false: unbounded); img: an image whose corner pixels have the
-// fp32 slopes ku0 <= ku <= ku1, kv0 <= kv <= kv1 and whose valid depths are
-// not negative (false: unbounded).  The image's region is widened by
+// Plane `which` of one frame's regions: 0..3 the fan's sides (a <= hw,
+// a >= -hw, b <= hh, b >= -hh of a pinhole fan of half sizes hw x hh at
+// vox_depth vd), 4..7 the image's (x <= ku1 z, x >= ku0 z, y <= kv1 z,
+// y >= kv0 z for an image whose corner pixels have the fp32 slopes ku0 <= ku
+// <= ku1, kv0 <= kv <= kv1).  R: T^v_c's rotation (row-major); o: the camera
+// in voxel units; gx: grid width (the columns the tests ask about lie in
+// [-vox_inf, gx + vox_inf)).  The image's region is widened by
 // (vox_inf + 1/2) sqrt(3) + 1 voxels: an occupied voxel's centre lies within
 // vox_inf + 1/2 voxels per axis of a measured point, plus fp32 rounding.
-// gx: grid width (the columns the tests ask about lie in [-vox_inf, gx +
-// vox_inf)).
-inline void make_row_limits(const float R[9], const float o[3], bool fan, int32_t vd, int32_t hw,
-                            int32_t hh, bool img, float ku0, float ku1, float kv0, float kv1,
-                            int32_t vox_inf, int32_t gx, RowLimits &L)
+// False if the plane is degenerate.
+VG_FR_HD bool make_region_plane(int which, const float R[9], const float o[3], int32_t vd,
+                                int32_t hw, int32_t hh, float ku0, float ku1, float kv0,
+                                float kv1, int32_t vox_inf, int32_t gx, RowPlane &q)
 {
-    L = RowLimits{};
-    const double reach = (double)gx + 2.0 * vox_inf + std::fabs((double)o[0]) + 2.0;
-    bool ok = true;
-    // plane k of the region: grid-frame normal R (cx, cy, cz), margin m
-    auto plane = [&](Region &G, int k, double cx, double cy, double cz, double m) {
-        double n[3];
-        for (int i = 0; i < 3; ++i)
-            n[i] = (double)R[3 * i] * cx + (double)R[3 * i + 1] * cy + (double)R[3 * i + 2] * cz;
-        ok = make_row_plane(n, m, o, reach, G.p[k]) && ok;
-    };
+    double c[3];
+    switch (which) {
+    case 0: c[0] = vd; c[1] = 0.0; c[2] = -(double)hw; break;
+    case 1: c[0] = -(double)vd; c[1] = 0.0; c[2] = -(double)hw; break;
+    case 2: c[0] = 0.0; c[1] = vd; c[2] = -(double)hh; break;
+    case 3: c[0] = 0.0; c[1] = -(double)vd; c[2] = -(double)hh; break;
+    case 4: c[0] = 1.0; c[1] = 0.0; c[2] = -(double)ku1; break;
+    case 5: c[0] = -1.0; c[1] = 0.0; c[2] = (double)ku0; break;
+    case 6: c[0] = 0.0; c[1] = 1.0; c[2] = -(double)kv1; break;
+    default: c[0] = 0.0; c[1] = -1.0; c[2] = (double)kv0; break;
+    }
+    double n[3];
+    for (int i = 0; i < 3; ++i)
+        n[i] = (double)R[3 * i] * c[0] + (double)R[3 * i + 1] * c[1] + (double)R[3 * i + 2] * c[2];
+    const double reach = (double)gx + 2.0 * vox_inf + fabs((double)o[0]) + 2.0;
+    const double m = which < 4 ? kFanMargin : (vox_inf + 0.5) * sqrt(3.0) + 1.0;
+    return make_row_plane(n, m, o, reach, q);
+}
+
+// The regions of one frame (fan: a pinhole fan, else unbounded; img: an
+// image whose valid depths are not negative, else unbounded; the other
+// arguments as for make_region_plane).
+VG_FR_HD void make_row_limits(const float R[9], const float o[3], bool fan, int32_t vd,
+                              int32_t hw, int32_t hh, bool img, float ku0, float ku1, float kv0,
+                              float kv1, int32_t vox_inf, int32_t gx, RowLimits &L)
+{
+    L.has_fan = L.has_img = 0;
     if (!fan)
         return;
-    plane(L.fan, 0, vd, 0.0, -hw, kFanMargin);    // a <= hw
-    plane(L.fan, 1, -vd, 0.0, -hw, kFanMargin);   // a >= -hw
-    plane(L.fan, 2, 0.0, vd, -hh, kFanMargin);    // b <= hh
-    plane(L.fan, 3, 0.0, -vd, -hh, kFanMargin);   // b >= -hh
+    bool ok = true;
+    for (int which = 0; which < (img ? 8 : 4); ++which)
+        ok = make_region_plane(which, R, o, vd, hw, hh, ku0, ku1, kv0, kv1, vox_inf, gx,
+                               which < 4 ? L.fan.p[which] : L.img.p[which - 4]) && ok;
     L.has_fan = ok ? 1 : 0;
-    if (!img || !ok)
-        return;
-    const double m = (vox_inf + 0.5) * std::sqrt(3.0) + 1.0;
-    plane(L.img, 0, 1.0, 0.0, -(double)ku1, m);   // x <= ku1 z
-    plane(L.img, 1, -1.0, 0.0, (double)ku0, m);   // x >= ku0 z
-    plane(L.img, 2, 0.0, 1.0, -(double)kv1, m);   // y <= kv1 z
-    plane(L.img, 3, 0.0, -1.0, (double)kv0, m);   // y >= kv0 z
-    L.has_img = ok ? 1 : 0;
+    L.has_img = ok && img ? 1 : 0;
 }
 
 }  // namespace vg

@@ -43,6 +43,27 @@ constexpr int32_t kMaxPlaneSets = 16;
 // Row pitch of the device grid layout.
 inline int32_t grid_pitch(int32_t gx) { return 32 * ((gx + 31) / 32); }
 
+// The merge and the x dilation have two forms: a narrow one, one lane per
+// 16-column chunk / 32-voxel word, for small launches (more lanes hide more
+// latency), and a wide one, one lane per 64 columns / 128 voxels, that reads
+// only the columns the frame can change (vg_frustum.h).  A launch whose
+// narrow form would have at least kWideLanes lanes (8 wavefronts per SIMD of
+// the chip) takes the wide form.
+constexpr int64_t kWideLanes = (int64_t)1 << 19;
+
+// Wide merge lanes per grid row.
+__host__ __device__ inline int32_t merge_lanes_per_row(int32_t gx) { return (gx + 63) / 64; }
+// Wide x-dilation lanes per padded row (wx: 32-voxel words per row).
+__host__ __device__ inline int32_t dilate_x_lanes_per_row(int32_t wx) { return (wx + 3) / 4; }
+
+inline int64_t merge_lanes(int32_t gx, bool wide)
+{
+    return wide ? merge_lanes_per_row(gx) : grid_pitch(gx) / 16;
+}
+inline bool merge_wide(int32_t gx, int64_t rows) { return merge_lanes(gx, false) * rows >= kWideLanes; }
+inline int64_t dilate_x_lanes(int32_t wx, bool wide) { return wide ? dilate_x_lanes_per_row(wx) : wx; }
+inline bool dilate_x_wide(int64_t narrow_lanes) { return narrow_lanes >= kWideLanes; }
+
 // A box of rows [y0, y1] x [z0, z1] (inclusive; empty if y0 > y1).
 struct RowBox {
     int32_t y0, y1, z0, z1;
@@ -68,7 +89,8 @@ struct Planes {
     uint32_t nbytes;     // bytes of the device-layout grid
     int32_t lo[3], hi[3];  // padded box that holds every seed (lo > hi: none)
     uint32_t epoch;      // stamp of this frame (1..255)
-    RowLimits lim;       // columns of each row the frame can change or seed
+    const RowLimits *lim;  // device: the columns of each row the frame can change
+                           // or seed, written by its seed pass (null: all)
 };
 
 // Step 2a: transform and quantise every measured point, stamp its voxel (or,
@@ -86,6 +108,14 @@ struct SeedParams {
     const float *img;     // depth / range image, or points[W][3]
     const float *col_tab; // spinning: cos/sin azimuth per column
     const float *row_tab; // spinning: cos/sin elevation per row
+    // the frame's regions (vg_frustum.h), computed by the pass's first lane
+    // into lim_out (= pl.lim) from these: a pinhole fan of half sizes hw x hh
+    // at vox_depth vd (lim_fan), an image with the corner slopes lim_k (ku0,
+    // ku1, kv0, kv1; lim_img)
+    RowLimits *lim_out;
+    int32_t vd, hw, hh;
+    int32_t lim_fan, lim_img;
+    float lim_k[4];
 };
 
 // Step 3: the bundled ray fan.  One wavefront owns a tile of 64 fan targets,
@@ -110,14 +140,22 @@ struct RayParams {
 
 // Step 5 on a ring-buffered grid: after the ring offsets moved, the voxels
 // whose grid coordinate lies in an exposed slab [lo, hi) of some axis become
-// unknown.  One lane per grid row.
+// unknown.  Lanes of 16 buffer columns, in three parts: (A) every grid row,
+// over the 16-column buffer chunks xrun[0] .. xrun[1] and xrun[2] .. xrun[3]
+// (half-open) that hold the exposed x slab (every chunk if it is the whole
+// row); (B) the rows of the exposed y slab and (C) those of the exposed z
+// slab, whole.  lanes[] counts each part's lanes.
 struct SlabClear {
     uint8_t *loc;
     int32_t n[3];
     int32_t gxp;
     int32_t ring[3];        // ring offsets after the shift
     int32_t lo[3], hi[3];   // exposed grid coordinates per axis (lo == hi: none)
+    int32_t xrun[4];
+    int64_t lanes[3];
 };
+
+inline int64_t clear_lanes(const SlabClear &c) { return c.lanes[0] + c.lanes[1] + c.lanes[2]; }
 
 // One frame of a batch round, as the batch kernels read it from device memory.
 struct FrameDesc {
@@ -138,35 +176,43 @@ struct FrameDesc {
 };
 
 // The y/z dilation runs on tiles staged through LDS when a row's words fit a
-// fixed slot width kW (8 or 16 words, so rows up to 256 / 512 voxels): a block
-// of kBlock threads is kW word lanes by kBlock / kW row slots, and a tile is
-// kBlock / kW output rows along y by kTileZ along z.  0: untiled.
-constexpr int kTileZ = 2;
-constexpr int kTileMaxIz = 8;    // input z rows a tile may need: kTileZ + 2 vox_inf
+// fixed slot width kW (8 or 16 words, so rows up to 256 / 512 voxels) and
+// vox_inf <= 3: a block of kBlock threads is kW word lanes by kBlock / kW row
+// slots, and a tile is kBlock / kW output rows along y by tz along z -- 2, or
+// 8 for launches with many tiles (fewer z rows read twice: an 8-deep tile
+// reads 8 + 2 vox_inf input z rows, four 2-deep tiles 4 (2 + 2 vox_inf)).
+// kw 0: untiled.
+constexpr int kTileMaxR = 3;
+constexpr int kTileDeep = 8;
+constexpr int64_t kDeepTileMin = 512;   // 8-deep tiles per launch to use them
 constexpr size_t kMaxTileLds = 48 * 1024;
 
-inline int dilate_tile_width(const Planes &pl)
+struct YzTile {
+    int kw, tz;
+};
+
+// The slot width for a frame at tile depth tz (0: the frame cannot be tiled).
+inline int dilate_tile_width(const Planes &pl, int tz)
 {
     const int kw = pl.wx <= 8 ? 8 : (pl.wx <= 16 ? 16 : 0);
-    const size_t ty = kw ? 256 / kw : 0, iz = (size_t)kTileZ + 2 * pl.r, iy = ty + 2 * pl.r;
+    const size_t ty = kw ? 256 / kw : 0, iz = (size_t)tz + 2 * pl.r, iy = ty + 2 * pl.r;
     // each thread loads at most 2 input rows of every z row: iy <= 2 ty
-    if (kw == 0 || iz > (size_t)kTileMaxIz || iy > 2 * ty)
+    if (kw == 0 || pl.r > kTileMaxR || iy > 2 * ty)
         return 0;
     return 4 * (size_t)kw * (iz * iy + iz * ty) <= kMaxTileLds ? kw : 0;
 }
 
-// LDS bytes of one tile of slot width kw: its padded input rows plus the
-// rows dilated along y.
-inline size_t dilate_tile_lds(const Planes &pl, int kw)
+// LDS bytes of one tile: its padded input rows plus the rows dilated along y.
+inline size_t dilate_tile_lds(const Planes &pl, YzTile t)
 {
-    const size_t ty = 256 / kw, iz = (size_t)kTileZ + 2 * pl.r, iy = ty + 2 * pl.r;
-    return 4 * (size_t)kw * (iz * iy + iz * ty);
+    const size_t ty = 256 / t.kw, iz = (size_t)t.tz + 2 * pl.r, iy = ty + 2 * pl.r;
+    return 4 * (size_t)t.kw * (iz * iy + iz * ty);
 }
 
-inline int64_t dilate_tiles(const Planes &pl, int kw)
+inline int64_t dilate_tiles(const Planes &pl, YzTile t)
 {
-    const int ty = 256 / kw;
-    return (int64_t)((pl.n[1] + ty - 1) / ty) * ((pl.n[2] + kTileZ - 1) / kTileZ);
+    const int ty = 256 / t.kw;
+    return (int64_t)((pl.n[1] + ty - 1) / ty) * ((pl.n[2] + t.tz - 1) / t.tz);
 }
 
 // Batch stages, in launch order within a round.
@@ -241,15 +287,18 @@ hipError_t static_batch_workspace(void **ptr);
 hipError_t launch_upload(uint32_t *dst, const uint32_t *src, size_t words, hipStream_t st);
 // Batch: one launch of stage `stage` (kBatch*) over the n frames of a round;
 // fd and start (n + 1 block prefixes) live in device memory; blocks = start[n].
-// tile_w > 0 (kBatchDilateYZ only): the tiled y/z dilation of that slot width
+// tile.kw > 0 (kBatchDilateYZ only): the tiled y/z dilation of that shape
 // with `lds` bytes of LDS per block; the block prefixes then count
-// dilate_tiles(pl, tile_w) per frame.
+// dilate_tiles(pl, tile) per frame.
 // seq (kBatchResolve only): the merge takes each grid's run of frames
 // together (FrameDesc::group), and the block prefixes count its domain's
 // blocks on the run's first frame and none on the others.
+// wide (kBatchDilateX and kBatchResolve without seq): the wide form of the
+// stage, whose block prefixes count its lanes.
 hipError_t launch_batch_stage(int stage, const FrameDesc *fd, const int32_t *start, int32_t n,
                               int32_t blocks, hipStream_t st, const StageEvents &ev = {},
-                              int tile_w = 0, size_t lds = 0, bool seq = false);
+                              YzTile tile = {0, 0}, size_t lds = 0, bool seq = false,
+                              bool wide = false);
 // Linear (pitch gx) <-> device layout (pitch gxp) copies of a whole grid.
 hipError_t copy_grid(uint8_t *dst, int64_t dst_pitch, const uint8_t *src, int64_t src_pitch,
                      const int32_t n[3], hipMemcpyKind kind, hipStream_t st);

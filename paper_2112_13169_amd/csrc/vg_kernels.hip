@@ -210,6 +210,26 @@ __device__ __forceinline__ bool seed_point(const SeedParams &p, int32_t bx, int3
 __device__ __forceinline__ void seed_body(const SeedParams &p, int32_t bx, int32_t by)
 {
     const Planes &pl = p.pl;
+    if (bx == 0 && by == 0 && threadIdx.x < 64 && p.lim_out) {
+        // the frame's regions, for the x dilation and the merge: lanes 0..7
+        // of the first wavefront build one plane each; the camera position as
+        // the walk's (the same fp32 quotients)
+        const int k = (int)threadIdx.x;
+        const int planes = p.lim_fan ? (p.lim_img ? 8 : 4) : 0;
+        bool ok = true;
+        if (k < planes) {
+            const float o[3] = {p.tv[0] / p.s, p.tv[1] / p.s, p.tv[2] / p.s};
+            RowPlane q;
+            ok = make_region_plane(k, p.R, o, p.vd, p.hw, p.hh, p.lim_k[0], p.lim_k[1],
+                                   p.lim_k[2], p.lim_k[3], pl.r, pl.n[0], q);
+            (k < 4 ? p.lim_out->fan.p[k] : p.lim_out->img.p[k - 4]) = q;
+        }
+        const bool all = __all(ok);
+        if (k == 0) {
+            p.lim_out->has_fan = planes > 0 && all ? 1 : 0;
+            p.lim_out->has_img = planes == 8 && all ? 1 : 0;
+        }
+    }
     int32_t pp[3] = {0, 0, 0};
     const bool ok = seed_point(p, bx, by, pp);
     if (!pl.occb) {
@@ -234,47 +254,103 @@ __device__ __forceinline__ void seed_body(const SeedParams &p, int32_t bx, int32
         }
 }
 
-// Seeds -> bits dilated along x.  One lane per 32-voxel word of a padded row
-// inside the seed box; output voxel x is set iff a seed lies at padded
-// x .. x + 2r of the same padded row.
+// Bit j of the result set iff some bit j .. j + span - 1 of w is (span >= 1):
+// shift-or doublings up to the largest power of two p <= span, then one
+// shifted or for the rest.
+__device__ __forceinline__ uint64_t or_span(uint64_t w, int32_t span)
+{
+    int32_t p = 1;
+    while (2 * p <= span) {
+        w |= w >> p;
+        p *= 2;
+    }
+    return span > p ? (w | (w >> (span - p))) : w;
+}
+
+// Seeds -> bits dilated along x: output voxel x is set iff a seed lies at
+// padded x .. x + 2r of the same padded row, for the padded rows of the seed
+// box.  kWide (large launches): one lane per four 32-voxel output words (128
+// voxels), which reads the row's stamp bytes x0 .. x0 + 127 + 2r once
+// (16-byte loads, SWAR compares) unless the seed box or the image's region of
+// the row (grid coordinates = padded - r) leaves them out.  Otherwise one lane
+// per output word, reading x0 .. x0 + 63 (more lanes for small launches).
+template <bool kWide>
 __device__ __forceinline__ void dilate_x_body(const Planes &pl, int64_t gid)
 {
     const int32_t ny = pl.hi[1] - pl.lo[1] + 1;
     const int32_t nz = pl.hi[2] - pl.lo[2] + 1;
-    if (pl.lo[0] > pl.hi[0] || ny <= 0 || nz <= 0 || gid >= (int64_t)pl.wx * ny * nz)
+    if (!kWide) {
+        if (pl.lo[0] > pl.hi[0] || ny <= 0 || nz <= 0 || gid >= (int64_t)pl.wx * ny * nz)
+            return;
+        const uint32_t g32 = (uint32_t)gid, wx = (uint32_t)pl.wx;
+        const int32_t w = (int32_t)(g32 % wx);
+        const uint32_t row = g32 / wx;
+        const int32_t y = pl.lo[1] + (int32_t)(row % (uint32_t)ny);
+        const int32_t z = pl.lo[2] + (int32_t)(row / (uint32_t)ny);
+        const int32_t x0 = 32 * w;
+        uint32_t out = 0;
+        if (x0 <= pl.hi[0] && x0 + 31 + 2 * pl.r >= pl.lo[0]) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(
+                pl.seed + (int64_t)pl.seed_pitch * (y + (int64_t)pl.py * z) + x0);
+            const uint32_t rep = (pl.epoch & 0xFFu) * 0x01010101u;
+            uint32_t m[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint4 q = src[k];
+                m[k] = byte_eq_mask(q.x, rep) | (byte_eq_mask(q.y, rep) << 4) |
+                       (byte_eq_mask(q.z, rep) << 8) | (byte_eq_mask(q.w, rep) << 12);
+            }
+            const uint64_t w64 = (uint64_t)(m[0] | (m[1] << 16)) |
+                                 ((uint64_t)(m[2] | (m[3] << 16)) << 32);
+            out = (uint32_t)or_span(w64, 2 * pl.r + 1);
+            const int32_t valid = pl.n[0] - x0;   // output voxels of this word inside the grid
+            if (valid < 32)
+                out &= (1u << valid) - 1u;
+        }
+        pl.bitx[(int64_t)pl.wx * (y + (int64_t)pl.py * z) + w] = out;
         return;
-    // fewer words than a padded grid has bytes: 32-bit index arithmetic
-    const uint32_t g32 = (uint32_t)gid, wx = (uint32_t)pl.wx;
-    const int32_t w = (int32_t)(g32 % wx);
-    const uint32_t row = g32 / wx;
+    }
+    const int32_t lanes = dilate_x_lanes_per_row(pl.wx);
+    if (pl.lo[0] > pl.hi[0] || ny <= 0 || nz <= 0 || gid >= (int64_t)lanes * ny * nz)
+        return;
+    // fewer lanes than a padded grid has bytes: 32-bit index arithmetic
+    const uint32_t g32 = (uint32_t)gid;
+    const int32_t k = (int32_t)(g32 % (uint32_t)lanes);
+    const uint32_t row = g32 / (uint32_t)lanes;
     const int32_t y = pl.lo[1] + (int32_t)(row % (uint32_t)ny);
     const int32_t z = pl.lo[2] + (int32_t)(row / (uint32_t)ny);
-    const int32_t x0 = 32 * w;
-    uint32_t out = 0;
-    // read the seeds of padded columns x0 .. x0 + 31 + 2r only if the seed box
-    // and the image's region of this row (grid coordinates = padded - r) reach them
-    if (x0 <= pl.hi[0] && x0 + 31 + 2 * pl.r >= pl.lo[0] &&
-        row_run_seeded(pl.lim, y - pl.r, z - pl.r, x0 - pl.r, x0 + 31 + pl.r)) {
+    const int32_t x0 = 128 * k;
+    const int32_t words = min(4, pl.wx - 4 * k);           // output words of this lane
+    const int32_t need = 32 * words + 2 * pl.r;            // stamp bytes they read
+    uint32_t m[5] = {0u, 0u, 0u, 0u, 0u};                  // bit j: byte x0 + j is a seed
+    if (x0 <= pl.hi[0] && x0 + need - 1 >= pl.lo[0] &&
+        (!pl.lim || row_run_seeded(*pl.lim, y - pl.r, z - pl.r, x0 - pl.r, x0 + need - 1 - pl.r))) {
         const uint4 *src = reinterpret_cast<const uint4 *>(
             pl.seed + (int64_t)pl.seed_pitch * (y + (int64_t)pl.py * z) + x0);
         const uint32_t rep = (pl.epoch & 0xFFu) * 0x01010101u;
-        uint64_t m = 0;
+        uint4 q[10];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            uint4 q = src[k];
-            uint32_t b = byte_eq_mask(q.x, rep) | (byte_eq_mask(q.y, rep) << 4) |
-                         (byte_eq_mask(q.z, rep) << 8) | (byte_eq_mask(q.w, rep) << 12);
-            m |= (uint64_t)b << (16 * k);
+        for (int j = 0; j < 10; ++j)
+            q[j] = 16 * j < need ? src[j] : make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+        for (int j = 0; j < 10; ++j) {
+            const uint32_t b = byte_eq_mask(q[j].x, rep) | (byte_eq_mask(q[j].y, rep) << 4) |
+                               (byte_eq_mask(q[j].z, rep) << 8) | (byte_eq_mask(q[j].w, rep) << 12);
+            m[j >> 1] |= b << (16 * (j & 1));
         }
-        uint64_t acc = m;
-        for (int d = 1; d <= 2 * pl.r; ++d)
-            acc |= m >> d;
-        out = (uint32_t)acc;
-        const int32_t valid = pl.n[0] - x0;   // output voxels of this word inside the grid
-        if (valid < 32)
-            out &= (1u << valid) - 1u;
     }
-    pl.bitx[(int64_t)pl.wx * (y + (int64_t)pl.py * z) + w] = out;
+    uint32_t *dst = pl.bitx + (int64_t)pl.wx * (y + (int64_t)pl.py * z) + 4 * k;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        if (i >= words)
+            break;
+        uint32_t out =
+            (uint32_t)or_span(((uint64_t)m[i + 1] << 32) | (uint64_t)m[i], 2 * pl.r + 1);
+        const int32_t valid = pl.n[0] - (x0 + 32 * i);   // output voxels inside the grid
+        if (valid < 32)
+            out = valid > 0 ? out & ((1u << valid) - 1u) : 0u;
+        dst[i] = out;
+    }
 }
 
 // x-dilated rows -> occupied bit plane: OR over the (2r+1) x (2r+1) padded
@@ -302,19 +378,20 @@ __device__ __forceinline__ void dilate_yz_body(const Planes &pl, int64_t gid)
 }
 
 // The same dilation for one tile (tile_y, tile_z) of kBlock / kW rows along y
-// by kTileZ along z.  Thread = (word lane w, row slot); the padded rows the
-// tile reads are loaded once into LDS (rows outside the seed box as 0), ORed
-// along y into a second LDS buffer, then along z.  No divisions: rows are
-// walked by slot, words by lane.
-template <int kW>
+// by kTZ along z (vox_inf <= kTileMaxR).  Thread = (word lane w, row slot);
+// the padded rows the tile reads are loaded once into LDS (rows outside the
+// seed box as 0), ORed along y into a second LDS buffer, then along z.  No
+// divisions: rows are walked by slot, words by lane.
+template <int kW, int kTZ>
 __device__ __forceinline__ void dilate_yz_tile_body(const Planes &pl, int32_t tile_y,
                                                     int32_t tile_z, uint32_t *lds)
 {
     constexpr int32_t kTY = kBlock / kW;
+    constexpr int kTileMaxIz = kTZ + 2 * kTileMaxR;   // input z rows a tile may need
     const int32_t w = (int32_t)threadIdx.x % kW, slot = (int32_t)threadIdx.x / kW;
     const int32_t r2 = 2 * pl.r, wx = pl.wx;
-    const int32_t iy = kTY + r2, iz = kTileZ + r2;
-    const int32_t y0 = tile_y * kTY, z0 = tile_z * kTileZ;   // first output row = padded row
+    const int32_t iy = kTY + r2, iz = kTZ + r2;
+    const int32_t y0 = tile_y * kTY, z0 = tile_z * kTZ;   // first output row = padded row
     uint32_t *in = lds;                   // [iz][iy][kW]
     uint32_t *yd = lds + iz * iy * kW;    // [iz][kTY][kW]
     const bool any = pl.lo[0] <= pl.hi[0];
@@ -355,7 +432,7 @@ __device__ __forceinline__ void dilate_yz_tile_body(const Planes &pl, int32_t ti
     const int32_t gy = y0 + slot;
     if (!lane || gy >= pl.n[1])
         return;
-    for (int32_t z = 0; z < kTileZ; ++z) {
+    for (int32_t z = 0; z < kTZ; ++z) {
         const int32_t gz = z0 + z;
         if (gz >= pl.n[2])
             break;
@@ -397,13 +474,6 @@ __device__ __forceinline__ int32_t wrap_add(int32_t v, int32_t r, int32_t n)
     return s >= n ? s - n : s;
 }
 
-// Bit j (j < 16) set iff byte j of q equals the byte replicated in rep.
-__device__ __forceinline__ uint32_t byte_eq_mask16(const uint4 &q, uint32_t rep)
-{
-    return byte_eq_mask(q.x, rep) | (byte_eq_mask(q.y, rep) << 4) |
-           (byte_eq_mask(q.z, rep) << 8) | (byte_eq_mask(q.w, rep) << 12);
-}
-
 // The 16 bytes at any byte address p: five aligned dword loads from p
 // rounded down to 4 (so up to 4 bytes past p + 16 are read), realigned with
 // v_alignbyte.
@@ -422,15 +492,54 @@ __device__ __forceinline__ uint4 load16_unaligned(const uint8_t *p)
                       __builtin_amdgcn_alignbyte(v[4], v[3], sh));
 }
 
-// Masks of 16 grid columns of one plane row (bit j: column x0 + j, wrapping
-// at the grid's width; nvalid columns): the frame's occupied voxels, traced
-// stamps and free stamps.  The columns' bytes are one aligned 16-byte run,
-// one unaligned run (aligned dwords + v_alignbyte), or a run that wraps (per
-// byte); the stamps are compared once, after the loads.
+// 0xFF in each byte of w that equals the byte replicated in rep, 0 in the
+// others (SWAR: no carry crosses a byte).
+__device__ __forceinline__ uint32_t byte_eq_ff(uint32_t w, uint32_t rep)
+{
+    const uint32_t x = w ^ rep;
+    const uint32_t y = ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x;   // bit 7 set in non-zero bytes
+    return ((~y >> 7) & 0x01010101u) * 0xFFu;
+}
+
+__device__ __forceinline__ uint4 byte_eq_ff16(const uint4 &q, uint32_t rep)
+{
+    return make_uint4(byte_eq_ff(q.x, rep), byte_eq_ff(q.y, rep), byte_eq_ff(q.z, rep),
+                      byte_eq_ff(q.w, rep));
+}
+
+// 0xFF in byte j (j < 4) of the result iff bit j of b is set.
+__device__ __forceinline__ uint32_t spread4(uint32_t b)
+{
+    return ((b & 0xFu) * 0x00204081u & 0x01010101u) * 0xFFu;
+}
+
+__device__ __forceinline__ uint4 spread16(uint32_t b)
+{
+    return make_uint4(spread4(b), spread4(b >> 4), spread4(b >> 8), spread4(b >> 12));
+}
+
+// A frame's states of 16 consecutive voxels as byte masks (0xFF in byte j
+// iff voxel j is): occupied, traced, free.
+struct Masks16 {
+    uint4 o, t, f;
+};
+
+__device__ __forceinline__ bool any16(const Masks16 &m)
+{
+    return ((m.o.x | m.o.y | m.o.z | m.o.w) | (m.t.x | m.t.y | m.t.z | m.t.w) |
+            (m.f.x | m.f.y | m.f.z | m.f.w)) != 0u;
+}
+
+// The frame's states of 16 grid columns of one plane row: columns x0 .. x0 +
+// 15, wrapping at the grid's width, of which the first nvalid are grid
+// columns.  The bytes are one aligned 16-byte run, one unaligned run (aligned
+// dwords + v_alignbyte), or a run that wraps (per byte, zero past nvalid).
+// The stamps are compared once, after the loads.  A plane byte or bit of a
+// column past the grid's width never holds the frame's stamp or bit (the
+// passes write grid voxels only), so no column mask is needed.
 template <bool kBytes>
 __device__ __forceinline__ void gather16(const Planes &pl, int64_t prow, int32_t x0,
-                                         int32_t nvalid, uint32_t &occ16, uint32_t &tr16,
-                                         uint32_t &fr16)
+                                         int32_t nvalid, Masks16 &m)
 {
     const int32_t gx = pl.n[0];
     const uint32_t rep = (pl.epoch & 0xFFu) * 0x01010101u;
@@ -477,90 +586,140 @@ __device__ __forceinline__ void gather16(const Planes &pl, int64_t prow, int32_t
         tr = make_uint4(t[0], t[1], t[2], t[3]);
         oc = make_uint4(o[0], o[1], o[2], o[3]);
     }
-    const uint32_t valid = nvalid >= 16 ? 0xFFFFu : (1u << nvalid) - 1u;
-    occ16 = (kBytes ? byte_eq_mask16(oc, rep) : obits) & valid;
-    tr16 = byte_eq_mask16(tr, rep) & valid;
-    fr16 = byte_eq_mask16(fr, rep) & valid;
+    m.o = kBytes ? byte_eq_ff16(oc, rep) : spread16(obits);
+    m.t = byte_eq_ff16(tr, rep);
+    m.f = byte_eq_ff16(fr, rep);
 }
 
-// 16 voxels of the local grid: the columns of clr16 become unknown (a
-// shift's clear), then Alg. 3 -- an occupied voxel becomes occupied, else a
-// traced one unknown, else a free one free; the others keep their value.
-__device__ __forceinline__ void apply16(uint4 &v, uint32_t clr16, uint32_t occ16, uint32_t tr16,
-                                        uint32_t fr16)
+// Four voxels of the local grid: the bytes of cm become unknown (a shift's
+// clear), then Alg. 3 -- an occupied voxel becomes occupied, else a traced
+// one unknown, else a free one free; the others keep their value.
+__device__ __forceinline__ uint32_t merge4(uint32_t v, uint32_t cm, uint32_t om, uint32_t tm,
+                                          uint32_t fm)
 {
-    uint32_t *vw = reinterpret_cast<uint32_t *>(&v);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        // spread 4 mask bits to 4 byte masks
-        uint32_t cm = (((clr16 >> (4 * j)) & 0xFu) * 0x00204081u & 0x01010101u) * 0xFFu;
-        uint32_t om = (((occ16 >> (4 * j)) & 0xFu) * 0x00204081u & 0x01010101u) * 0xFFu;
-        uint32_t tm = (((tr16 >> (4 * j)) & 0xFu) * 0x00204081u & 0x01010101u) * 0xFFu;
-        uint32_t fm = (((fr16 >> (4 * j)) & 0xFu) * 0x00204081u & 0x01010101u) * 0xFFu;
-        tm &= ~om;
-        fm &= ~(om | tm);
-        vw[j] = (vw[j] & ~(cm | om | tm | fm)) | (0x02020202u & om) | (0x01010101u & fm);
-    }
+    tm &= ~om;
+    fm &= ~(om | tm);
+    return (v & ~(cm | om | tm | fm)) | (0x02020202u & om) | (0x01010101u & fm);
+}
+
+__device__ __forceinline__ void apply16(uint4 &v, const uint4 &cm, const Masks16 &m)
+{
+    v.x = merge4(v.x, cm.x, m.o.x, m.t.x, m.f.x);
+    v.y = merge4(v.y, cm.y, m.o.y, m.t.y, m.f.y);
+    v.z = merge4(v.z, cm.z, m.o.z, m.t.z, m.f.z);
+    v.w = merge4(v.w, cm.w, m.o.w, m.t.w, m.f.w);
 }
 
 // Whether the frame may change one of the nvalid grid columns x0 .. (wrapping
-// at gx) of grid row (y, z): outside the frame's regions (vg_frustum.h) its
-// planes hold no mark and no occupied voxel, and the merge reads nothing.
-__device__ __forceinline__ bool chunk_touched(const Planes &pl, int32_t y, int32_t z, int32_t x0,
-                                              int32_t nvalid)
+// at gx) given its runs of the row (bounded false: every column).
+__device__ __forceinline__ bool run_touched(bool bounded, const int32_t run[4], int32_t gx,
+                                            int32_t x0, int32_t nvalid)
 {
-    const int32_t gx = pl.n[0], e = x0 + nvalid - 1;
-    int32_t run[4];
-    if (!row_runs(pl.lim, y, z, gx, run))
+    if (!bounded)
         return true;
+    const int32_t e = x0 + nvalid - 1;
     if (e < gx)
         return runs_meet(run, x0, e);
     return runs_meet(run, x0, gx - 1) || runs_meet(run, 0, e - gx);
 }
 
-// Alg. 3: the frame's marks merged into the local grid.  One lane per 16
-// buffer columns of the buffer row that holds a grid row of the row box:
-// occupied bit -> occupied; else a traced stamp -> unknown; else a free stamp
-// -> free; else unchanged.  The frame's planes are read at the grid columns
-// the 16 buffer columns hold (one run, or two where the ring wraps).
-template <bool kBytes>
+// Alg. 3: the frame's marks merged into the local grid, over the buffer rows
+// that hold the grid rows of the row box: occupied bit -> occupied; else a
+// traced stamp -> unknown; else a free stamp -> free; else unchanged.  The
+// frame's planes are read at the grid columns each 16-column chunk holds (one
+// run, or two where the ring wraps).  kWide (large launches): one lane per 64
+// buffer columns (four chunks); only chunks within the frame's runs of the
+// row (vg_frustum.h) are read, and every gather is issued before the local
+// grid is read and written.  Otherwise one lane per chunk (more lanes for
+// small launches).
+template <bool kBytes, bool kWide>
 __device__ __forceinline__ void resolve_body(const Planes &pl, uint8_t *loc, const RowBox &rows,
                                              const int32_t ring[3], int64_t gid)
 {
     const int32_t ny = rows.y1 - rows.y0 + 1, nz = rows.z1 - rows.z0 + 1;
-    const int32_t chunks = pl.wx * 2;   // 16-column chunks per row
-    if (ny <= 0 || nz <= 0 || gid >= (int64_t)chunks * ny * nz)
+    const int32_t gx = pl.n[0];
+    if (!kWide) {
+        const int32_t chunks = pl.wx * 2;   // 16-column chunks per row
+        if (ny <= 0 || nz <= 0 || gid >= (int64_t)chunks * ny * nz)
+            return;
+        const uint32_t g32 = (uint32_t)gid;   // < 2^26 chunks in a grid
+        const int32_t k = (int32_t)(g32 % (uint32_t)chunks);
+        const uint32_t row = g32 / (uint32_t)chunks;
+        const int32_t y = rows.y0 + (int32_t)(row % (uint32_t)ny);
+        const int32_t z = rows.z0 + (int32_t)(row / (uint32_t)ny);
+        const int32_t c0 = 16 * k;   // buffer column of the chunk
+        if (c0 >= gx)
+            return;                  // row padding only
+        const int32_t nvalid = min(16, gx - c0);
+        const int32_t by = wrap_add(y, ring[1], pl.n[1]), bz = wrap_add(z, ring[2], pl.n[2]);
+        const int64_t prow = 32 * (int64_t)pl.wx * (y + (int64_t)pl.n[1] * z);
+        const int64_t brow = 32 * (int64_t)pl.wx * (by + (int64_t)pl.n[1] * bz);
+        int32_t x0 = c0 - ring[0];   // grid column of buffer column c0
+        if (x0 < 0)
+            x0 += gx;
+        Masks16 mk;
+        gather16<kBytes>(pl, prow, x0, nvalid, mk);
+        if (!any16(mk))
+            return;
+        uint8_t *dst = loc + brow + c0;
+        uint4 v = *reinterpret_cast<const uint4 *>(dst);
+        apply16(v, make_uint4(0u, 0u, 0u, 0u), mk);
+        *reinterpret_cast<uint4 *>(dst) = v;
         return;
-    const uint32_t g32 = (uint32_t)gid;   // < 2^26 chunks in a grid
-    const int32_t k = (int32_t)(g32 % (uint32_t)chunks);
-    const uint32_t row = g32 / (uint32_t)chunks;
+    }
+    const int32_t lanes = merge_lanes_per_row(gx);
+    if (ny <= 0 || nz <= 0 || gid >= (int64_t)lanes * ny * nz)
+        return;
+    const uint32_t g32 = (uint32_t)gid;   // < 2^26 lanes in a grid
+    const int32_t k = (int32_t)(g32 % (uint32_t)lanes);
+    const uint32_t row = g32 / (uint32_t)lanes;
     const int32_t y = rows.y0 + (int32_t)(row % (uint32_t)ny);
     const int32_t z = rows.z0 + (int32_t)(row / (uint32_t)ny);
-    const int32_t gx = pl.n[0];
-    const int32_t c0 = 16 * k;               // buffer column of the chunk
-    if (c0 >= gx)
-        return;                              // row padding only
-    const int32_t nvalid = min(16, gx - c0);
     const int32_t by = wrap_add(y, ring[1], pl.n[1]), bz = wrap_add(z, ring[2], pl.n[2]);
     const int64_t prow = 32 * (int64_t)pl.wx * (y + (int64_t)pl.n[1] * z);    // planes
     const int64_t brow = 32 * (int64_t)pl.wx * (by + (int64_t)pl.n[1] * bz);  // buffer
-    int32_t x0 = c0 - ring[0];               // grid column of buffer column c0
-    if (x0 < 0)
-        x0 += gx;
-    if (!chunk_touched(pl, y, z, x0, nvalid))
-        return;
-    uint32_t occ16, tr16, fr16;
-    gather16<kBytes>(pl, prow, x0, nvalid, occ16, tr16, fr16);
-    if ((occ16 | tr16 | fr16) == 0)
-        return;
-    uint8_t *dst = loc + brow + c0;
-    uint4 v = *reinterpret_cast<const uint4 *>(dst);
-    apply16(v, 0u, occ16, tr16, fr16);
-    *reinterpret_cast<uint4 *>(dst) = v;
+    int32_t run[4];
+    const bool bounded = pl.lim && row_runs(*pl.lim, y, z, gx, run);
+    // chunks within the runs: their planes and the local grid's 16 voxels
+    // are loaded together (the runs are tight, so nearly all of them change)
+    Masks16 mk[4];
+    uint4 v[4];
+    bool in[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        in[s] = false;
+        const int32_t c0 = 64 * k + 16 * s;   // buffer column of the chunk
+        if (c0 >= gx)
+            continue;                          // row padding only
+        const int32_t nvalid = min(16, gx - c0);
+        int32_t x0 = c0 - ring[0];             // grid column of buffer column c0
+        if (x0 < 0)
+            x0 += gx;
+        if (run_touched(bounded, run, gx, x0, nvalid)) {
+            in[s] = true;
+            gather16<kBytes>(pl, prow, x0, nvalid, mk[s]);
+            v[s] = *reinterpret_cast<const uint4 *>(loc + brow + c0);
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+        if (in[s] && any16(mk[s])) {
+            apply16(v[s], make_uint4(0u, 0u, 0u, 0u), mk[s]);
+            *reinterpret_cast<uint4 *>(loc + brow + 64 * k + 16 * s) = v[s];
+        }
+}
+
+// Bits a .. b - 1 of a 16-bit mask, clamped to 0 .. 16.
+__device__ __forceinline__ uint32_t range_mask16(int32_t a, int32_t b)
+{
+    a = max(a, 0);
+    b = min(b, 16);
+    return a < b ? ((1u << b) - 1u) & ~((1u << a) - 1u) : 0u;
 }
 
 // Columns of 16 grid columns (x0 .. , wrapping; nvalid of them) in row (y, z)
 // that a frame's shift clears (clear_body's rule); none if it does not shift.
+// Column j holds grid column x0 + j, or x0 + j - gx past the seam.
 __device__ __forceinline__ uint32_t clear_mask16(const SlabClear &c, int32_t y, int32_t z,
                                                  int32_t x0, int32_t nvalid)
 {
@@ -572,15 +731,10 @@ __device__ __forceinline__ uint32_t clear_mask16(const SlabClear &c, int32_t y, 
         return valid;
     if (c.lo[0] >= c.hi[0])
         return 0u;
-    uint32_t m = 0;
-    for (int j = 0; j < nvalid; ++j) {
-        int32_t x = x0 + j;
-        if (x >= c.n[0])
-            x -= c.n[0];
-        if (x >= c.lo[0] && x < c.hi[0])
-            m |= 1u << j;
-    }
-    return m;
+    // j with x0 + j in [lo, hi), and past the seam j with x0 + j - gx in it
+    const uint32_t m = range_mask16(c.lo[0] - x0, c.hi[0] - x0) |
+                       range_mask16(c.lo[0] - x0 + c.n[0], c.hi[0] - x0 + c.n[0]);
+    return m & valid;
 }
 
 // Alg. 3 for a run of consecutive frames of one grid (fd[0 .. group), in
@@ -590,10 +744,11 @@ __device__ __forceinline__ uint32_t clear_mask16(const SlabClear &c, int32_t y, 
 // its marks, so the latest frame that saw the voxel decides.  The shifts'
 // clears have already run over the whole grid (the batch's shift stage);
 // here they are applied again in order, so that they also undo the marks of
-// earlier frames of the run.  One lane per 16 buffer columns of a buffer row
-// that holds a grid row (in the coordinates of the run's last frame) of the
-// merge's domain; each frame's planes are read at its own grid coordinates of
-// those voxels, where its row box holds them.
+// earlier frames of the run.  One lane per 64 buffer columns (four 16-column
+// chunks) of a buffer row that holds a grid row (in the coordinates of the
+// run's last frame) of the merge's domain; each frame's planes are read at
+// its own grid coordinates of those voxels, where its row box and its runs
+// of the row hold them.
 __device__ __forceinline__ void resolve_seq_body(const FrameDesc *fd, int64_t gid)
 {
     const FrameDesc &f0 = fd[0];
@@ -601,73 +756,106 @@ __device__ __forceinline__ void resolve_seq_body(const FrameDesc *fd, int64_t gi
     const RowBox &dom = f0.dom;
     const Planes &pl0 = f0.sp.pl;
     const int32_t ny = dom.y1 - dom.y0 + 1, nz = dom.z1 - dom.z0 + 1;
-    const int32_t chunks = pl0.wx * 2;
-    if (m <= 0 || ny <= 0 || nz <= 0 || gid >= (int64_t)chunks * ny * nz)
-        return;
-    const uint32_t g32 = (uint32_t)gid;   // < 2^26 chunks in a grid
-    const int32_t k = (int32_t)(g32 % (uint32_t)chunks);
-    const uint32_t row = g32 / (uint32_t)chunks;
     const int32_t gx = pl0.n[0], gy = pl0.n[1], gz = pl0.n[2];
-    const int32_t c0 = 16 * k;
-    if (c0 >= gx)
+    const int32_t lanes = merge_lanes_per_row(gx);
+    if (m <= 0 || ny <= 0 || nz <= 0 || gid >= (int64_t)lanes * ny * nz)
         return;
-    const int32_t nvalid = min(16, gx - c0);
+    const uint32_t g32 = (uint32_t)gid;   // < 2^26 lanes in a grid
+    const int32_t k = (int32_t)(g32 % (uint32_t)lanes);
+    const uint32_t row = g32 / (uint32_t)lanes;
     const FrameDesc &fl = fd[m - 1];
     const int32_t by = wrap_add(dom.y0 + (int32_t)(row % (uint32_t)ny), fl.ring[1], gy);
     const int32_t bz = wrap_add(dom.z0 + (int32_t)(row / (uint32_t)ny), fl.ring[2], gz);
-    uint8_t *dst = f0.loc + 32 * (int64_t)pl0.wx * (by + (int64_t)gy * bz) + c0;
-    uint4 v = make_uint4(0u, 0u, 0u, 0u);
-    bool loaded = false;
+    uint8_t *dst = f0.loc + 32 * (int64_t)pl0.wx * (by + (int64_t)gy * bz) + 64 * k;
+    uint4 v[4];
+    uint32_t loaded = 0;   // bit s: v[s] holds the grid's 16 voxels of chunk s
     for (int32_t j = 0; j < m; ++j) {
         const FrameDesc &f = fd[j];
-        int32_t y = by - f.ring[1], z = bz - f.ring[2], x0 = c0 - f.ring[0];
+        int32_t y = by - f.ring[1], z = bz - f.ring[2];
         if (y < 0)
             y += gy;
         if (z < 0)
             z += gz;
-        if (x0 < 0)
-            x0 += gx;
-        const uint32_t clr16 = clear_mask16(f.clear, y, z, x0, nvalid);
-        uint32_t occ16 = 0, tr16 = 0, fr16 = 0;
-        if (y >= f.rows.y0 && y <= f.rows.y1 && z >= f.rows.z0 && z <= f.rows.z1 &&
-            chunk_touched(f.sp.pl, y, z, x0, nvalid))
-            gather16<false>(f.sp.pl, 32 * (int64_t)pl0.wx * (y + (int64_t)gy * z), x0, nvalid,
-                            occ16, tr16, fr16);
-        if ((clr16 | occ16 | tr16 | fr16) == 0)
-            continue;
-        if (!loaded) {
-            v = *reinterpret_cast<const uint4 *>(dst);
-            loaded = true;
+        const bool in_rows = y >= f.rows.y0 && y <= f.rows.y1 && z >= f.rows.z0 && z <= f.rows.z1;
+        int32_t run[4];
+        const bool bounded = in_rows && f.sp.pl.lim && row_runs(*f.sp.pl.lim, y, z, gx, run);
+        const int64_t prow = 32 * (int64_t)pl0.wx * (y + (int64_t)gy * z);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int32_t c0 = 64 * k + 16 * s;
+            if (c0 >= gx)
+                continue;
+            const int32_t nvalid = min(16, gx - c0);
+            int32_t x0 = c0 - f.ring[0];
+            if (x0 < 0)
+                x0 += gx;
+            const uint32_t cm = clear_mask16(f.clear, y, z, x0, nvalid);
+            Masks16 mk = {make_uint4(0u, 0u, 0u, 0u), make_uint4(0u, 0u, 0u, 0u),
+                          make_uint4(0u, 0u, 0u, 0u)};
+            bool any = false;
+            if (in_rows && run_touched(bounded, run, gx, x0, nvalid)) {
+                gather16<false>(f.sp.pl, prow, x0, nvalid, mk);
+                any = any16(mk);
+            }
+            if (cm == 0u && !any)
+                continue;
+            if (!((loaded >> s) & 1u)) {
+                v[s] = *reinterpret_cast<const uint4 *>(dst + 16 * s);
+                loaded |= 1u << s;
+            }
+            apply16(v[s], spread16(cm), mk);
         }
-        apply16(v, clr16, occ16, tr16, fr16);
     }
-    if (loaded)
-        *reinterpret_cast<uint4 *>(dst) = v;
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+        if ((loaded >> s) & 1u)
+            *reinterpret_cast<uint4 *>(dst + 16 * s) = v[s];
 }
 
-// Sec. IV-E on the ring buffer: one lane per 16 buffer columns of a grid
-// row.  Rows of an exposed y or z slab (every row when the x slab is the
-// whole row) are cleared whole; other rows clear the buffer columns that hold
-// grid columns of the exposed x slab.
+// Sec. IV-E on the ring buffer: the voxels of the exposed slabs become
+// unknown, 16 buffer columns per lane (the lane parts of SlabClear).  Part A
+// clears, in every grid row, the buffer columns of its chunks that hold grid
+// columns of the exposed x slab; parts B and C clear whole rows of the
+// exposed y and z slabs (16-byte stores).  Lanes of different parts may
+// clear the same voxel; every store writes unknown.
 __device__ __forceinline__ void clear_body(const SlabClear &c, int64_t gid)
 {
-    const int32_t cpr = c.gxp >> 4;
-    if (gid >= (int64_t)cpr * c.n[1] * c.n[2])
+    const int32_t cpr = c.gxp >> 4;   // 16-column chunks per buffer row
+    int32_t y, z, chunk;
+    bool whole;
+    if (gid < c.lanes[0]) {
+        const int32_t na = c.xrun[1] - c.xrun[0];
+        const int32_t per = na + (c.xrun[3] - c.xrun[2]);
+        const uint32_t g32 = (uint32_t)gid, row = g32 / (uint32_t)per;
+        const int32_t j = (int32_t)(g32 - row * (uint32_t)per);
+        chunk = j < na ? c.xrun[0] + j : c.xrun[2] + (j - na);
+        y = (int32_t)(row % (uint32_t)c.n[1]);
+        z = (int32_t)(row / (uint32_t)c.n[1]);
+        whole = c.hi[0] - c.lo[0] >= c.n[0];
+    } else if (gid < c.lanes[0] + c.lanes[1]) {
+        const uint32_t g32 = (uint32_t)(gid - c.lanes[0]), row = g32 / (uint32_t)cpr;
+        chunk = (int32_t)(g32 - row * (uint32_t)cpr);
+        const int32_t ny = c.hi[1] - c.lo[1];
+        y = c.lo[1] + (int32_t)(row % (uint32_t)ny);
+        z = (int32_t)(row / (uint32_t)ny);
+        whole = true;
+    } else if (gid < c.lanes[0] + c.lanes[1] + c.lanes[2]) {
+        const uint32_t g32 = (uint32_t)(gid - c.lanes[0] - c.lanes[1]);
+        const uint32_t row = g32 / (uint32_t)cpr;
+        chunk = (int32_t)(g32 - row * (uint32_t)cpr);
+        y = (int32_t)(row % (uint32_t)c.n[1]);
+        z = c.lo[2] + (int32_t)(row / (uint32_t)c.n[1]);
+        whole = true;
+    } else {
         return;
-    const uint32_t g32 = (uint32_t)gid;   // < 2^26 chunks in a grid
-    const uint32_t row = g32 / (uint32_t)cpr;
-    const int32_t c0 = 16 * (int32_t)(g32 - row * (uint32_t)cpr);
-    const int32_t y = (int32_t)(row % (uint32_t)c.n[1]), z = (int32_t)(row / (uint32_t)c.n[1]);
+    }
+    const int32_t c0 = 16 * chunk;
     const int32_t by = wrap_add(y, c.ring[1], c.n[1]), bz = wrap_add(z, c.ring[2], c.n[2]);
     uint8_t *dst = c.loc + (int64_t)c.gxp * (by + (int64_t)c.n[1] * bz) + c0;
-    const bool whole = (y >= c.lo[1] && y < c.hi[1]) || (z >= c.lo[2] && z < c.hi[2]) ||
-                       c.hi[0] - c.lo[0] >= c.n[0];
     if (whole) {
         *reinterpret_cast<uint4 *>(dst) = make_uint4(0u, 0u, 0u, 0u);
         return;
     }
-    if (c.lo[0] >= c.hi[0])
-        return;
     for (int j = 0; j < 16; ++j) {
         const int32_t col = c0 + j;
         if (col >= c.n[0])
@@ -687,9 +875,10 @@ __global__ __launch_bounds__(kBlock) void k_seed(SeedParams p)
     seed_body(p, blockIdx.x, blockIdx.y);
 }
 
+template <bool kWide>
 __global__ __launch_bounds__(kBlock) void k_dilate_x(Planes pl)
 {
-    dilate_x_body(pl, (int64_t)blockIdx.x * kBlock + threadIdx.x);
+    dilate_x_body<kWide>(pl, (int64_t)blockIdx.x * kBlock + threadIdx.x);
 }
 
 __global__ __launch_bounds__(kBlock) void k_dilate_yz(Planes pl)
@@ -697,11 +886,11 @@ __global__ __launch_bounds__(kBlock) void k_dilate_yz(Planes pl)
     dilate_yz_body(pl, (int64_t)blockIdx.x * kBlock + threadIdx.x);
 }
 
-template <int kW>
+template <int kW, int kTZ>
 __global__ __launch_bounds__(kBlock) void k_dilate_yz_tile(Planes pl)
 {
     extern __shared__ uint32_t lds[];
-    dilate_yz_tile_body<kW>(pl, blockIdx.x, blockIdx.y, lds);
+    dilate_yz_tile_body<kW, kTZ>(pl, blockIdx.x, blockIdx.y, lds);
 }
 
 // The walk; workgroups from ray_blocks on run the slab clear c instead (the
@@ -727,12 +916,12 @@ __global__ __launch_bounds__(kBlock) void k_rays(RayParams p, SlabClear c, int32
     rays_body<kGeneral, kBytes, kLone>(p, rb * (kBlock / 64) + (threadIdx.x >> 6));
 }
 
-template <bool kBytes>
+template <bool kBytes, bool kWide>
 __global__ __launch_bounds__(kBlock) void k_resolve(Planes pl, uint8_t *loc, RowBox rows,
                                                     int32_t rx, int32_t ry, int32_t rz)
 {
     const int32_t ring[3] = {rx, ry, rz};
-    resolve_body<kBytes>(pl, loc, rows, ring, (int64_t)blockIdx.x * kBlock + threadIdx.x);
+    resolve_body<kBytes, kWide>(pl, loc, rows, ring, (int64_t)blockIdx.x * kBlock + threadIdx.x);
 }
 
 __global__ __launch_bounds__(kBlock) void k_clear(SlabClear c)
@@ -786,12 +975,13 @@ __global__ __launch_bounds__(kBlock) void kb_seed(const FrameDesc *__restrict__ 
         seed_body(f.sp, local, 0);
 }
 
+template <bool kWide>
 __global__ __launch_bounds__(kBlock) void kb_dilate_x(const FrameDesc *__restrict__ fd,
                                                       const int32_t *__restrict__ start, int32_t n)
 {
     int32_t local;
     const FrameDesc &f = fd[frame_of(start, n, blockIdx.x, local)];
-    dilate_x_body(f.sp.pl, (int64_t)local * kBlock + threadIdx.x);
+    dilate_x_body<kWide>(f.sp.pl, (int64_t)local * kBlock + threadIdx.x);
 }
 
 __global__ __launch_bounds__(kBlock) void kb_dilate_yz(const FrameDesc *__restrict__ fd,
@@ -803,7 +993,7 @@ __global__ __launch_bounds__(kBlock) void kb_dilate_yz(const FrameDesc *__restri
     dilate_yz_body(f.sp.pl, (int64_t)local * kBlock + threadIdx.x);
 }
 
-template <int kW>
+template <int kW, int kTZ>
 __global__ __launch_bounds__(kBlock) void kb_dilate_yz_tile(const FrameDesc *__restrict__ fd,
                                                             const int32_t *__restrict__ start,
                                                             int32_t n)
@@ -813,7 +1003,7 @@ __global__ __launch_bounds__(kBlock) void kb_dilate_yz_tile(const FrameDesc *__r
     const FrameDesc &f = fd[frame_of(start, n, blockIdx.x, local)];
     constexpr int32_t kTY = kBlock / kW;
     const int32_t tiles_y = (f.sp.pl.n[1] + kTY - 1) / kTY;
-    dilate_yz_tile_body<kW>(f.sp.pl, local % tiles_y, local / tiles_y, lds);
+    dilate_yz_tile_body<kW, kTZ>(f.sp.pl, local % tiles_y, local / tiles_y, lds);
 }
 
 __global__ __launch_bounds__(kBlock) void kb_rays(const FrameDesc *__restrict__ fd,
@@ -828,12 +1018,14 @@ __global__ __launch_bounds__(kBlock) void kb_rays(const FrameDesc *__restrict__ 
         rays_body<true, false, false>(f.rp, tile);
 }
 
+template <bool kWide>
 __global__ __launch_bounds__(kBlock) void kb_resolve(const FrameDesc *__restrict__ fd,
                                                      const int32_t *__restrict__ start, int32_t n)
 {
     int32_t local;
     const FrameDesc &f = fd[frame_of(start, n, blockIdx.x, local)];
-    resolve_body<false>(f.sp.pl, f.loc, f.rows, f.ring, (int64_t)local * kBlock + threadIdx.x);
+    resolve_body<false, kWide>(f.sp.pl, f.loc, f.rows, f.ring,
+                               (int64_t)local * kBlock + threadIdx.x);
 }
 
 // The merge of a round that holds runs of frames of one grid: a block finds
@@ -890,26 +1082,29 @@ hipError_t launch_dilate(const Planes &pl, hipStream_t st, const StageEvents &ev
     const bool any = pl.lo[0] <= pl.hi[0] && pl.lo[1] <= pl.hi[1] && pl.lo[2] <= pl.hi[2];
     hipEvent_t start = ev.start;
     if (any) {
-        int64_t n = (int64_t)pl.wx * (pl.hi[1] - pl.lo[1] + 1) * (pl.hi[2] - pl.lo[2] + 1);
-        hipExtLaunchKernelGGL(k_dilate_x, dim3(blocks_for(n)), dim3(kBlock), 0, st, start,
+        const int64_t rows = (int64_t)(pl.hi[1] - pl.lo[1] + 1) * (pl.hi[2] - pl.lo[2] + 1);
+        const bool wide = dilate_x_wide((int64_t)pl.wx * rows);
+        const int64_t n = (int64_t)dilate_x_lanes(pl.wx, wide) * rows;
+        hipExtLaunchKernelGGL(wide ? k_dilate_x<true> : k_dilate_x<false>, dim3(blocks_for(n)),
+                              dim3(kBlock), 0, st, start,
                               (hipEvent_t) nullptr, 0, pl);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
         start = nullptr;
     }
-    const int kw = dilate_tile_width(pl);
-    if (kw > 0) {
-        const uint32_t lds = (uint32_t)dilate_tile_lds(pl, kw);
-        const int32_t ty = kBlock / kw;
+    // 8-deep tiles where there are enough of them to fill the chip, else 2-deep
+    YzTile t{dilate_tile_width(pl, kTileDeep), kTileDeep};
+    if (t.kw == 0 || dilate_tiles(pl, t) < kDeepTileMin)
+        t = YzTile{dilate_tile_width(pl, 2), 2};
+    if (t.kw > 0) {
+        const uint32_t lds = (uint32_t)dilate_tile_lds(pl, t);
+        const int32_t ty = kBlock / t.kw;
         const dim3 tiles((uint32_t)((pl.n[1] + ty - 1) / ty),
-                         (uint32_t)((pl.n[2] + kTileZ - 1) / kTileZ));
-        if (kw == 8)
-            hipExtLaunchKernelGGL(k_dilate_yz_tile<8>, tiles, dim3(kBlock), lds, st, start,
-                                  ev.stop, 0, pl);
-        else
-            hipExtLaunchKernelGGL(k_dilate_yz_tile<16>, tiles, dim3(kBlock), lds, st, start,
-                                  ev.stop, 0, pl);
+                         (uint32_t)((pl.n[2] + t.tz - 1) / t.tz));
+        auto kern = t.kw == 8 ? (t.tz == 2 ? k_dilate_yz_tile<8, 2> : k_dilate_yz_tile<8, 8>)
+                              : (t.tz == 2 ? k_dilate_yz_tile<16, 2> : k_dilate_yz_tile<16, 8>);
+        hipExtLaunchKernelGGL(kern, tiles, dim3(kBlock), lds, st, start, ev.stop, 0, pl);
         return hipGetLastError();
     }
     int64_t n = (int64_t)pl.wx * pl.n[1] * pl.n[2];
@@ -927,7 +1122,7 @@ hipError_t launch_rays(const RayParams &p, bool camera_inside, hipStream_t st,
     int64_t clear_blocks = 0;
     if (clear) {
         c = *clear;
-        clear_blocks = blocks_for((int64_t)(c.gxp / 16) * c.n[1] * c.n[2]);
+        clear_blocks = blocks_for(clear_lanes(c));
     }
     const uint32_t blocks = (uint32_t)(ray_blocks + clear_blocks);
     if (blocks == 0)
@@ -955,19 +1150,20 @@ hipError_t launch_resolve(const Planes &pl, uint8_t *loc, const RowBox &rows,
     if (rows.y0 > rows.y1 || rows.z0 > rows.z1)
         return record_empty_stage(ev, st);
     const int32_t ny = rows.y1 - rows.y0 + 1, nz = rows.z1 - rows.z0 + 1;
-    int64_t n = (int64_t)pl.wx * 2 * ny * nz;
-    if (pl.occb)
-        hipExtLaunchKernelGGL(k_resolve<true>, dim3(blocks_for(n)), dim3(kBlock), 0, st, ev.start,
-                              ev.stop, 0, pl, loc, rows, ring[0], ring[1], ring[2]);
-    else
-        hipExtLaunchKernelGGL(k_resolve<false>, dim3(blocks_for(n)), dim3(kBlock), 0, st, ev.start,
-                              ev.stop, 0, pl, loc, rows, ring[0], ring[1], ring[2]);
+    const bool wide = merge_wide(pl.n[0], (int64_t)ny * nz);
+    const int64_t n = (int64_t)merge_lanes(pl.n[0], wide) * ny * nz;
+    auto kern = pl.occb ? (wide ? k_resolve<true, true> : k_resolve<true, false>)
+                        : (wide ? k_resolve<false, true> : k_resolve<false, false>);
+    hipExtLaunchKernelGGL(kern, dim3(blocks_for(n)), dim3(kBlock), 0, st, ev.start, ev.stop, 0, pl,
+                          loc, rows, ring[0], ring[1], ring[2]);
     return hipGetLastError();
 }
 
 hipError_t launch_clear(const SlabClear &c, hipStream_t st, const StageEvents &ev)
 {
-    const int64_t lanes = (int64_t)(c.gxp / 16) * c.n[1] * c.n[2];
+    const int64_t lanes = clear_lanes(c);
+    if (lanes == 0)
+        return record_empty_stage(ev, st);
     hipExtLaunchKernelGGL(k_clear, dim3(blocks_for(lanes)), dim3(kBlock), 0, st, ev.start,
                           ev.stop, 0, c);
     return hipGetLastError();
@@ -1014,8 +1210,8 @@ hipError_t launch_upload(uint32_t *dst, const uint32_t *src, size_t words, hipSt
 }
 
 hipError_t launch_batch_stage(int stage, const FrameDesc *fd, const int32_t *start, int32_t n,
-                              int32_t blocks, hipStream_t st, const StageEvents &ev, int tile_w,
-                              size_t lds, bool seq)
+                              int32_t blocks, hipStream_t st, const StageEvents &ev, YzTile tile,
+                              size_t lds, bool seq, bool wide)
 {
     if (blocks <= 0 || n <= 0)
         return record_empty_stage(ev, st);
@@ -1028,17 +1224,23 @@ hipError_t launch_batch_stage(int stage, const FrameDesc *fd, const int32_t *sta
         hipExtLaunchKernelGGL(kb_seed, g, b, 0, st, ev.start, ev.stop, 0, fd, start, n);
         break;
     case kBatchDilateX:
-        hipExtLaunchKernelGGL(kb_dilate_x, g, b, 0, st, ev.start, ev.stop, 0, fd, start, n);
+        if (wide)
+            hipExtLaunchKernelGGL(kb_dilate_x<true>, g, b, 0, st, ev.start, ev.stop, 0, fd, start,
+                                  n);
+        else
+            hipExtLaunchKernelGGL(kb_dilate_x<false>, g, b, 0, st, ev.start, ev.stop, 0, fd,
+                                  start, n);
         break;
     case kBatchDilateYZ:
-        if (tile_w == 8)
-            hipExtLaunchKernelGGL(kb_dilate_yz_tile<8>, g, b, (uint32_t)lds, st, ev.start,
-                                  ev.stop, 0, fd, start, n);
-        else if (tile_w == 16)
-            hipExtLaunchKernelGGL(kb_dilate_yz_tile<16>, g, b, (uint32_t)lds, st, ev.start,
-                                  ev.stop, 0, fd, start, n);
-        else
+        if (tile.kw > 0) {
+            auto kern = tile.kw == 8
+                            ? (tile.tz == 2 ? kb_dilate_yz_tile<8, 2> : kb_dilate_yz_tile<8, 8>)
+                            : (tile.tz == 2 ? kb_dilate_yz_tile<16, 2> : kb_dilate_yz_tile<16, 8>);
+            hipExtLaunchKernelGGL(kern, g, b, (uint32_t)lds, st, ev.start, ev.stop, 0, fd, start,
+                                  n);
+        } else {
             hipExtLaunchKernelGGL(kb_dilate_yz, g, b, 0, st, ev.start, ev.stop, 0, fd, start, n);
+        }
         break;
     case kBatchRays:
         hipExtLaunchKernelGGL(kb_rays, g, b, 0, st, ev.start, ev.stop, 0, fd, start, n);
@@ -1046,8 +1248,12 @@ hipError_t launch_batch_stage(int stage, const FrameDesc *fd, const int32_t *sta
     case kBatchResolve:
         if (seq)
             hipExtLaunchKernelGGL(kb_resolve_seq, g, b, 0, st, ev.start, ev.stop, 0, fd, start, n);
+        else if (wide)
+            hipExtLaunchKernelGGL(kb_resolve<true>, g, b, 0, st, ev.start, ev.stop, 0, fd, start,
+                                  n);
         else
-            hipExtLaunchKernelGGL(kb_resolve, g, b, 0, st, ev.start, ev.stop, 0, fd, start, n);
+            hipExtLaunchKernelGGL(kb_resolve<false>, g, b, 0, st, ev.start, ev.stop, 0, fd, start,
+                                  n);
         break;
     default:
         return hipErrorInvalidValue;

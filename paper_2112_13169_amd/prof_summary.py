@@ -3,10 +3,12 @@ the library: a per-kernel table (launches, durations, counter bytes) in
 Markdown, and the measured bytes per launch beyond the L2 that the benchmark
 reports beside its roofline.
 
-Inputs are three rocprofv3 runs of the same benchmark command:
+Inputs are rocprofv3 runs of the same benchmark command:
   --kernel-trace --stats --output-format csv      (durations)
   --pmc FETCH_SIZE --output-format csv            (KiB read per dispatch)
   --pmc WRITE_SIZE --output-format csv            (KiB written per dispatch)
+  --pmc SQ_INSTS_VALU SQ_INSTS_SALU ... (optional: instruction counts, summed
+    over the device's shader engines)
 The benchmark runs an untimed device copy of a known size (the run's largest
 copy); its counter readings give the factor that turns each counter into bytes (on gfx950
 FETCH_SIZE reads half the bytes a streaming copy moves; WRITE_SIZE reads them
@@ -29,7 +31,8 @@ import os
 import re
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ["csrc/vg_kernels.hip", "csrc/vg_walk.h", "csrc/vg_internal.h"]
+KERNEL_SOURCES = ["csrc/vg_kernels.hip", "csrc/vg_walk.h", "csrc/vg_internal.h",
+                  "csrc/vg_frustum.h"]
 
 
 def code_only(text):
@@ -80,6 +83,25 @@ def read_stats(kt_dir):
 
 # MI355X HBM3E peak, GB/s (vendor figure)
 HBM_PEAK_GBS = 8000.0
+# MI355X: 256 CUs x 4 SIMDs; a wave64 VALU instruction occupies a 16-lane
+# SIMD for 4 cycles; 2.4 GHz
+SIMDS = 1024
+VALU_CYCLES = 4
+CLOCK_GHZ = 2.4
+SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_VMEM_RD",
+               "SQ_INSTS_VMEM_WR", "SQ_ACTIVE_INST_VALU", "SQ_BUSY_CYCLES", "SQ_WAVE_CYCLES")
+
+
+def read_sq(pmc_dir):
+    """Per-kernel mean of each SQ counter over its dispatches."""
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    with open(_one(os.path.join(pmc_dir, "*counter_collection.csv"))) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] in SQ_COUNTERS:
+                vals[short_name(r["Kernel_Name"])][r["Counter_Name"]].append(
+                    float(r["Counter_Value"]))
+    return {k: {c: sum(v) / len(v) for c, v in d.items()} | {"dispatches": len(next(iter(
+        d.values())))} for k, d in vals.items()}
 
 
 def read_counter(pmc_dir, counter):
@@ -118,6 +140,10 @@ def main(argv=None):
     ap.add_argument("--command", required=True, help="the profiled command, for the record")
     ap.add_argument("--md", required=True)
     ap.add_argument("--json", help="traffic summary to write (needs both counter runs)")
+    ap.add_argument("--sq", help="SQ counter run (optional: instruction table)")
+    ap.add_argument("--walk-kernel", help="kernel whose VALU per walk step is reported")
+    ap.add_argument("--walk-steps", type=float,
+                    help="in-grid walk steps per launch of --walk-kernel (from the benchmark)")
     a = ap.parse_args(argv)
 
     stats = read_stats(a.kt)
@@ -164,6 +190,37 @@ def main(argv=None):
                      f"{'-' if gbs is None else f'{gbs:.0f}'} | "
                      f"{'-' if gbs is None else f'{gbs / HBM_PEAK_GBS:.3f}'} |")
     lines.append("")
+    sq_rows = {}
+    if a.sq:
+        sq = read_sq(a.sq)
+        lines += ["Instruction counters (one `rocprofv3 --pmc` pass of SQ counters; values are summed "
+                  "over the device's shader engines and averaged over a kernel's dispatches). "
+                  "`VALU busy` is SQ_INSTS_VALU x 4 cycles over the SIMD cycles of the "
+                  "kernel's trace average (1 024 SIMDs x 2.4 GHz): the share of the chip's VALU "
+                  "issue slots the kernel used.", "",
+                  "| kernel | waves | VALU / wave | SALU / wave | VMEM rd / wave | VMEM wr / wave "
+                  "| VALU busy |", "|---|---|---|---|---|---|---|"]
+        for k, s in sorted(stats.items(), key=lambda kv: -kv[1]["pct"]):
+            q = sq.get(k)
+            if not q or not k.startswith(("k_", "kb_")) or not q.get("SQ_WAVES"):
+                continue
+            w = q["SQ_WAVES"]
+            busy = q["SQ_INSTS_VALU"] * VALU_CYCLES / (SIMDS * s["avg_ns"] * CLOCK_GHZ)
+            sq_rows[k] = dict(waves=round(w), valu_per_wave=round(q["SQ_INSTS_VALU"] / w, 1),
+                              salu_per_wave=round(q["SQ_INSTS_SALU"] / w, 1),
+                              valu_busy=round(busy, 3), valu_insts=q["SQ_INSTS_VALU"])
+            lines.append(f"| `{k}` | {w:.0f} | {q['SQ_INSTS_VALU'] / w:.1f} | "
+                         f"{q['SQ_INSTS_SALU'] / w:.1f} | {q['SQ_INSTS_VMEM_RD'] / w:.1f} | "
+                         f"{q['SQ_INSTS_VMEM_WR'] / w:.1f} | {busy:.3f} |")
+        lines.append("")
+        if a.walk_kernel and a.walk_steps and a.walk_kernel in sq:
+            q = sq[a.walk_kernel]
+            per = 64.0 * q["SQ_INSTS_VALU"] / a.walk_steps
+            lines += [f"`{a.walk_kernel}`: {q['SQ_INSTS_VALU']:.4g} VALU wave-instructions per "
+                      f"launch for {a.walk_steps:.4g} in-grid walk steps, i.e. {per:.1f} VALU "
+                      f"lane-slots per step (64 per wave-instruction, idle lanes of partly "
+                      f"finished wavefronts included), against the 20 algorithmic operations "
+                      f"of a step.", ""]
     with open(a.md, "w") as fh:
         fh.write("\n".join(lines))
     if counters and a.json:
@@ -171,7 +228,7 @@ def main(argv=None):
             json.dump(dict(workload=a.workload, source_hash=kernel_source_hash(),
                            hbm_peak_gbs=HBM_PEAK_GBS,
                            fetch_factor=round(f_fac, 4), write_factor=round(w_fac, 4),
-                           kernels=kernels), fh, indent=1)
+                           kernels=kernels, sq=sq_rows or None), fh, indent=1)
             fh.write("\n")
     print("\n".join(lines))
 

@@ -87,6 +87,29 @@ def test_rows_wider_than_the_tiled_dilation(dims, vox_inf):
     _one_frame(fr, f"wide grid {dims}")
 
 
+# 8-deep y/z dilation tiles are used where a launch has at least this many
+# of them (256 / kw row slots along y, 8 slices along z); 2-deep ones elsewhere.
+DEEP_TILE_MIN = 512
+
+
+def _deep_tiles(dims):
+    ty = 256 // (8 if _words(dims[0]) <= 8 else 16)
+    return -(-dims[1] // ty) * -(-dims[2] // 8)
+
+
+@pytest.mark.parametrize("dims,vox_inf", [((64, 1000, 165), 3), ((40, 900, 150), 1),
+                                          ((300, 600, 140), 0)])
+def test_deep_yz_dilation_tiles(dims, vox_inf):
+    """Grids with many y rows and z slices take 8-deep y/z dilation tiles
+    (8 output slices per tile, 8 + 2 vox_inf input slices staged in LDS),
+    including a partial last tile along y and along z."""
+    assert _deep_tiles(dims) >= DEEP_TILE_MIN and dims[1] % 32 and dims[2] % 8
+    fr = scenes.make_frame("plain-medium", 120 + dims[1], dims=dims, vox_inf=vox_inf,
+                           size=(320, 240))
+    _say(f"deep dilation tiles {dims} vox_inf {vox_inf}")
+    _one_frame(fr, f"deep tiles {dims}")
+
+
 def _round_of_grids(specs, seed):
     """One frame per grid (a single batch round), each grid centred on its
     frame's camera."""
