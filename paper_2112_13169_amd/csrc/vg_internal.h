@@ -199,14 +199,14 @@ inline int dilate_tile_width(const Planes &pl, int tz)
     // each thread loads at most 2 input rows of every z row: iy <= 2 ty
     if (kw == 0 || pl.r > kTileMaxR || iy > 2 * ty)
         return 0;
-    return 4 * (size_t)kw * (iz * iy + iz * ty) <= kMaxTileLds ? kw : 0;
+    return 4 * (size_t)kw * iz * iy <= kMaxTileLds ? kw : 0;
 }
 
-// LDS bytes of one tile: its padded input rows plus the rows dilated along y.
+// LDS bytes of one tile: its padded input rows.
 inline size_t dilate_tile_lds(const Planes &pl, YzTile t)
 {
     const size_t ty = 256 / t.kw, iz = (size_t)t.tz + 2 * pl.r, iy = ty + 2 * pl.r;
-    return 4 * (size_t)t.kw * (iz * iy + iz * ty);
+    return 4 * (size_t)t.kw * iz * iy;
 }
 
 inline int64_t dilate_tiles(const Planes &pl, YzTile t)

@@ -50,8 +50,27 @@ constexpr int kBlock = 256;
 // Ray wavefronts up to which a launch has at most one per SIMD (gfx950:
 // 256 compute units x 4 SIMDs) and its ray blocks go to the XCDs in ranges.
 constexpr int64_t kLoneWaves = 1024;
+// Larger walk launches give each XCD runs of this many consecutive ray blocks.
+constexpr int32_t kXcdRun = 8;
 
 // ----------------------------------------------------------------- helpers
+
+// Workgroup b of a launch runs on XCD b mod 8, and each of the 8 XCDs has an
+// L2 of its own.  Neighbouring ray tiles mark the same mark-plane lines, and a
+// line dirtied in several L2s is written back from each of them.  The block
+// that runs as workgroup b takes block xcd_runs(b, n) instead, so that each
+// XCD walks runs of kXcdRun consecutive blocks: most lines then stay in one
+// L2, and the runs still spread the costly tiles over every XCD.  A
+// permutation of [0, n) (blocks past the last whole round of 8 runs keep
+// their numbers).
+__device__ __forceinline__ int32_t xcd_runs(int32_t b, int32_t n)
+{
+    constexpr int32_t round = 8 * kXcdRun;
+    if (b >= n / round * round)
+        return b;
+    const int32_t k = b >> 3, x = b & 7;
+    return ((k / kXcdRun) * 8 + x) * kXcdRun + k % kXcdRun;
+}
 
 // Row i of R p: ((R_i0 x + R_i1 y) + R_i2 z), each operation rounded.
 __device__ __forceinline__ float row_dot(const float *Ri, float x, float y, float z)
@@ -380,8 +399,11 @@ __device__ __forceinline__ void dilate_yz_body(const Planes &pl, int64_t gid)
 // The same dilation for one tile (tile_y, tile_z) of kBlock / kW rows along y
 // by kTZ along z (vox_inf <= kTileMaxR).  Thread = (word lane w, row slot);
 // the padded rows the tile reads are loaded once into LDS (rows outside the
-// seed box as 0), ORed along y into a second LDS buffer, then along z.  No
-// divisions: rows are walked by slot, words by lane.
+// seed box as 0).  Each thread then ORs its column along y, one input z row
+// at a time, into registers, and ORs those along z.  Both passes read a fixed
+// 2 kTileMaxR + 1 rows (rows past the window are read, at clamped addresses,
+// and not used), so that the reads of a pass issue together.  No divisions:
+// rows are walked by slot, words by lane.
 template <int kW, int kTZ>
 __device__ __forceinline__ void dilate_yz_tile_body(const Planes &pl, int32_t tile_y,
                                                     int32_t tile_z, uint32_t *lds)
@@ -393,7 +415,6 @@ __device__ __forceinline__ void dilate_yz_tile_body(const Planes &pl, int32_t ti
     const int32_t iy = kTY + r2, iz = kTZ + r2;
     const int32_t y0 = tile_y * kTY, z0 = tile_z * kTZ;   // first output row = padded row
     uint32_t *in = lds;                   // [iz][iy][kW]
-    uint32_t *yd = lds + iz * iy * kW;    // [iz][kTY][kW]
     const bool any = pl.lo[0] <= pl.hi[0];
     const bool lane = w < wx;
     // all loads of a thread first, so that they are in flight together: the
@@ -422,23 +443,33 @@ __device__ __forceinline__ void dilate_yz_tile_body(const Planes &pl, int32_t ti
                 in[(zz * iy + yy) * kW + w] = ld[h][zz];
     }
     __syncthreads();
-    for (int32_t zz = 0; zz < iz; ++zz) {
+    // along y: t[zz] = OR of input rows slot .. slot + r2 of input z row zz
+    // (z rows past iz are read at row iz - 1 and not used either)
+    uint32_t t[kTileMaxIz];
+#pragma unroll
+    for (int zz = 0; zz < kTileMaxIz; ++zz) {
+        const int32_t zr = min(zz, iz - 1);
         uint32_t v = 0;
-        for (int32_t d = 0; d <= r2; ++d)
-            v |= in[(zz * iy + slot + d) * kW + w];
-        yd[(zz * kTY + slot) * kW + w] = v;
+#pragma unroll
+        for (int d = 0; d <= 2 * kTileMaxR; ++d) {
+            const uint32_t x = in[(zr * iy + min(slot + d, iy - 1)) * kW + w];
+            v |= d <= r2 ? x : 0u;
+        }
+        t[zz] = zz < iz ? v : 0u;
     }
-    __syncthreads();
     const int32_t gy = y0 + slot;
     if (!lane || gy >= pl.n[1])
         return;
-    for (int32_t z = 0; z < kTZ; ++z) {
+    // along z: output z row z0 + z = OR of t[z .. z + r2]
+#pragma unroll
+    for (int z = 0; z < kTZ; ++z) {
         const int32_t gz = z0 + z;
         if (gz >= pl.n[2])
             break;
         uint32_t v = 0;
-        for (int32_t d = 0; d <= r2; ++d)
-            v |= yd[((z + d) * kTY + slot) * kW + w];
+#pragma unroll
+        for (int d = 0; d <= 2 * kTileMaxR; ++d)
+            v |= d <= r2 ? t[z + d] : 0u;
         pl.occ[(int64_t)wx * (gy + (int64_t)pl.n[1] * gz) + w] = v;
     }
 }
@@ -479,9 +510,10 @@ __device__ __forceinline__ int32_t wrap_add(int32_t v, int32_t r, int32_t n)
 // v_alignbyte.
 __device__ __forceinline__ uint4 load16_unaligned(const uint8_t *p)
 {
-    const uintptr_t a = (uintptr_t)p;
-    const uint32_t *w = reinterpret_cast<const uint32_t *>(a & ~(uintptr_t)3);
-    const uint32_t sh = (uint32_t)(a & 3);
+    // pointer arithmetic, not an integer round trip, keeps the global
+    // address space (global rather than flat loads)
+    const uint32_t sh = (uint32_t)((uintptr_t)p & 3);
+    const uint32_t *w = reinterpret_cast<const uint32_t *>(p - sh);
     uint32_t v[5];
 #pragma unroll
     for (int k = 0; k < 5; ++k)
@@ -591,6 +623,90 @@ __device__ __forceinline__ void gather16(const Planes &pl, int64_t prow, int32_t
     m.f = byte_eq_ff16(fr, rep);
 }
 
+// The four 16-column chunks a wide merge lane reads, and the loads they need.
+// Chunk s holds grid columns x0[s] .. (nv[s] of them, wrapping at the grid's
+// width); want[s]: the lane reads it.  Chunks that lie in one run of grid
+// columns load through buffer resources -- 20 bytes from the dword below the
+// run's first byte, realigned with v_alignbyte -- and the others (not read,
+// or wrapping at the seam) at an offset past every range, which reads 0
+// without a branch; so every load of the lane is issued before the first is
+// used.  The wrapping chunks are read byte by byte afterwards.
+struct Lane64 {
+    int32_t x0[4], nv[4];
+    bool want[4];
+};
+
+template <bool kBytes>
+struct Loads64 {
+    uint4 f4[4], t4[4], o4[4];
+    uint32_t f1[4], t1[4], o1[4];
+    uint32_t sh[4];
+    uint32_t ob[4][2], osh[4];
+};
+
+template <bool kBytes>
+__device__ __forceinline__ void issue64(const Planes &pl, uint32_t prow, const Lane64 &c,
+                                        Loads64<kBytes> &ld)
+{
+    const uint32_t nb = pl.nbytes;
+    // one dword of slack past each plane: the plane that follows, or the
+    // scratch region after the traced plane
+    const __amdgpu_buffer_rsrc_t rm = buffer_rsrc(pl.marks, 2u * nb + 4u);
+    const __amdgpu_buffer_rsrc_t ro =
+        kBytes ? buffer_rsrc(pl.occb, nb + 4u) : buffer_rsrc(pl.occ, nb / 8u + 4u);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const uint32_t b = prow + (uint32_t)c.x0[s];
+        const bool run = c.want[s] && c.x0[s] + c.nv[s] <= pl.n[0];
+        const uint32_t off = run ? (b & ~3u) : kOob;
+        ld.sh[s] = b & 3u;
+        const auto f = __builtin_amdgcn_raw_buffer_load_b128(rm, (int)off, 0, 0);
+        const auto t = __builtin_amdgcn_raw_buffer_load_b128(rm, (int)(off + nb), 0, 0);
+        ld.f4[s] = make_uint4(f[0], f[1], f[2], f[3]);
+        ld.t4[s] = make_uint4(t[0], t[1], t[2], t[3]);
+        ld.f1[s] = __builtin_amdgcn_raw_buffer_load_b32(rm, (int)(off + 16u), 0, 0);
+        ld.t1[s] = __builtin_amdgcn_raw_buffer_load_b32(rm, (int)(off + nb + 16u), 0, 0);
+        if (kBytes) {
+            const auto o = __builtin_amdgcn_raw_buffer_load_b128(ro, (int)off, 0, 0);
+            ld.o4[s] = make_uint4(o[0], o[1], o[2], o[3]);
+            ld.o1[s] = __builtin_amdgcn_raw_buffer_load_b32(ro, (int)(off + 16u), 0, 0);
+        } else {
+            const auto o = __builtin_amdgcn_raw_buffer_load_b64(ro, (int)(run ? (b >> 5) << 2 : kOob),
+                                                                0, 0);
+            ld.ob[s][0] = o[0];
+            ld.ob[s][1] = o[1];
+            ld.osh[s] = b & 31u;
+        }
+    }
+}
+
+__device__ __forceinline__ uint4 align16(const uint4 &v, uint32_t next, uint32_t sh)
+{
+    return make_uint4(__builtin_amdgcn_alignbyte(v.y, v.x, sh),
+                      __builtin_amdgcn_alignbyte(v.z, v.y, sh),
+                      __builtin_amdgcn_alignbyte(v.w, v.z, sh),
+                      __builtin_amdgcn_alignbyte(next, v.w, sh));
+}
+
+template <bool kBytes>
+__device__ __forceinline__ void finish64(const Planes &pl, uint32_t prow, const Lane64 &c,
+                                         const Loads64<kBytes> &ld, Masks16 mk[4])
+{
+    const uint32_t rep = (pl.epoch & 0xFFu) * 0x01010101u;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        mk[s].f = byte_eq_ff16(align16(ld.f4[s], ld.f1[s], ld.sh[s]), rep);
+        mk[s].t = byte_eq_ff16(align16(ld.t4[s], ld.t1[s], ld.sh[s]), rep);
+        if (kBytes)
+            mk[s].o = byte_eq_ff16(align16(ld.o4[s], ld.o1[s], ld.sh[s]), rep);
+        else
+            mk[s].o = spread16(__builtin_amdgcn_alignbit(ld.ob[s][1], ld.ob[s][0], ld.osh[s]) &
+                               0xFFFFu);
+        if (c.want[s] && c.x0[s] + c.nv[s] > pl.n[0])
+            gather16<kBytes>(pl, prow, c.x0[s], c.nv[s], mk[s]);
+    }
+}
+
 // Four voxels of the local grid: the bytes of cm become unknown (a shift's
 // clear), then Alg. 3 -- an occupied voxel becomes occupied, else a traced
 // one unknown, else a free one free; the others keep their value.
@@ -682,28 +798,33 @@ __device__ __forceinline__ void resolve_body(const Planes &pl, uint8_t *loc, con
     const bool bounded = pl.lim && row_runs(*pl.lim, y, z, gx, run);
     // chunks within the runs: their planes and the local grid's 16 voxels
     // are loaded together (the runs are tight, so nearly all of them change)
-    Masks16 mk[4];
-    uint4 v[4];
-    bool in[4];
+    Lane64 c;
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
-        in[s] = false;
         const int32_t c0 = 64 * k + 16 * s;   // buffer column of the chunk
-        if (c0 >= gx)
-            continue;                          // row padding only
-        const int32_t nvalid = min(16, gx - c0);
         int32_t x0 = c0 - ring[0];             // grid column of buffer column c0
         if (x0 < 0)
             x0 += gx;
-        if (run_touched(bounded, run, gx, x0, nvalid)) {
-            in[s] = true;
-            gather16<kBytes>(pl, prow, x0, nvalid, mk[s]);
-            v[s] = *reinterpret_cast<const uint4 *>(loc + brow + c0);
-        }
+        c.x0[s] = x0;
+        c.nv[s] = min(16, gx - c0);
+        // c0 >= gx: row padding only
+        c.want[s] = c0 < gx && run_touched(bounded, run, gx, x0, c.nv[s]);
     }
+    Loads64<kBytes> ld;
+    issue64<kBytes>(pl, (uint32_t)prow, c, ld);
+    const __amdgpu_buffer_rsrc_t rl = buffer_rsrc(loc, pl.nbytes);
+    uint4 v[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const uint32_t off = c.want[s] ? (uint32_t)brow + 64u * k + 16u * s : kOob;
+        const auto q = __builtin_amdgcn_raw_buffer_load_b128(rl, (int)off, 0, 0);
+        v[s] = make_uint4(q[0], q[1], q[2], q[3]);
+    }
+    Masks16 mk[4];
+    finish64<kBytes>(pl, (uint32_t)prow, c, ld, mk);
 #pragma unroll
     for (int s = 0; s < 4; ++s)
-        if (in[s] && any16(mk[s])) {
+        if (c.want[s] && any16(mk[s])) {
             apply16(v[s], make_uint4(0u, 0u, 0u, 0u), mk[s]);
             *reinterpret_cast<uint4 *>(loc + brow + 64 * k + 16 * s) = v[s];
         }
@@ -779,31 +900,35 @@ __device__ __forceinline__ void resolve_seq_body(const FrameDesc *fd, int64_t gi
         const bool in_rows = y >= f.rows.y0 && y <= f.rows.y1 && z >= f.rows.z0 && z <= f.rows.z1;
         int32_t run[4];
         const bool bounded = in_rows && f.sp.pl.lim && row_runs(*f.sp.pl.lim, y, z, gx, run);
-        const int64_t prow = 32 * (int64_t)pl0.wx * (y + (int64_t)gy * z);
+        const uint32_t prow = 32u * (uint32_t)pl0.wx * (uint32_t)(y + gy * z);
+        Lane64 c;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int32_t c0 = 64 * k + 16 * s;
+            int32_t x0 = c0 - f.ring[0];
+            if (x0 < 0)
+                x0 += gx;
+            c.x0[s] = x0;
+            c.nv[s] = min(16, gx - c0);
+            c.want[s] = c0 < gx && in_rows && run_touched(bounded, run, gx, x0, c.nv[s]);
+        }
+        Loads64<false> ld;
+        issue64<false>(f.sp.pl, prow, c, ld);
+        Masks16 mk[4];
+        finish64<false>(f.sp.pl, prow, c, ld, mk);
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int32_t c0 = 64 * k + 16 * s;
             if (c0 >= gx)
                 continue;
-            const int32_t nvalid = min(16, gx - c0);
-            int32_t x0 = c0 - f.ring[0];
-            if (x0 < 0)
-                x0 += gx;
-            const uint32_t cm = clear_mask16(f.clear, y, z, x0, nvalid);
-            Masks16 mk = {make_uint4(0u, 0u, 0u, 0u), make_uint4(0u, 0u, 0u, 0u),
-                          make_uint4(0u, 0u, 0u, 0u)};
-            bool any = false;
-            if (in_rows && run_touched(bounded, run, gx, x0, nvalid)) {
-                gather16<false>(f.sp.pl, prow, x0, nvalid, mk);
-                any = any16(mk);
-            }
-            if (cm == 0u && !any)
+            const uint32_t cm = clear_mask16(f.clear, y, z, c.x0[s], c.nv[s]);
+            if (cm == 0u && !(c.want[s] && any16(mk[s])))
                 continue;
             if (!((loaded >> s) & 1u)) {
                 v[s] = *reinterpret_cast<const uint4 *>(dst + 16 * s);
                 loaded |= 1u << s;
             }
-            apply16(v[s], spread16(cm), mk);
+            apply16(v[s], spread16(cm), mk[s]);
         }
     }
 #pragma unroll
@@ -908,10 +1033,12 @@ __global__ __launch_bounds__(kBlock) void k_rays(RayParams p, SlabClear c, int32
         // Workgroups go to the 8 XCDs in turn.  With every ray wavefront
         // resident at once, each XCD takes a contiguous range of ray blocks,
         // whose neighbouring tiles share cache lines in its L2.  (With more
-        // wavefronts than SIMDs the turn order spreads the costly tiles
-        // over the XCDs, which matters more.)
+        // wavefronts than SIMDs, contiguous ranges load the XCDs unevenly:
+        // runs of kXcdRun blocks keep the costly tiles spread.)
         const int32_t q = ray_blocks / 8, rem = ray_blocks % 8, xcd = rb % 8;
         rb = xcd * q + min(xcd, rem) + rb / 8;
+    } else {
+        rb = xcd_runs(rb, ray_blocks);
     }
     rays_body<kGeneral, kBytes, kLone>(p, rb * (kBlock / 64) + (threadIdx.x >> 6));
 }
@@ -1010,7 +1137,7 @@ __global__ __launch_bounds__(kBlock) void kb_rays(const FrameDesc *__restrict__ 
                                                   const int32_t *__restrict__ start, int32_t n)
 {
     int32_t local;
-    const FrameDesc &f = fd[frame_of(start, n, blockIdx.x, local)];
+    const FrameDesc &f = fd[frame_of(start, n, xcd_runs((int32_t)blockIdx.x, start[n]), local)];
     const int32_t tile = local * (kBlock / 64) + (threadIdx.x >> 6);
     if (f.inside)
         rays_body<false, false, true>(f.rp, tile);

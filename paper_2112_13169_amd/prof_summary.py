@@ -9,6 +9,8 @@ Inputs are rocprofv3 runs of the same benchmark command:
   --pmc WRITE_SIZE --output-format csv            (KiB written per dispatch)
   --pmc SQ_INSTS_VALU SQ_INSTS_SALU ... (optional: instruction counts, summed
     over the device's shader engines)
+  --pmc TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_32B_sum ... (optional: read requests by
+    size)
 The benchmark runs an untimed device copy of a known size (the run's largest
 copy); its counter readings give the factor that turns each counter into bytes (on gfx950
 FETCH_SIZE reads half the bytes a streaming copy moves; WRITE_SIZE reads them
@@ -104,6 +106,23 @@ def read_sq(pmc_dir):
         d.values())))} for k, d in vals.items()}
 
 
+RDREQ_COUNTERS = ("TCC_EA0_RDREQ_sum", "TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum",
+                  "TCC_EA0_RDREQ_128B_sum")
+
+
+def read_rdreq(pmc_dir):
+    """Per-kernel mean of the L2's read requests to the memory side by size,
+    over its dispatches."""
+    vals = collections.defaultdict(lambda: collections.defaultdict(list))
+    with open(_one(os.path.join(pmc_dir, "*counter_collection.csv"))) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] in RDREQ_COUNTERS:
+                vals[short_name(r["Kernel_Name"])][r["Counter_Name"]].append(
+                    float(r["Counter_Value"]))
+    return {k: {c[len("TCC_EA0_"):-len("_sum")]: sum(v) / len(v) for c, v in d.items()}
+            for k, d in vals.items()}
+
+
 def read_counter(pmc_dir, counter):
     """Per-kernel list of (grid size, KiB) of each dispatch, in dispatch order."""
     rows = []
@@ -141,6 +160,7 @@ def main(argv=None):
     ap.add_argument("--md", required=True)
     ap.add_argument("--json", help="traffic summary to write (needs both counter runs)")
     ap.add_argument("--sq", help="SQ counter run (optional: instruction table)")
+    ap.add_argument("--rdreq", help="run of the read request counters by size (optional)")
     ap.add_argument("--walk-kernel", help="kernel whose VALU per walk step is reported")
     ap.add_argument("--walk-steps", type=float,
                     help="in-grid walk steps per launch of --walk-kernel (from the benchmark)")
@@ -221,6 +241,29 @@ def main(argv=None):
                       f"lane-slots per step (64 per wave-instruction, idle lanes of partly "
                       f"finished wavefronts included), against the 20 algorithmic operations "
                       f"of a step.", ""]
+    rd_rows = {}
+    if a.rdreq:
+        rq = read_rdreq(a.rdreq)
+        lines += ["Read requests by size (one `rocprofv3 --pmc` pass of TCC_EA0_RDREQ, "
+                  "TCC_EA0_RDREQ_32B, _64B and _128B, summed over the L2 channels, mean per "
+                  "dispatch): the share of 128-byte requests tells whether a kernel's scattered "
+                  "loads fetch the same 128-byte lines as the streaming copy the FETCH_SIZE "
+                  "factor comes from.", "",
+                  "| kernel | read requests | 32 B | 64 B | 128 B | share 128 B | bytes requested |",
+                  "|---|---|---|---|---|---|---|"]
+        for k, s in sorted(stats.items(), key=lambda kv: -kv[1]["pct"]):
+            q = rq.get(k)
+            if not q or not q.get("RDREQ"):
+                continue
+            n32, n64, n128 = q.get("RDREQ_32B", 0.0), q.get("RDREQ_64B", 0.0), q.get("RDREQ_128B", 0.0)
+            nbytes = 32 * n32 + 64 * n64 + 128 * n128
+            share = n128 / q["RDREQ"]
+            if k.startswith(("k_", "kb_")):
+                rd_rows[k] = dict(requests=round(q["RDREQ"]), share_128b=round(share, 4),
+                                  bytes_requested=round(nbytes))
+            lines.append(f"| `{k}` | {q['RDREQ']:.0f} | {n32:.0f} | {n64:.0f} | {n128:.0f} | "
+                         f"{share:.3f} | {nbytes / 1e6:.3f} MB |")
+        lines.append("")
     with open(a.md, "w") as fh:
         fh.write("\n".join(lines))
     if counters and a.json:
@@ -228,7 +271,8 @@ def main(argv=None):
             json.dump(dict(workload=a.workload, source_hash=kernel_source_hash(),
                            hbm_peak_gbs=HBM_PEAK_GBS,
                            fetch_factor=round(f_fac, 4), write_factor=round(w_fac, 4),
-                           kernels=kernels, sq=sq_rows or None), fh, indent=1)
+                           kernels=kernels, sq=sq_rows or None, read_requests=rd_rows or None),
+                      fh, indent=1)
             fh.write("\n")
     print("\n".join(lines))
 
