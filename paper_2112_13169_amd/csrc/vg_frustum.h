@@ -63,17 +63,16 @@ VG_FR_HD void region_columns(const Region &R, int32_t y, int32_t z, int32_t xmin
     const double yd = (double)y, zd = (double)z;
     double flo = (double)xmin, fhi = (double)xmax;
     bool none = false;
+    // selects, no branches: the device loads every plane before the first
+    // is used
     for (int k = 0; k < 4; ++k) {
         const RowPlane &q = R.p[k];
         // a conservative bound: fused multiply-adds are fine here
         const double t = fma(q.g, zd, fma(q.f, yd, q.e));
-        const double b = fma(t, q.inv, q.c0);
-        if (q.kind > 0)
-            fhi = fmin(fhi, b + 1.0);
-        else if (q.kind < 0)
-            flo = fmax(flo, b - 1.0);
-        else
-            none = none || t < 0.0;
+        const double b = fma(t, q.inv, q.c0);   // kind 0: inv 0, b finite and unused
+        fhi = q.kind > 0 ? fmin(fhi, b + 1.0) : fhi;
+        flo = q.kind < 0 ? fmax(flo, b - 1.0) : flo;
+        none = none || (q.kind == 0 && t < 0.0);
     }
     if (none || !(flo <= fhi)) {
         lo = 1;

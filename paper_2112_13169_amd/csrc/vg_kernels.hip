@@ -55,6 +55,23 @@ constexpr int32_t kXcdRun = 8;
 
 // ----------------------------------------------------------------- helpers
 
+// A frame's row limits as the kernels read them: through the constant address
+// space (the seed pass wrote them in an earlier launch and no kernel that
+// reads them writes them), so that they load with scalar loads also where
+// the pointer itself was read from memory (a batch's frame table).
+// (The host pass of this file, which never runs the kernels, keeps the plain
+// pointer.)
+#ifdef __HIP_DEVICE_COMPILE__
+typedef const __attribute__((address_space(4))) RowLimits *ConstLimits;
+#else
+typedef const RowLimits *ConstLimits;
+#endif
+
+__device__ __forceinline__ ConstLimits const_limits(const RowLimits *p)
+{
+    return (ConstLimits)p;
+}
+
 // Workgroup b of a launch runs on XCD b mod 8, and each of the 8 XCDs has an
 // L2 of its own.  Neighbouring ray tiles mark the same mark-plane lines, and a
 // line dirtied in several L2s is written back from each of them.  The block
@@ -343,7 +360,8 @@ __device__ __forceinline__ void dilate_x_body(const Planes &pl, int64_t gid)
     const int32_t need = 32 * words + 2 * pl.r;            // stamp bytes they read
     uint32_t m[5] = {0u, 0u, 0u, 0u, 0u};                  // bit j: byte x0 + j is a seed
     if (x0 <= pl.hi[0] && x0 + need - 1 >= pl.lo[0] &&
-        (!pl.lim || row_run_seeded(*pl.lim, y - pl.r, z - pl.r, x0 - pl.r, x0 + need - 1 - pl.r))) {
+        (!pl.lim || row_run_seeded(*const_limits(pl.lim), y - pl.r, z - pl.r, x0 - pl.r,
+                                   x0 + need - 1 - pl.r))) {
         const uint4 *src = reinterpret_cast<const uint4 *>(
             pl.seed + (int64_t)pl.seed_pitch * (y + (int64_t)pl.py * z) + x0);
         const uint32_t rep = (pl.epoch & 0xFFu) * 0x01010101u;
@@ -795,7 +813,7 @@ __device__ __forceinline__ void resolve_body(const Planes &pl, uint8_t *loc, con
     const int64_t prow = 32 * (int64_t)pl.wx * (y + (int64_t)pl.n[1] * z);    // planes
     const int64_t brow = 32 * (int64_t)pl.wx * (by + (int64_t)pl.n[1] * bz);  // buffer
     int32_t run[4];
-    const bool bounded = pl.lim && row_runs(*pl.lim, y, z, gx, run);
+    const bool bounded = pl.lim && row_runs(*const_limits(pl.lim), y, z, gx, run);
     // chunks within the runs: their planes and the local grid's 16 voxels
     // are loaded together (the runs are tight, so nearly all of them change)
     Lane64 c;
@@ -899,7 +917,8 @@ __device__ __forceinline__ void resolve_seq_body(const FrameDesc *fd, int64_t gi
             z += gz;
         const bool in_rows = y >= f.rows.y0 && y <= f.rows.y1 && z >= f.rows.z0 && z <= f.rows.z1;
         int32_t run[4];
-        const bool bounded = in_rows && f.sp.pl.lim && row_runs(*f.sp.pl.lim, y, z, gx, run);
+        const bool bounded =
+            in_rows && f.sp.pl.lim && row_runs(*const_limits(f.sp.pl.lim), y, z, gx, run);
         const uint32_t prow = 32u * (uint32_t)pl0.wx * (uint32_t)(y + gy * z);
         Lane64 c;
 #pragma unroll
