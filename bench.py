@@ -67,8 +67,8 @@ TRAFFIC_FILE_MEDIUM = os.path.join(PROFILES, "traffic.json")
 TRAFFIC_FILE_BATCHED = os.path.join(PROFILES, "traffic_batched.json")
 SECTIONS = ("headline", "spinning", "medium", "small", "batched", "served", "paper")
 
-STAGE_KERNELS = {"k_dilate": ["k_dilate_x<false>", "k_dilate_x<true>", "k_dilate_yz",
-                              "k_dilate_yz_tile<8>", "k_dilate_yz_tile<16>"],
+STAGE_KERNELS = {"k_dilate": ["k_dilate_x<false>", "k_dilate_x<true>", "k_dilate_yz"] +
+                             [f"k_dilate_yz_tile<{w}, {z}>" for w in (8, 16) for z in (2, 8)],
                  "k_rays": [f"k_rays<{g}, {b}, {l}>" for g in ("false", "true")
                             for b in ("false", "true") for l in ("false", "true")],
                  "k_resolve": [f"k_resolve<{b}, {w}>" for b in ("false", "true")
@@ -154,6 +154,50 @@ def measured_traffic(stage, path, workload):
         return None
     n = sum(k.get("launches", 1) for k in got)
     return float(sum(k["hbm_bytes_per_launch"] * k.get("launches", 1) for k in got)) / n
+
+
+def frame_counter_bytes(path, workload):
+    """Memory-side bytes per frame of the one-frame path (seed, dilations,
+    walk, merge, clear) from the committed counter summary: every such
+    kernel's bytes over the profiled run, per walk launch (one per frame);
+    None if absent or stale."""
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    from paper_2112_13169_amd.prof_summary import kernel_source_hash
+    if t.get("source_hash") != kernel_source_hash() or t.get("workload") != workload:
+        return None
+    ks = t.get("kernels", {})
+    frames = sum(v.get("launches", 0) for k, v in ks.items() if k.startswith("k_rays<"))
+    if not frames:
+        return None
+    stages = ("k_seed", "k_dilate_", "k_rays<", "k_resolve<", "k_clear")
+    total = sum(v["hbm_bytes_per_launch"] * v.get("launches", 1) for k, v in ks.items()
+                if k.startswith(stages))
+    return float(total) / frames
+
+
+def frame_memory(f0, upd, fps):
+    """Bytes per frame of the one-frame path at its measured rate: the
+    algorithmic bytes (4 B per pixel of depth read, 5 B per voxel update:
+    its mark store and the merge's two mark reads, local-grid read and
+    write) and the memory-side bytes of the committed counter summary."""
+    if not upd:
+        return None
+    H, W = f0.depth.shape
+    alg = 4.0 * W * H + 5.0 * upd
+    ctr = frame_counter_bytes(TRAFFIC_FILE, WORKLOAD)
+    out = {"algorithmic_bytes_per_frame": round(alg),
+           "algorithmic_gb_per_s": round(alg * fps / 1e9, 1),
+           "counter_bytes_per_frame": round(ctr) if ctr else None,
+           "counter_gb_per_s": round(ctr * fps / 1e9, 1) if ctr else None,
+           "counter_frac_of_hbm_peak": round(ctr * fps / 1e9 / HBM_PEAK_GBS, 4) if ctr else None,
+           "hbm_peak_gb_per_s": HBM_PEAK_GBS,
+           "note": "counter bytes: FETCH_SIZE and WRITE_SIZE of every kernel of the one-frame "
+                   "path in the committed profile, calibrated on a device copy, per frame"}
+    return out
 
 
 # ------------------------------------------------ inputs (worker processes)
@@ -1103,6 +1147,8 @@ def main():
             "voxel_updates_per_s": round(upd * fps, 1) if upd else None,
             "voxel_updates_per_frame": round(upd, 1) if upd else None,
             "walk_steps_per_frame": round(float(np.mean(steps)), 1) if steps else None,
+            "walk_steps_per_s": round(float(np.mean(steps)) * fps, 1) if steps else None,
+            "memory": frame_memory(pin[0], upd, fps),
             "latency_ms": res["latency_ms"],
             "stage_ms": res["stage_ms"],
             "walk_ms": pct(res["walk_ms"]),
