@@ -103,7 +103,8 @@ size_t vg_grid_bytes(int32_t grid_size_x, int32_t grid_size_y, int32_t grid_size
 
 /* Bytes of device scratch workspace a grid of this size and vox_inf needs
  * for one set of per-frame planes (stamp and bit planes of steps 2-3, Alg. 1
- * and 2).  A scratch of k times this size (k <= VG_MAX_PLANE_SETS) holds k
+ * and 2; with the frame's row regions and, in the first set, the order in
+ * which large walks take their ray blocks).  A scratch of k times this size (k <= VG_MAX_PLANE_SETS) holds k
  * sets: vg_integrate_batch then runs up to k consecutive frames of the grid
  * together (see there).  Host-only; 0 for invalid sizes. */
 size_t vg_scratch_bytes(int32_t grid_size_x, int32_t grid_size_y, int32_t grid_size_z,

@@ -35,7 +35,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 //   lim       the frame's row regions (vg_frustum.h), written by its seed pass
 struct Layout {
     int32_t gxp, wx, py, pz, seed_pitch;
-    size_t seed, bitx, occ, marks, hz, lim, fixed;
+    size_t seed, bitx, occ, marks, hz, lim, order, fixed;
 };
 
 Layout layout_for(int32_t gx, int32_t gy, int32_t gz, int32_t r)
@@ -52,7 +52,8 @@ Layout layout_for(int32_t gx, int32_t gy, int32_t gz, int32_t r)
     l.marks = l.occ + align_up((size_t)4 * l.wx * gy * gz);
     l.hz = l.marks + align_up((size_t)2 * l.gxp * gy * gz);
     l.lim = l.hz + kHzBytes;
-    l.fixed = l.lim + align_up(sizeof(RowLimits));
+    l.order = l.lim + align_up(sizeof(RowLimits));
+    l.fixed = l.order + align_up(2 * kOrderBufBytes);
     return l;
 }
 
@@ -144,6 +145,7 @@ struct vg_grid {
     size_t scratch_bytes;
     Layout lay;
     uint32_t epoch;          // stamp of the last frame, 0 = none yet
+    uint32_t order_flip = 0; // which walk-order buffer (plane set 0) the next walk reads
     int device;
     int32_t sets = 1;        // plane sets in scratch, lay.fixed bytes apart
     // spinning fan table currently in each set
@@ -587,6 +589,8 @@ vg_status plan_frame(const vg_grid *g, const GridState &gs, int kind, const floa
     rp.marks = pl.marks;
     rp.nbytes = pl.nbytes;
     rp.epoch = p.epoch;
+    rp.order_in = nullptr;
+    rp.order_out = nullptr;
     p.inside = v0[0] >= 0 && v0[0] < g->n[0] && v0[1] >= 0 && v0[1] < g->n[1] && v0[2] >= 0 &&
                v0[2] < g->n[2];
 
@@ -672,6 +676,22 @@ bool shift_in_range(const vg_grid *g, const int32_t d[3])
     return true;
 }
 
+// A pinhole walk from inside the grid with more ray wavefronts than the GPU
+// has SIMDs (and no more blocks than an order holds) reads the block order
+// the previous such walk of the grid built and builds the next one
+// (WalkOrder); the two buffers of plane set 0 alternate.
+void use_walk_order(vg_grid *g, FramePlan &p)
+{
+    const int64_t ray_blocks = ((int64_t)p.rp.tiles + 3) / 4;
+    if (p.rp.kind != kPinhole || !p.inside || ray_blocks * 4 <= kLoneWaves ||
+        ray_blocks > kOrderMaxBlocks)
+        return;
+    uint8_t *base = g->scratch + g->lay.order;
+    const uint32_t f = g->order_flip++ & 1u;
+    p.rp.order_in = reinterpret_cast<const int32_t *>(base + kOrderBufBytes * f);
+    p.rp.order_out = reinterpret_cast<int32_t *>(base + kOrderBufBytes * (1u - f));
+}
+
 // Steps 2-4 of one frame, after the shift d (step 5) if d is given and not
 // zero: its slab clear runs as extra workgroups of the walk launch.
 vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_floats, int32_t W,
@@ -709,8 +729,10 @@ vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_float
     if (e == hipSuccess)   // direct stamping has nothing to dilate
         e = p.direct ? record_empty_stage(stage(kStageDilate), st)
                      : launch_dilate(p.sp.pl, st, stage(kStageDilate));
-    if (e == hipSuccess)
+    if (e == hipSuccess) {
+        use_walk_order(g, p);
         e = launch_rays(p.rp, p.inside, st, stage(kStageRays), shifted ? &clear : nullptr);
+    }
     if (e == hipSuccess)
         e = launch_resolve(p.sp.pl, g->loc, p.rows, p.ring, st, stage(kStageResolve));
     if (ev)

@@ -136,7 +136,32 @@ struct RayParams {
     uint8_t *marks;       // as Planes::marks
     uint32_t nbytes;
     uint32_t epoch;
+    // order of the ray blocks (WalkOrder): the one a previous walk built
+    // (used if it was built for this launch's blocks), and where this walk
+    // builds the next one; null: neither
+    const int32_t *order_in;
+    int32_t *order_out;
 };
+
+// Ray wavefronts up to which a launch has at most one per SIMD (gfx950:
+// 256 compute units x 4 SIMDs) and its ray blocks go to the XCDs in ranges.
+constexpr int64_t kLoneWaves = 1024;
+
+// Order of the ray blocks of a large one-frame walk.  Every workgroup of a
+// launch runs as soon as a compute unit has room, in block order, so the
+// launch ends with the wavefronts that started last; when those are the
+// shortest, fewer SIMDs idle at the end.  So each such walk also builds, in
+// one extra workgroup, the order for the next frame's walk: its ray blocks by
+// an estimate of their walk length from this frame's pose, longest first
+// (the next frame's pose is close).  The marks do not depend on the order.
+// In scratch: two buffers (one read, one built), each a tag -- the launch
+// shape it was built for -- and a permutation of [0, ray_blocks).
+constexpr int32_t kOrderMaxBlocks = 8192;
+constexpr int32_t kOrderTagInts = 16;
+struct WalkOrderTag {
+    int32_t ray_blocks, tiles_a, tiles, tile_log2w;
+};
+constexpr size_t kOrderBufBytes = 4 * ((size_t)kOrderTagInts + kOrderMaxBlocks);
 
 // Step 5 on a ring-buffered grid: after the ring offsets moved, the voxels
 // whose grid coordinate lies in an exposed slab [lo, hi) of some axis become

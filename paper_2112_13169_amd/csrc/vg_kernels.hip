@@ -47,9 +47,6 @@ namespace vg {
 namespace {
 
 constexpr int kBlock = 256;
-// Ray wavefronts up to which a launch has at most one per SIMD (gfx950:
-// 256 compute units x 4 SIMDs) and its ray blocks go to the XCDs in ranges.
-constexpr int64_t kLoneWaves = 1024;
 // Larger walk launches give each XCD runs of this many consecutive ray blocks.
 constexpr int32_t kXcdRun = 8;
 
@@ -1037,17 +1034,117 @@ __global__ __launch_bounds__(kBlock) void k_dilate_yz_tile(Planes pl)
     dilate_yz_tile_body<kW, kTZ>(pl, blockIdx.x, blockIdx.y, lds);
 }
 
+// Walk length estimate of the pinhole target (ia, ib) from inside the grid:
+// the distance to the target or to the grid's boundary along the ray,
+// whichever is nearer, times the steps per unit length (|u_x| + |u_y| +
+// |u_z| for the unit direction u).  Only orders blocks: any value is safe.
+__device__ __forceinline__ float walk_cost(const RayParams &p, int32_t ia, int32_t ib)
+{
+    const float x = (float)(ia - p.hw), y = (float)(ib - p.hh), z = (float)p.vd;
+    float d[3];
+    ray_direction(p, ia - p.hw, ib - p.hh, p.vd, d);
+    const float len = sqrtf(x * x + y * y + z * z);
+    const float il = 1.0f / len;
+    float t = len, l1 = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float u = d[a] * il;
+        l1 += fabsf(u);
+        const float o = p.wf.o[a], n = (float)p.wf.n[a];
+        const float ta = u > 0.0f ? (n - o) / u : (u < 0.0f ? -o / u : len);
+        t = fminf(t, fmaxf(ta, 0.0f));
+    }
+    return t * l1;
+}
+
+// The extra workgroup of a walk that builds the next walk's block order
+// (WalkOrder): each ray block's estimate is the largest of its tiles' corner
+// targets', bucketed into 256 levels; a counting sort in LDS places the
+// blocks, highest level first.
+__device__ __forceinline__ void build_walk_order(const RayParams &p, int32_t nblk)
+{
+    __shared__ uint8_t key[kOrderMaxBlocks];
+    __shared__ int32_t cnt[256], pos[256];
+    const int32_t t = (int32_t)threadIdx.x;   // kBlock == 256 threads
+    cnt[t] = 0;
+    __syncthreads();
+    const int32_t tw = 1 << p.tile_log2w, th = 64 >> p.tile_log2w;
+    const float top = 1.7321f * sqrtf((float)p.hw * p.hw + (float)p.hh * p.hh +
+                                      (float)p.vd * p.vd);
+    const float scale = 255.0f / fmaxf(top, 1.0f);
+    for (int32_t j = t; j < nblk; j += kBlock) {
+        float c = 0.0f;
+        for (int32_t q = 0; q < 4; ++q) {
+            const int32_t tile = 4 * j + q;
+            if (tile >= p.tiles)
+                break;
+            const int32_t ta = tile % p.tiles_a, tb = tile / p.tiles_a;
+            const int32_t a0 = ta * tw, b0 = tb * th;
+            const int32_t a1 = min(a0 + tw, p.na) - 1, b1 = min(b0 + th, p.nb) - 1;
+            c = fmaxf(c, fmaxf(fmaxf(walk_cost(p, a0, b0), walk_cost(p, a1, b0)),
+                               fmaxf(walk_cost(p, a0, b1), walk_cost(p, a1, b1))));
+        }
+        const int32_t k = min(max((int32_t)(c * scale), 0), 255);
+        key[j] = (uint8_t)k;
+        atomicAdd(&cnt[k], 1);
+    }
+    __syncthreads();
+    // pos[k] = blocks of levels above k (Hillis-Steele over the levels from
+    // the top: thread t holds level 255 - t)
+    int32_t v = cnt[255 - t];
+    pos[t] = v;
+    __syncthreads();
+    for (int32_t off = 1; off < 256; off <<= 1) {
+        const int32_t w = t >= off ? pos[t - off] : 0;
+        __syncthreads();
+        pos[t] += w;
+        __syncthreads();
+    }
+    const int32_t excl = pos[t] - v;
+    __syncthreads();
+    cnt[255 - t] = excl;   // cnt now: next free position of each level
+    __syncthreads();
+    int32_t *out = p.order_out + kOrderTagInts;
+    for (int32_t j = t; j < nblk; j += kBlock)
+        out[atomicAdd(&cnt[key[j]], 1)] = j;
+    if (t == 0) {
+        WalkOrderTag *tag = reinterpret_cast<WalkOrderTag *>(p.order_out);
+        tag->ray_blocks = nblk;
+        tag->tiles_a = p.tiles_a;
+        tag->tiles = p.tiles;
+        tag->tile_log2w = p.tile_log2w;
+    }
+}
+
+// The ray block that takes position rb: the previous walk's order if it was
+// built for this launch's blocks, else rb.
+__device__ __forceinline__ int32_t ordered_block(const RayParams &p, int32_t nblk, int32_t rb)
+{
+    const WalkOrderTag tag = *reinterpret_cast<const WalkOrderTag *>(p.order_in);
+    if (tag.ray_blocks != nblk || tag.tiles_a != p.tiles_a || tag.tiles != p.tiles ||
+        tag.tile_log2w != p.tile_log2w)
+        return rb;
+    return p.order_in[kOrderTagInts + rb];
+}
+
 // The walk; workgroups from ray_blocks on run the slab clear c instead (the
 // walk leaves most compute units idle for its longest rays).  kLone: the walk
 // form that overlaps each chunk's loads with the next chunk's steps.
 template <bool kGeneral, bool kBytes, bool kLone>
 __global__ __launch_bounds__(kBlock) void k_rays(RayParams p, SlabClear c, int32_t ray_blocks)
 {
-    if ((int32_t)blockIdx.x >= ray_blocks) {
-        clear_body(c, (int64_t)(blockIdx.x - ray_blocks) * kBlock + threadIdx.x);
+    int32_t rb = (int32_t)blockIdx.x;
+    if (p.order_out) {   // workgroup 0 builds the next walk's order
+        if (rb == 0) {
+            build_walk_order(p, ray_blocks);
+            return;
+        }
+        --rb;
+    }
+    if (rb >= ray_blocks) {
+        clear_body(c, (int64_t)(rb - ray_blocks) * kBlock + threadIdx.x);
         return;
     }
-    int32_t rb = (int32_t)blockIdx.x;
     if (kLone && (int64_t)ray_blocks * (kBlock / 64) <= kLoneWaves) {
         // Workgroups go to the 8 XCDs in turn.  With every ray wavefront
         // resident at once, each XCD takes a contiguous range of ray blocks,
@@ -1058,6 +1155,8 @@ __global__ __launch_bounds__(kBlock) void k_rays(RayParams p, SlabClear c, int32
         rb = xcd * q + min(xcd, rem) + rb / 8;
     } else {
         rb = xcd_runs(rb, ray_blocks);
+        if (p.order_in)
+            rb = ordered_block(p, ray_blocks, rb);
     }
     rays_body<kGeneral, kBytes, kLone>(p, rb * (kBlock / 64) + (threadIdx.x >> 6));
 }
@@ -1270,8 +1369,8 @@ hipError_t launch_rays(const RayParams &p, bool camera_inside, hipStream_t st,
         c = *clear;
         clear_blocks = blocks_for(clear_lanes(c));
     }
-    const uint32_t blocks = (uint32_t)(ray_blocks + clear_blocks);
-    if (blocks == 0)
+    const uint32_t blocks = (uint32_t)(ray_blocks + clear_blocks) + (p.order_out ? 1u : 0u);
+    if (ray_blocks + clear_blocks == 0)
         return record_empty_stage(ev, st);
     // the camera inside the grid: the walk form that keeps its loads in
     // flight; from outside, every step takes the tested path anyway

@@ -248,3 +248,26 @@ def test_fp32_canary_denormal_coordinates():
                                 intr["fov_y"], intr["depth_max"], R, t)
         tw.check(f"denormal canary, {name}")
         tw.close()
+
+
+def test_walk_block_order_across_frames_and_tile_shapes():
+    """Large one-frame walks take their ray blocks in the order the previous
+    walk of the grid built (longest estimated walks first); the order is only
+    used for the launch shape it was built for.  Frames of the large pinhole
+    sequence into one grid, re-centred before each, with the ray tile
+    changed between some of them (an order built for another shape is not
+    used) and kept between others (it is): every grid equals the oracle's."""
+    traj = scenes.make_trajectory("large-pinhole", n_frames=60)
+    first = scenes.trajectory_frame(traj, 0)
+    t = Twin(first.dims, first.vox_size, first.origin, first.vox_inf)
+    sensor = vg.pinhole_sensor(first.intr)
+    for i, tile in [(0, 2), (10, 2), (20, 3), (30, 3), (40, 2), (50, 2)]:
+        fr = first if i == 0 else scenes.trajectory_frame(traj, i)
+        vg.vg_set_ray_tile(t.h, tile)
+        d = oracle.center_offset(fr.dims, fr.vox_size, t.origin(), fr.t)
+        _say(f"block order: frame {i} ray tile {tile} shift {d}")
+        df = DevFrame(t, fr)
+        vg.vg_integrate_frame_shifted(t.h, df.data, sensor, vg.make_pose(fr.R, fr.t), d)
+        t.oracle_frame(fr, d)
+        t.check(f"block order frame {i}")
+    t.close()
