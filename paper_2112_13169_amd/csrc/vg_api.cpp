@@ -53,7 +53,7 @@ Layout layout_for(int32_t gx, int32_t gy, int32_t gz, int32_t r)
     l.hz = l.marks + align_up((size_t)2 * l.gxp * gy * gz);
     l.lim = l.hz + kHzBytes;
     l.order = l.lim + align_up(sizeof(RowLimits));
-    l.fixed = l.order + align_up(2 * kOrderBufBytes);
+    l.fixed = l.order + align_up(kOrderBytes);
     return l;
 }
 
@@ -145,7 +145,6 @@ struct vg_grid {
     size_t scratch_bytes;
     Layout lay;
     uint32_t epoch;          // stamp of the last frame, 0 = none yet
-    uint32_t order_flip = 0; // which walk-order buffer (plane set 0) the next walk reads
     int device;
     int32_t sets = 1;        // plane sets in scratch, lay.fixed bytes apart
     // spinning fan table currently in each set
@@ -590,7 +589,6 @@ vg_status plan_frame(const vg_grid *g, const GridState &gs, int kind, const floa
     rp.nbytes = pl.nbytes;
     rp.epoch = p.epoch;
     rp.order_in = nullptr;
-    rp.order_out = nullptr;
     p.inside = v0[0] >= 0 && v0[0] < g->n[0] && v0[1] >= 0 && v0[1] < g->n[1] && v0[2] >= 0 &&
                v0[2] < g->n[2];
 
@@ -677,19 +675,23 @@ bool shift_in_range(const vg_grid *g, const int32_t d[3])
 }
 
 // A pinhole walk from inside the grid with more ray wavefronts than the GPU
-// has SIMDs (and no more blocks than an order holds) reads the block order
-// the previous such walk of the grid built and builds the next one
-// (WalkOrder); the two buffers of plane set 0 alternate.
-void use_walk_order(vg_grid *g, FramePlan &p)
+// has SIMDs (and no more blocks than an order holds) takes its ray blocks in
+// the order its frame's x dilation launch builds (WalkOrder), in plane set 0.
+void use_walk_order(vg_grid *g, FramePlan &p, OrderBuild &ob)
 {
+    ob.order = nullptr;
     const int64_t ray_blocks = ((int64_t)p.rp.tiles + 3) / 4;
-    if (p.rp.kind != kPinhole || !p.inside || ray_blocks * 4 <= kLoneWaves ||
+    if (p.rp.kind != kPinhole || !p.inside || p.direct || ray_blocks * 4 <= kLoneWaves ||
         ray_blocks > kOrderMaxBlocks)
         return;
     uint8_t *base = g->scratch + g->lay.order;
-    const uint32_t f = g->order_flip++ & 1u;
-    p.rp.order_in = reinterpret_cast<const int32_t *>(base + kOrderBufBytes * f);
-    p.rp.order_out = reinterpret_cast<int32_t *>(base + kOrderBufBytes * (1u - f));
+    p.rp.order_in = reinterpret_cast<const int32_t *>(base);
+    ob.rp = p.rp;
+    ob.ray_blocks = (int32_t)ray_blocks;
+    ob.parts = kOrderMaxParts;
+    ob.order = reinterpret_cast<int32_t *>(base);
+    ob.keys = base + kOrderBufBytes;
+    ob.counts = reinterpret_cast<int32_t *>(base + kOrderBufBytes + kOrderKeyBytes);
 }
 
 // Steps 2-4 of one frame, after the shift d (step 5) if d is given and not
@@ -724,15 +726,15 @@ vg_status integrate(vg_grid *g, int kind, const float *data, int64_t pitch_float
     auto stage = [&](int k) -> const StageEvents & { return ev ? ev[k] : none; };
     if (d)   // the shift's own pair: markers (its clear is timed with the walk)
         e = record_empty_stage(stage(kStageShift), st);
+    OrderBuild ob;
+    use_walk_order(g, p, ob);
     if (e == hipSuccess)
-        e = launch_seeds(p.sp, st, stage(kStageSeed));
+        e = launch_seeds(p.sp, st, stage(kStageSeed), &ob);
     if (e == hipSuccess)   // direct stamping has nothing to dilate
         e = p.direct ? record_empty_stage(stage(kStageDilate), st)
-                     : launch_dilate(p.sp.pl, st, stage(kStageDilate));
-    if (e == hipSuccess) {
-        use_walk_order(g, p);
+                     : launch_dilate(p.sp.pl, st, stage(kStageDilate), &ob);
+    if (e == hipSuccess)
         e = launch_rays(p.rp, p.inside, st, stage(kStageRays), shifted ? &clear : nullptr);
-    }
     if (e == hipSuccess)
         e = launch_resolve(p.sp.pl, g->loc, p.rows, p.ring, st, stage(kStageResolve));
     if (ev)

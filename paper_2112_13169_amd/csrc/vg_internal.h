@@ -136,11 +136,9 @@ struct RayParams {
     uint8_t *marks;       // as Planes::marks
     uint32_t nbytes;
     uint32_t epoch;
-    // order of the ray blocks (WalkOrder): the one a previous walk built
-    // (used if it was built for this launch's blocks), and where this walk
-    // builds the next one; null: neither
+    // order of the ray blocks (WalkOrder), used if it was built for this
+    // launch's blocks; null: block order
     const int32_t *order_in;
-    int32_t *order_out;
 };
 
 // Ray wavefronts up to which a launch has at most one per SIMD (gfx950:
@@ -150,18 +148,38 @@ constexpr int64_t kLoneWaves = 1024;
 // Order of the ray blocks of a large one-frame walk.  Every workgroup of a
 // launch runs as soon as a compute unit has room, in block order, so the
 // launch ends with the wavefronts that started last; when those are the
-// shortest, fewer SIMDs idle at the end.  So each such walk also builds, in
-// one extra workgroup, the order for the next frame's walk: its ray blocks by
-// an estimate of their walk length from this frame's pose, longest first
-// (the next frame's pose is close).  The marks do not depend on the order.
-// In scratch: two buffers (one read, one built), each a tag -- the launch
-// shape it was built for -- and a permutation of [0, ray_blocks).
+// shortest, fewer SIMDs idle at the end.  So the frame's earlier launches
+// also build the order in which its walk takes the ray blocks: by an
+// estimate of each block's walk length from the frame's pose, longest first.
+// The seed launch's extra workgroups rate the blocks (a level per block, and
+// each workgroup's count of every level); one extra workgroup of the x
+// dilation launch sorts them by level (the launch boundary orders the two).
+// The marks do not depend on the order.  In scratch (plane set 0): a tag --
+// the launch shape the order was built for, 0 while none is valid -- and a
+// permutation of [0, ray_blocks); then the levels and the counts.
 constexpr int32_t kOrderMaxBlocks = 8192;
 constexpr int32_t kOrderTagInts = 16;
+constexpr int32_t kOrderMaxParts = 64;   // rating workgroups
+constexpr int32_t kOrderLevels = 256;
 struct WalkOrderTag {
     int32_t ray_blocks, tiles_a, tiles, tile_log2w;
 };
 constexpr size_t kOrderBufBytes = 4 * ((size_t)kOrderTagInts + kOrderMaxBlocks);
+constexpr size_t kOrderKeyBytes = kOrderMaxBlocks;
+constexpr size_t kOrderCountBytes = 4 * (size_t)kOrderMaxParts * kOrderLevels;
+constexpr size_t kOrderBytes = kOrderBufBytes + kOrderKeyBytes + kOrderCountBytes;
+
+// A walk-order build: the walk's parameters and ray blocks, the rating
+// workgroups (parts), and where the order (tag + blocks), the levels and
+// the counts ([parts][kOrderLevels]) go; order null: none.
+struct OrderBuild {
+    RayParams rp;
+    int32_t ray_blocks;
+    int32_t parts;
+    int32_t *order;
+    uint8_t *keys;
+    int32_t *counts;
+};
 
 // Step 5 on a ring-buffered grid: after the ring offsets moved, the voxels
 // whose grid coordinate lies in an exposed slab [lo, hi) of some axis become
@@ -289,9 +307,11 @@ struct StageEvents {
 };
 
 hipError_t launch_fill(void *dst, uint8_t value, size_t bytes, hipStream_t st);
-hipError_t launch_seeds(const SeedParams &p, hipStream_t st, const StageEvents &ev = {});
+hipError_t launch_seeds(const SeedParams &p, hipStream_t st, const StageEvents &ev = {},
+                        const OrderBuild *order = nullptr);
 // Seeds -> occupied bit plane (dilation by vox_inf along x, then y and z).
-hipError_t launch_dilate(const Planes &pl, hipStream_t st, const StageEvents &ev = {});
+hipError_t launch_dilate(const Planes &pl, hipStream_t st, const StageEvents &ev = {},
+                         const OrderBuild *order = nullptr);
 // The walk of every fan ray.  camera_inside: the camera voxel lies in the grid.
 // clear (optional): a slab clear of the local grid run by extra workgroups of
 // the same launch (it touches no memory the walk uses).

@@ -1011,15 +1011,192 @@ __device__ __forceinline__ void clear_body(const SlabClear &c, int64_t gid)
 
 // ------------------------------------------------------- one-frame kernels
 
-__global__ __launch_bounds__(kBlock) void k_seed(SeedParams p)
+// Walk length estimate of the pinhole target (ia, ib) from inside the grid:
+// the distance to the target or to the grid's boundary along the ray,
+// whichever is nearer, times the steps per unit length (|u_x| + |u_y| +
+// |u_z| for the unit direction u).  It only orders blocks, so approximate
+// reciprocals do.
+__device__ __forceinline__ float walk_cost(const RayParams &p, int32_t ia, int32_t ib)
 {
-    seed_body(p, blockIdx.x, blockIdx.y);
+    const float x = (float)(ia - p.hw), y = (float)(ib - p.hh), z = (float)p.vd;
+    float d[3];
+    ray_direction(p, ia - p.hw, ib - p.hh, p.vd, d);
+    const float len = sqrtf(x * x + y * y + z * z);
+    const float il = __builtin_amdgcn_rcpf(len);
+    float t = len, l1 = 0.0f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float u = d[a] * il;
+        l1 += fabsf(u);
+        const float o = p.wf.o[a], n = (float)p.wf.n[a];
+        const float ta = u > 0.0f   ? (n - o) * __builtin_amdgcn_rcpf(u)
+                         : u < 0.0f ? -o * __builtin_amdgcn_rcpf(u)
+                                    : len;
+        t = fminf(t, fmaxf(ta, 0.0f));
+    }
+    return t * l1;
 }
 
-template <bool kWide>
-__global__ __launch_bounds__(kBlock) void k_dilate_x(Planes pl)
+// Rating workgroup `part` (< ob.parts) of a walk-order build (WalkOrder):
+// the level of each of its ray blocks -- the highest walk-length estimate at
+// the corner targets of the block's tiles (of the box of its four tiles
+// where they share a row of tiles), in kOrderLevels steps -- and its count of
+// every level, in its own row of the counts.  Four consecutive lanes take the
+// four corners of a block.
+__device__ __forceinline__ void rate_walk_blocks(const OrderBuild &ob, int32_t part)
 {
-    dilate_x_body<kWide>(pl, (int64_t)blockIdx.x * kBlock + threadIdx.x);
+    __shared__ int32_t cnt[kOrderLevels];
+    const RayParams &p = ob.rp;
+    const int32_t t = (int32_t)threadIdx.x;   // kBlock == kOrderLevels threads
+    const int32_t tw = 1 << p.tile_log2w, th = 64 >> p.tile_log2w;
+    const float top = 1.7321f * sqrtf((float)p.hw * p.hw + (float)p.hh * p.hh +
+                                      (float)p.vd * p.vd);
+    const float scale = (float)(kOrderLevels - 1) / fmaxf(top, 1.0f);
+    cnt[t] = 0;
+    __syncthreads();
+    const int32_t corner = t & 3;
+    const int32_t per = ob.parts * (kBlock / 4);   // blocks per round of the parts
+    // every lane runs the same rounds (the shuffles need all four lanes)
+    for (int32_t j0 = part * (kBlock / 4); j0 < ob.ray_blocks; j0 += per) {
+        const int32_t j = j0 + (t >> 2);
+        float c = 0.0f;
+        if (j < ob.ray_blocks) {
+            const int32_t first = 4 * j, lastt = min(4 * j + 3, p.tiles - 1);
+            if (first / p.tiles_a == lastt / p.tiles_a) {   // one row of tiles: the box
+                const int32_t a0 = (first % p.tiles_a) * tw, b0 = (first / p.tiles_a) * th;
+                const int32_t a1 = min((lastt % p.tiles_a + 1) * tw, p.na) - 1;
+                const int32_t b1 = min(b0 + th, p.nb) - 1;
+                c = walk_cost(p, corner & 1 ? a1 : a0, corner & 2 ? b1 : b0);
+            } else {   // across two rows of tiles: each lane one tile's corners
+                const int32_t tile = first + corner;
+                if (tile <= lastt) {
+                    const int32_t a0 = (tile % p.tiles_a) * tw, b0 = (tile / p.tiles_a) * th;
+                    const int32_t a1 = min(a0 + tw, p.na) - 1, b1 = min(b0 + th, p.nb) - 1;
+                    c = fmaxf(fmaxf(walk_cost(p, a0, b0), walk_cost(p, a1, b0)),
+                              fmaxf(walk_cost(p, a0, b1), walk_cost(p, a1, b1)));
+                }
+            }
+        }
+        c = fmaxf(c, __shfl_xor(c, 1));
+        c = fmaxf(c, __shfl_xor(c, 2));
+        if (j < ob.ray_blocks && corner == 0) {
+            const int32_t k = min(max((int32_t)(c * scale), 0), kOrderLevels - 1);
+            ob.keys[j] = (uint8_t)k;
+            atomicAdd(&cnt[k], 1);
+        }
+    }
+    __syncthreads();
+    ob.counts[part * kOrderLevels + t] = cnt[t];
+}
+
+// The sorting workgroup of a walk-order build, in the launch after the
+// rating one: every block by level, highest first (a counting sort over the
+// parts' counts), then the tag.  A total other than the blocks' leaves no
+// valid order.
+__device__ __forceinline__ void sort_walk_blocks(const OrderBuild &ob)
+{
+    __shared__ int32_t cnt[kOrderLevels], pos[kOrderLevels];
+    const RayParams &p = ob.rp;
+    const int32_t nblk = ob.ray_blocks;
+    const int32_t t = (int32_t)threadIdx.x;   // kBlock == kOrderLevels threads
+    WalkOrderTag *tag = reinterpret_cast<WalkOrderTag *>(ob.order);
+    if (t == 0)
+        tag->ray_blocks = 0;   // no valid order while it is rewritten
+    // pos[k] = blocks of levels above k (Hillis-Steele over the levels from
+    // the top: thread t holds level kOrderLevels - 1 - t)
+    // the parts' counts of level kOrderLevels - 1 - t: 16 loads at a time, at
+    // clamped rows (no branch, so that they issue together)
+    int32_t v = 0;
+    for (int32_t q0 = 0; q0 < ob.parts; q0 += 16) {
+        int32_t x[16];
+#pragma unroll
+        for (int32_t q = 0; q < 16; ++q)
+            x[q] = ob.counts[min(q0 + q, ob.parts - 1) * kOrderLevels + kOrderLevels - 1 - t];
+#pragma unroll
+        for (int32_t q = 0; q < 16; ++q)
+            v += q0 + q < ob.parts ? x[q] : 0;
+    }
+    pos[t] = v;
+    __syncthreads();
+    for (int32_t off = 1; off < kOrderLevels; off <<= 1) {
+        const int32_t w = t >= off ? pos[t - off] : 0;
+        __syncthreads();
+        pos[t] += w;
+        __syncthreads();
+    }
+    const bool whole = pos[kOrderLevels - 1] == nblk;   // every block counted once
+    cnt[kOrderLevels - 1 - t] = pos[t] - v;   // next free position of each level
+    __syncthreads();
+    if (!whole)
+        return;
+    int32_t *out = ob.order + kOrderTagInts;
+    for (int32_t j0 = t; j0 < nblk; j0 += 8 * kBlock) {
+        // eight levels at a time, at clamped indices, so that the loads issue
+        // together
+        uint32_t kk[8];
+#pragma unroll
+        for (int32_t q = 0; q < 8; ++q)
+            kk[q] = ob.keys[min(j0 + q * kBlock, nblk - 1)];
+#pragma unroll
+        for (int32_t q = 0; q < 8; ++q) {
+            const int32_t j = j0 + q * kBlock;
+            if (j < nblk) {
+                const int32_t at = atomicAdd(&cnt[kk[q]], 1);
+                if (at < nblk)
+                    out[at] = j;
+            }
+        }
+    }
+    __syncthreads();
+    if (t == 0) {
+        tag->tiles_a = p.tiles_a;
+        tag->tiles = p.tiles;
+        tag->tile_log2w = p.tile_log2w;
+        tag->ray_blocks = nblk;
+    }
+}
+
+// The ray block that takes position rb: the frame's order if it was built
+// for this launch's blocks, else rb.
+__device__ __forceinline__ int32_t ordered_block(const RayParams &p, int32_t nblk, int32_t rb)
+{
+    const WalkOrderTag tag = *reinterpret_cast<const WalkOrderTag *>(p.order_in);
+    if (tag.ray_blocks != nblk || tag.tiles_a != p.tiles_a || tag.tiles != p.tiles ||
+        tag.tile_log2w != p.tile_log2w)
+        return rb;
+    return p.order_in[kOrderTagInts + rb];
+}
+
+// The seed pass; with ob.order, an extra row of workgroups rates the walk's
+// ray blocks instead.
+__global__ __launch_bounds__(kBlock) void k_seed(SeedParams p, OrderBuild ob)
+{
+    int32_t by = (int32_t)blockIdx.y;
+    if (ob.order) {   // the first row, so that it runs beside the seeds
+        if (by == 0) {
+            if ((int32_t)blockIdx.x < ob.parts)
+                rate_walk_blocks(ob, (int32_t)blockIdx.x);
+            return;
+        }
+        --by;
+    }
+    seed_body(p, blockIdx.x, by);
+}
+
+// The x dilation; with ob.order, workgroup 0 sorts the frame's walk order
+// instead.
+template <bool kWide>
+__global__ __launch_bounds__(kBlock) void k_dilate_x(Planes pl, OrderBuild ob)
+{
+    int32_t b = (int32_t)blockIdx.x;
+    if (ob.order) {
+        if (b == 0) {
+            sort_walk_blocks(ob);
+            return;
+        }
+        --b;
+    }
+    dilate_x_body<kWide>(pl, (int64_t)b * kBlock + threadIdx.x);
 }
 
 __global__ __launch_bounds__(kBlock) void k_dilate_yz(Planes pl)
@@ -1034,99 +1211,6 @@ __global__ __launch_bounds__(kBlock) void k_dilate_yz_tile(Planes pl)
     dilate_yz_tile_body<kW, kTZ>(pl, blockIdx.x, blockIdx.y, lds);
 }
 
-// Walk length estimate of the pinhole target (ia, ib) from inside the grid:
-// the distance to the target or to the grid's boundary along the ray,
-// whichever is nearer, times the steps per unit length (|u_x| + |u_y| +
-// |u_z| for the unit direction u).  Only orders blocks: any value is safe.
-__device__ __forceinline__ float walk_cost(const RayParams &p, int32_t ia, int32_t ib)
-{
-    const float x = (float)(ia - p.hw), y = (float)(ib - p.hh), z = (float)p.vd;
-    float d[3];
-    ray_direction(p, ia - p.hw, ib - p.hh, p.vd, d);
-    const float len = sqrtf(x * x + y * y + z * z);
-    const float il = 1.0f / len;
-    float t = len, l1 = 0.0f;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const float u = d[a] * il;
-        l1 += fabsf(u);
-        const float o = p.wf.o[a], n = (float)p.wf.n[a];
-        const float ta = u > 0.0f ? (n - o) / u : (u < 0.0f ? -o / u : len);
-        t = fminf(t, fmaxf(ta, 0.0f));
-    }
-    return t * l1;
-}
-
-// The extra workgroup of a walk that builds the next walk's block order
-// (WalkOrder): each ray block's estimate is the largest of its tiles' corner
-// targets', bucketed into 256 levels; a counting sort in LDS places the
-// blocks, highest level first.
-__device__ __forceinline__ void build_walk_order(const RayParams &p, int32_t nblk)
-{
-    __shared__ uint8_t key[kOrderMaxBlocks];
-    __shared__ int32_t cnt[256], pos[256];
-    const int32_t t = (int32_t)threadIdx.x;   // kBlock == 256 threads
-    cnt[t] = 0;
-    __syncthreads();
-    const int32_t tw = 1 << p.tile_log2w, th = 64 >> p.tile_log2w;
-    const float top = 1.7321f * sqrtf((float)p.hw * p.hw + (float)p.hh * p.hh +
-                                      (float)p.vd * p.vd);
-    const float scale = 255.0f / fmaxf(top, 1.0f);
-    for (int32_t j = t; j < nblk; j += kBlock) {
-        float c = 0.0f;
-        for (int32_t q = 0; q < 4; ++q) {
-            const int32_t tile = 4 * j + q;
-            if (tile >= p.tiles)
-                break;
-            const int32_t ta = tile % p.tiles_a, tb = tile / p.tiles_a;
-            const int32_t a0 = ta * tw, b0 = tb * th;
-            const int32_t a1 = min(a0 + tw, p.na) - 1, b1 = min(b0 + th, p.nb) - 1;
-            c = fmaxf(c, fmaxf(fmaxf(walk_cost(p, a0, b0), walk_cost(p, a1, b0)),
-                               fmaxf(walk_cost(p, a0, b1), walk_cost(p, a1, b1))));
-        }
-        const int32_t k = min(max((int32_t)(c * scale), 0), 255);
-        key[j] = (uint8_t)k;
-        atomicAdd(&cnt[k], 1);
-    }
-    __syncthreads();
-    // pos[k] = blocks of levels above k (Hillis-Steele over the levels from
-    // the top: thread t holds level 255 - t)
-    int32_t v = cnt[255 - t];
-    pos[t] = v;
-    __syncthreads();
-    for (int32_t off = 1; off < 256; off <<= 1) {
-        const int32_t w = t >= off ? pos[t - off] : 0;
-        __syncthreads();
-        pos[t] += w;
-        __syncthreads();
-    }
-    const int32_t excl = pos[t] - v;
-    __syncthreads();
-    cnt[255 - t] = excl;   // cnt now: next free position of each level
-    __syncthreads();
-    int32_t *out = p.order_out + kOrderTagInts;
-    for (int32_t j = t; j < nblk; j += kBlock)
-        out[atomicAdd(&cnt[key[j]], 1)] = j;
-    if (t == 0) {
-        WalkOrderTag *tag = reinterpret_cast<WalkOrderTag *>(p.order_out);
-        tag->ray_blocks = nblk;
-        tag->tiles_a = p.tiles_a;
-        tag->tiles = p.tiles;
-        tag->tile_log2w = p.tile_log2w;
-    }
-}
-
-// The ray block that takes position rb: the previous walk's order if it was
-// built for this launch's blocks, else rb.
-__device__ __forceinline__ int32_t ordered_block(const RayParams &p, int32_t nblk, int32_t rb)
-{
-    const WalkOrderTag tag = *reinterpret_cast<const WalkOrderTag *>(p.order_in);
-    if (tag.ray_blocks != nblk || tag.tiles_a != p.tiles_a || tag.tiles != p.tiles ||
-        tag.tile_log2w != p.tile_log2w)
-        return rb;
-    return p.order_in[kOrderTagInts + rb];
-}
-
 // The walk; workgroups from ray_blocks on run the slab clear c instead (the
 // walk leaves most compute units idle for its longest rays).  kLone: the walk
 // form that overlaps each chunk's loads with the next chunk's steps.
@@ -1134,13 +1218,6 @@ template <bool kGeneral, bool kBytes, bool kLone>
 __global__ __launch_bounds__(kBlock) void k_rays(RayParams p, SlabClear c, int32_t ray_blocks)
 {
     int32_t rb = (int32_t)blockIdx.x;
-    if (p.order_out) {   // workgroup 0 builds the next walk's order
-        if (rb == 0) {
-            build_walk_order(p, ray_blocks);
-            return;
-        }
-        --rb;
-    }
     if (rb >= ray_blocks) {
         clear_body(c, (int64_t)(rb - ray_blocks) * kBlock + threadIdx.x);
         return;
@@ -1311,18 +1388,27 @@ hipError_t record_empty_stage(const StageEvents &ev, hipStream_t st)
     return e;
 }
 
-hipError_t launch_seeds(const SeedParams &p, hipStream_t st, const StageEvents &ev)
+hipError_t launch_seeds(const SeedParams &p, hipStream_t st, const StageEvents &ev,
+                        const OrderBuild *order)
 {
     dim3 grid;
     if (p.kind == kPoints)
         grid = dim3(std::max<uint32_t>(blocks_for(p.W), 1u), 1);
     else
         grid = dim3((uint32_t)std::max((p.W + 63) / 64, 1), (uint32_t)std::max((p.H + 3) / 4, 1));
-    hipExtLaunchKernelGGL(k_seed, grid, dim3(kBlock), 0, st, ev.start, ev.stop, 0, p);
+    OrderBuild ob{};
+    if (order && order->order) {
+        // an extra row of workgroups rates the walk's blocks
+        ob = *order;
+        ob.parts = (int32_t)std::min<uint32_t>(grid.x, (uint32_t)kOrderMaxParts);
+        grid.y += 1;
+    }
+    hipExtLaunchKernelGGL(k_seed, grid, dim3(kBlock), 0, st, ev.start, ev.stop, 0, p, ob);
     return hipGetLastError();
 }
 
-hipError_t launch_dilate(const Planes &pl, hipStream_t st, const StageEvents &ev)
+hipError_t launch_dilate(const Planes &pl, hipStream_t st, const StageEvents &ev,
+                         const OrderBuild *order)
 {
     const bool any = pl.lo[0] <= pl.hi[0] && pl.lo[1] <= pl.hi[1] && pl.lo[2] <= pl.hi[2];
     hipEvent_t start = ev.start;
@@ -1330,9 +1416,12 @@ hipError_t launch_dilate(const Planes &pl, hipStream_t st, const StageEvents &ev
         const int64_t rows = (int64_t)(pl.hi[1] - pl.lo[1] + 1) * (pl.hi[2] - pl.lo[2] + 1);
         const bool wide = dilate_x_wide((int64_t)pl.wx * rows);
         const int64_t n = (int64_t)dilate_x_lanes(pl.wx, wide) * rows;
-        hipExtLaunchKernelGGL(wide ? k_dilate_x<true> : k_dilate_x<false>, dim3(blocks_for(n)),
-                              dim3(kBlock), 0, st, start,
-                              (hipEvent_t) nullptr, 0, pl);
+        OrderBuild ob{};
+        if (order && order->order)
+            ob = *order;
+        hipExtLaunchKernelGGL(wide ? k_dilate_x<true> : k_dilate_x<false>,
+                              dim3(blocks_for(n) + (ob.order ? 1u : 0u)), dim3(kBlock), 0, st,
+                              start, (hipEvent_t) nullptr, 0, pl, ob);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess)
             return e;
@@ -1369,8 +1458,8 @@ hipError_t launch_rays(const RayParams &p, bool camera_inside, hipStream_t st,
         c = *clear;
         clear_blocks = blocks_for(clear_lanes(c));
     }
-    const uint32_t blocks = (uint32_t)(ray_blocks + clear_blocks) + (p.order_out ? 1u : 0u);
-    if (ray_blocks + clear_blocks == 0)
+    const uint32_t blocks = (uint32_t)(ray_blocks + clear_blocks);
+    if (blocks == 0)
         return record_empty_stage(ev, st);
     // the camera inside the grid: the walk form that keeps its loads in
     // flight; from outside, every step takes the tested path anyway
