@@ -691,7 +691,6 @@ void use_walk_order(vg_grid *g, FramePlan &p, OrderBuild &ob)
     ob.parts = kOrderMaxParts;
     ob.order = reinterpret_cast<int32_t *>(base);
     ob.keys = base + kOrderBufBytes;
-    ob.counts = reinterpret_cast<int32_t *>(base + kOrderBufBytes + kOrderKeyBytes);
 }
 
 // Steps 2-4 of one frame, after the shift d (step 5) if d is given and not

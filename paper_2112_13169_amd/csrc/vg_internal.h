@@ -151,12 +151,12 @@ constexpr int64_t kLoneWaves = 1024;
 // shortest, fewer SIMDs idle at the end.  So the frame's earlier launches
 // also build the order in which its walk takes the ray blocks: by an
 // estimate of each block's walk length from the frame's pose, longest first.
-// The seed launch's extra workgroups rate the blocks (a level per block, and
-// each workgroup's count of every level); one extra workgroup of the x
-// dilation launch sorts them by level (the launch boundary orders the two).
+// The seed launch's extra workgroups rate the blocks (a level per block);
+// one extra workgroup of the x dilation launch sorts them, in runs that keep
+// the XCD runs of the walk's blocks (the launch boundary orders the two).
 // The marks do not depend on the order.  In scratch (plane set 0): a tag --
 // the launch shape the order was built for, 0 while none is valid -- and a
-// permutation of [0, ray_blocks); then the levels and the counts.
+// permutation of [0, ray_blocks); then the levels.
 constexpr int32_t kOrderMaxBlocks = 8192;
 constexpr int32_t kOrderTagInts = 16;
 constexpr int32_t kOrderMaxParts = 64;   // rating workgroups
@@ -166,19 +166,17 @@ struct WalkOrderTag {
 };
 constexpr size_t kOrderBufBytes = 4 * ((size_t)kOrderTagInts + kOrderMaxBlocks);
 constexpr size_t kOrderKeyBytes = kOrderMaxBlocks;
-constexpr size_t kOrderCountBytes = 4 * (size_t)kOrderMaxParts * kOrderLevels;
-constexpr size_t kOrderBytes = kOrderBufBytes + kOrderKeyBytes + kOrderCountBytes;
+constexpr size_t kOrderBytes = kOrderBufBytes + kOrderKeyBytes;
 
 // A walk-order build: the walk's parameters and ray blocks, the rating
-// workgroups (parts), and where the order (tag + blocks), the levels and
-// the counts ([parts][kOrderLevels]) go; order null: none.
+// workgroups (parts), and where the order (tag + blocks) and the levels go;
+// order null: none.
 struct OrderBuild {
     RayParams rp;
     int32_t ray_blocks;
     int32_t parts;
     int32_t *order;
     uint8_t *keys;
-    int32_t *counts;
 };
 
 // Step 5 on a ring-buffered grid: after the ring offsets moved, the voxels

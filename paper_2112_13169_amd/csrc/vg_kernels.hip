@@ -48,7 +48,7 @@ namespace {
 
 constexpr int kBlock = 256;
 // Larger walk launches give each XCD runs of this many consecutive ray blocks.
-constexpr int32_t kXcdRun = 8;
+constexpr int32_t kXcdRun = 4;
 
 // ----------------------------------------------------------------- helpers
 
@@ -1040,20 +1040,16 @@ __device__ __forceinline__ float walk_cost(const RayParams &p, int32_t ia, int32
 // Rating workgroup `part` (< ob.parts) of a walk-order build (WalkOrder):
 // the level of each of its ray blocks -- the highest walk-length estimate at
 // the corner targets of the block's tiles (of the box of its four tiles
-// where they share a row of tiles), in kOrderLevels steps -- and its count of
-// every level, in its own row of the counts.  Four consecutive lanes take the
-// four corners of a block.
+// where they share a row of tiles), in kOrderLevels steps.  Four consecutive
+// lanes take the four corners of a block.
 __device__ __forceinline__ void rate_walk_blocks(const OrderBuild &ob, int32_t part)
 {
-    __shared__ int32_t cnt[kOrderLevels];
     const RayParams &p = ob.rp;
-    const int32_t t = (int32_t)threadIdx.x;   // kBlock == kOrderLevels threads
+    const int32_t t = (int32_t)threadIdx.x;
     const int32_t tw = 1 << p.tile_log2w, th = 64 >> p.tile_log2w;
     const float top = 1.7321f * sqrtf((float)p.hw * p.hw + (float)p.hh * p.hh +
                                       (float)p.vd * p.vd);
     const float scale = (float)(kOrderLevels - 1) / fmaxf(top, 1.0f);
-    cnt[t] = 0;
-    __syncthreads();
     const int32_t corner = t & 3;
     const int32_t per = ob.parts * (kBlock / 4);   // blocks per round of the parts
     // every lane runs the same rounds (the shuffles need all four lanes)
@@ -1079,43 +1075,50 @@ __device__ __forceinline__ void rate_walk_blocks(const OrderBuild &ob, int32_t p
         }
         c = fmaxf(c, __shfl_xor(c, 1));
         c = fmaxf(c, __shfl_xor(c, 2));
-        if (j < ob.ray_blocks && corner == 0) {
-            const int32_t k = min(max((int32_t)(c * scale), 0), kOrderLevels - 1);
-            ob.keys[j] = (uint8_t)k;
-            atomicAdd(&cnt[k], 1);
-        }
+        if (j < ob.ray_blocks && corner == 0)
+            ob.keys[j] = (uint8_t)min(max((int32_t)(c * scale), 0), kOrderLevels - 1);
     }
-    __syncthreads();
-    ob.counts[part * kOrderLevels + t] = cnt[t];
 }
 
 // The sorting workgroup of a walk-order build, in the launch after the
-// rating one: every block by level, highest first (a counting sort over the
-// parts' counts), then the tag.  A total other than the blocks' leaves no
-// valid order.
+// rating one.  It orders runs of kXcdRun consecutive blocks, not blocks, so
+// that each run still lands on one XCD (xcd_runs deals positions out in such
+// runs): every whole run by its highest level, highest first (a counting sort
+// in LDS); the blocks past the last whole run keep their positions.  Then
+// the tag.
 __device__ __forceinline__ void sort_walk_blocks(const OrderBuild &ob)
 {
+    constexpr int32_t kRunsPerThread = kOrderMaxBlocks / kXcdRun / kBlock;
     __shared__ int32_t cnt[kOrderLevels], pos[kOrderLevels];
     const RayParams &p = ob.rp;
-    const int32_t nblk = ob.ray_blocks;
+    const int32_t nblk = ob.ray_blocks, nrun = nblk / kXcdRun;
     const int32_t t = (int32_t)threadIdx.x;   // kBlock == kOrderLevels threads
     WalkOrderTag *tag = reinterpret_cast<WalkOrderTag *>(ob.order);
     if (t == 0)
         tag->ray_blocks = 0;   // no valid order while it is rewritten
-    // pos[k] = blocks of levels above k (Hillis-Steele over the levels from
-    // the top: thread t holds level kOrderLevels - 1 - t)
-    // the parts' counts of level kOrderLevels - 1 - t: 16 loads at a time, at
-    // clamped rows (no branch, so that they issue together)
-    int32_t v = 0;
-    for (int32_t q0 = 0; q0 < ob.parts; q0 += 16) {
-        int32_t x[16];
+    cnt[t] = 0;
+    __syncthreads();
+    // each thread's runs' levels: all their blocks' levels load together
+    int32_t lv[kRunsPerThread];
 #pragma unroll
-        for (int32_t q = 0; q < 16; ++q)
-            x[q] = ob.counts[min(q0 + q, ob.parts - 1) * kOrderLevels + kOrderLevels - 1 - t];
+    for (int32_t r = 0; r < kRunsPerThread; ++r) {
+        const int32_t run = min(t + r * kBlock, max(nrun - 1, 0));
+        uint32_t k[kXcdRun];
 #pragma unroll
-        for (int32_t q = 0; q < 16; ++q)
-            v += q0 + q < ob.parts ? x[q] : 0;
+        for (int32_t i = 0; i < kXcdRun; ++i)
+            k[i] = ob.keys[min(run * kXcdRun + i, nblk - 1)];
+        uint32_t m = 0;
+#pragma unroll
+        for (int32_t i = 0; i < kXcdRun; ++i)
+            m = max(m, k[i]);
+        lv[r] = (int32_t)m;
+        if (t + r * kBlock < nrun)
+            atomicAdd(&cnt[m], 1);
     }
+    __syncthreads();
+    // pos[k] = runs of levels above k (Hillis-Steele over the levels from
+    // the top: thread t holds level kOrderLevels - 1 - t)
+    const int32_t v = cnt[kOrderLevels - 1 - t];
     pos[t] = v;
     __syncthreads();
     for (int32_t off = 1; off < kOrderLevels; off <<= 1) {
@@ -1124,29 +1127,25 @@ __device__ __forceinline__ void sort_walk_blocks(const OrderBuild &ob)
         pos[t] += w;
         __syncthreads();
     }
-    const bool whole = pos[kOrderLevels - 1] == nblk;   // every block counted once
+    const bool whole = pos[kOrderLevels - 1] == nrun;   // every run counted once
     cnt[kOrderLevels - 1 - t] = pos[t] - v;   // next free position of each level
     __syncthreads();
     if (!whole)
         return;
     int32_t *out = ob.order + kOrderTagInts;
-    for (int32_t j0 = t; j0 < nblk; j0 += 8 * kBlock) {
-        // eight levels at a time, at clamped indices, so that the loads issue
-        // together
-        uint32_t kk[8];
 #pragma unroll
-        for (int32_t q = 0; q < 8; ++q)
-            kk[q] = ob.keys[min(j0 + q * kBlock, nblk - 1)];
+    for (int32_t r = 0; r < kRunsPerThread; ++r) {
+        const int32_t run = t + r * kBlock;
+        if (run < nrun) {
+            const int32_t at = atomicAdd(&cnt[lv[r]], 1);
+            if (at < nrun)
 #pragma unroll
-        for (int32_t q = 0; q < 8; ++q) {
-            const int32_t j = j0 + q * kBlock;
-            if (j < nblk) {
-                const int32_t at = atomicAdd(&cnt[kk[q]], 1);
-                if (at < nblk)
-                    out[at] = j;
-            }
+                for (int32_t i = 0; i < kXcdRun; ++i)
+                    out[at * kXcdRun + i] = run * kXcdRun + i;
         }
     }
+    for (int32_t j = nrun * kXcdRun + t; j < nblk; j += kBlock)
+        out[j] = j;
     __syncthreads();
     if (t == 0) {
         tag->tiles_a = p.tiles_a;
