@@ -149,14 +149,32 @@ __device__ __forceinline__ void ray_direction(const RayParams &p, int32_t tx, in
     dir[2] = row_dot(p.R + 6, x, y, z);
 }
 
-// Bit j (j < 4) set iff byte j of w equals the byte replicated in rep.
-__device__ __forceinline__ uint32_t byte_eq_mask(uint32_t w, uint32_t rep)
+// Bit 0 of byte j set iff byte j of w equals the byte replicated in rep (the
+// other bits clear).
+__device__ __forceinline__ uint32_t byte_eq_ones(uint32_t w, uint32_t rep)
 {
     uint32_t x = w ^ rep;                                  // zero bytes = matches
     uint32_t y = (x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu;
     y = ~(y | x | 0x7F7F7F7Fu);                            // 0x80 exactly in zero bytes
-    uint32_t t = (y >> 7) & 0x01010101u;
-    return (t * 0x01020408u) >> 24;                        // gather the four flags
+    return y >> 7;
+}
+
+// The flags of two such words in bits 0 .. 7: a's bytes 0 .. 3, then b's.
+// One multiply gathers all eight: flag k of a sits at bit 8k and of b at
+// 8k + 4, and the multiplier's bits 24 - 7i move flag i of each to bit
+// 24 + i (a) and 28 + i (b); the other products land on distinct bits below
+// 24 or at 32 and above, so nothing carries into bits 24 .. 31.
+__device__ __forceinline__ uint32_t gather8(uint32_t a, uint32_t b)
+{
+    return ((a | (b << 4)) * 0x01020408u) >> 24;
+}
+
+// Bit j (j < 16) set iff byte j of q (x's bytes first) equals the byte
+// replicated in rep.
+__device__ __forceinline__ uint32_t byte_eq_mask16(const uint4 &q, uint32_t rep)
+{
+    return gather8(byte_eq_ones(q.x, rep), byte_eq_ones(q.y, rep)) |
+           (gather8(byte_eq_ones(q.z, rep), byte_eq_ones(q.w, rep)) << 8);
 }
 
 // ----------------------------------------------------------------- kernels
@@ -329,9 +347,7 @@ __device__ __forceinline__ void dilate_x_body(const Planes &pl, int64_t gid)
             uint32_t m[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
-                const uint4 q = src[k];
-                m[k] = byte_eq_mask(q.x, rep) | (byte_eq_mask(q.y, rep) << 4) |
-                       (byte_eq_mask(q.z, rep) << 8) | (byte_eq_mask(q.w, rep) << 12);
+                m[k] = byte_eq_mask16(src[k], rep);
             }
             const uint64_t w64 = (uint64_t)(m[0] | (m[1] << 16)) |
                                  ((uint64_t)(m[2] | (m[3] << 16)) << 32);
@@ -368,9 +384,7 @@ __device__ __forceinline__ void dilate_x_body(const Planes &pl, int64_t gid)
             q[j] = 16 * j < need ? src[j] : make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
         for (int j = 0; j < 10; ++j) {
-            const uint32_t b = byte_eq_mask(q[j].x, rep) | (byte_eq_mask(q[j].y, rep) << 4) |
-                               (byte_eq_mask(q[j].z, rep) << 8) | (byte_eq_mask(q[j].w, rep) << 12);
-            m[j >> 1] |= b << (16 * (j & 1));
+            m[j >> 1] |= byte_eq_mask16(q[j], rep) << (16 * (j & 1));
         }
     }
     uint32_t *dst = pl.bitx + (int64_t)pl.wx * (y + (int64_t)pl.py * z) + 4 * k;
@@ -435,18 +449,28 @@ __device__ __forceinline__ void dilate_yz_tile_body(const Planes &pl, int32_t ti
     // all loads of a thread first, so that they are in flight together: the
     // thread's word lane w of padded rows y0 + slot (+ kTY) of every input z
     // row (at most 2 x kTileMaxIz, unrolled, no divisions); then the stores
+    // Buffer loads: the lane's byte offset of padded row (py, z0) once (kOob,
+    // which reads 0, for rows outside the seed box), and the z row's offset
+    // as the uniform scalar offset, so that a load costs no vector
+    // arithmetic.  Rows of at most 16 words: the padded plane holds fewer than
+    // 2^31 bytes.
+    const uint32_t zs = 4u * (uint32_t)wx * (uint32_t)pl.py;   // bytes per padded z row
+    const __amdgpu_buffer_rsrc_t rb = buffer_rsrc(pl.bitx, zs * (uint32_t)pl.pz);
     uint32_t ld[2][kTileMaxIz];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int32_t yy = slot + h * kTY;
         const int32_t py = y0 + yy;
         const bool yin = any && lane && yy < iy && py >= pl.lo[1] && py <= pl.hi[1];
+        const uint32_t off =
+            yin ? 4u * ((uint32_t)wx * (uint32_t)py + (uint32_t)w) + (uint32_t)z0 * zs : kOob;
 #pragma unroll
         for (int zz = 0; zz < kTileMaxIz; ++zz) {
             const int32_t pz = z0 + zz;
-            ld[h][zz] = 0;
-            if (yin && zz < iz && pz >= pl.lo[2] && pz <= pl.hi[2])
-                ld[h][zz] = pl.bitx[(int64_t)wx * (py + (int64_t)pl.py * pz) + w];
+            ld[h][zz] = (zz < iz && pz >= pl.lo[2] && pz <= pl.hi[2])
+                            ? __builtin_amdgcn_raw_buffer_load_b32(rb, (int)off,
+                                                                   (int)((uint32_t)zz * zs), 0)
+                            : 0u;
         }
     }
 #pragma unroll
@@ -476,6 +500,10 @@ __device__ __forceinline__ void dilate_yz_tile_body(const Planes &pl, int32_t ti
     if (!lane || gy >= pl.n[1])
         return;
     // along z: output z row z0 + z = OR of t[z .. z + r2]
+    // stores as the loads: the lane's offset once, the z row's as the scalar
+    const uint32_t os = 4u * (uint32_t)wx * (uint32_t)pl.n[1];   // bytes per grid z row
+    const __amdgpu_buffer_rsrc_t ro = buffer_rsrc(pl.occ, os * (uint32_t)pl.n[2]);
+    const uint32_t out = 4u * ((uint32_t)wx * (uint32_t)gy + (uint32_t)w) + (uint32_t)z0 * os;
 #pragma unroll
     for (int z = 0; z < kTZ; ++z) {
         const int32_t gz = z0 + z;
@@ -485,7 +513,7 @@ __device__ __forceinline__ void dilate_yz_tile_body(const Planes &pl, int32_t ti
 #pragma unroll
         for (int d = 0; d <= 2 * kTileMaxR; ++d)
             v |= d <= r2 ? t[z + d] : 0u;
-        pl.occ[(int64_t)wx * (gy + (int64_t)pl.n[1] * gz) + w] = v;
+        __builtin_amdgcn_raw_buffer_store_b32(v, ro, (int)out, (int)((uint32_t)z * os), 0);
     }
 }
 

@@ -316,9 +316,12 @@ struct Chunk {
 VG_HD bool chunk_safe(const Walk &w, int32_t m2)
 {
     constexpr int32_t room = 2 * (kChunk - 1);
+    // q = 2 * steps + 1 < 2^20 (a wavefront's walks end within 3 * 65535
+    // steps, a finished walk's q moving with the live ones' chunks): the
+    // full-rate 24-bit multiply is exact
     const int32_t qm = imax(w.qx, imax(w.qy, w.qz));
     return w.qx + room < w.lx && w.qy + room < w.ly && w.qz + room < w.lz &&
-           w.d2 + (kChunk - 1) * qm + (kChunk - 1) * (kChunk - 2) < m2;
+           w.d2 + (int32_t)mul24((uint32_t)qm, kChunk - 1) + (kChunk - 1) * (kChunk - 2) < m2;
 }
 
 // kLone selects the form for wavefronts that each have a SIMD to themselves
