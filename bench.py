@@ -69,8 +69,9 @@ SECTIONS = ("headline", "spinning", "medium", "small", "batched", "served", "pap
 
 STAGE_KERNELS = {"k_dilate": ["k_dilate_x<false>", "k_dilate_x<true>", "k_dilate_yz"] +
                              [f"k_dilate_yz_tile<{w}, {z}>" for w in (8, 16) for z in (2, 8)],
-                 "k_rays": [f"k_rays<{g}, {b}, {l}>" for g in ("false", "true")
-                            for b in ("false", "true") for l in ("false", "true")],
+                 "k_rays": [f"{k}<{g}, {b}, {l}>" for k in ("k_rays", "k_rays_w")
+                            for g in ("false", "true") for b in ("false", "true")
+                            for l in ("false", "true")],
                  "k_resolve": [f"k_resolve<{b}, {w}>" for b in ("false", "true")
                                for w in ("false", "true")]}
 
@@ -170,10 +171,11 @@ def frame_counter_bytes(path, workload):
     if t.get("source_hash") != kernel_source_hash() or t.get("workload") != workload:
         return None
     ks = t.get("kernels", {})
-    frames = sum(v.get("launches", 0) for k, v in ks.items() if k.startswith("k_rays<"))
+    frames = sum(v.get("launches", 0) for k, v in ks.items()
+                 if k.startswith(("k_rays<", "k_rays_w<")))
     if not frames:
         return None
-    stages = ("k_seed", "k_dilate_", "k_rays<", "k_resolve<", "k_clear")
+    stages = ("k_seed", "k_dilate_", "k_rays<", "k_rays_w<", "k_resolve<", "k_clear")
     total = sum(v["hbm_bytes_per_launch"] * v.get("launches", 1) for k, v in ks.items()
                 if k.startswith(stages))
     return float(total) / frames
@@ -1108,7 +1110,7 @@ def main():
         roof = None
         if stats:
             walk_s = res["walk_ms"][hl["stats_idx"]]
-            roof = walk_roofline(steps, walk_s, "k_rays<false, false, true>",
+            roof = walk_roofline(steps, walk_s, "k_rays_w<false, false, true>",
                                  measured_traffic("k_rays", TRAFFIC_FILE, WORKLOAD),
                                  f"walk launch live time (events its own dispatches record) on "
                                  f"the {len(steps)} sampled frames of a dedicated pass over the "

@@ -1265,6 +1265,41 @@ __global__ __launch_bounds__(kBlock) void k_rays(RayParams p, SlabClear c, int32
     rays_body<kGeneral, kBytes, kLone>(p, rb * (kBlock / 64) + (threadIdx.x >> 6));
 }
 
+// The walk of a launch of more than kLoneWaves wavefronts, one wavefront per
+// workgroup: a compute unit starts the next wavefront as soon as one of its
+// SIMDs has a free slot, where a workgroup of four waits for a slot on each
+// (the walk took 139 -> 135 us on the 1280x720 frame).  Wavefront u walks
+// tile w of ray block position bb; the four tiles of a position go to one
+// XCD, as workgroup bb of four wavefronts would (workgroups go to the 8 XCDs
+// in turn), so the positions keep their XCD runs and their walk order.
+// Workgroups from 4 ray_blocks on run the slab clear c, 64 lanes each.
+template <bool kGeneral, bool kBytes, bool kLone>
+__global__ __launch_bounds__(64) void k_rays_w(RayParams p, SlabClear c, int32_t ray_blocks)
+{
+    constexpr int32_t kTiles = kBlock / 64;   // tiles per ray block
+    const int32_t units = kTiles * ray_blocks, u = (int32_t)blockIdx.x;
+    if (u >= units) {
+        clear_body(c, (int64_t)(u - units) * 64 + threadIdx.x);
+        return;
+    }
+    // whole rounds of 8 positions x 4 tiles: wavefront u = 32 j + 8 w + x
+    // walks tile w of position 8 j + x; the last partial round in order
+    const int32_t full = 8 * kTiles * (ray_blocks / 8);
+    int32_t bb, w;
+    if (u < full) {
+        const int32_t k = u >> 3, x = u & 7;
+        bb = (k / kTiles) * 8 + x;
+        w = k % kTiles;
+    } else {
+        bb = ray_blocks / 8 * 8 + (u - full) / kTiles;
+        w = (u - full) % kTiles;
+    }
+    int32_t rb = xcd_runs(bb, ray_blocks);
+    if (p.order_in)
+        rb = ordered_block(p, ray_blocks, rb);
+    rays_body<kGeneral, kBytes, kLone>(p, rb * kTiles + w);
+}
+
 template <bool kBytes, bool kWide>
 __global__ __launch_bounds__(kBlock) void k_resolve(Planes pl, uint8_t *loc, RowBox rows,
                                                     int32_t rx, int32_t ry, int32_t rz)
@@ -1490,6 +1525,22 @@ hipError_t launch_rays(const RayParams &p, bool camera_inside, hipStream_t st,
         return record_empty_stage(ev, st);
     // the camera inside the grid: the walk form that keeps its loads in
     // flight; from outside, every step takes the tested path anyway
+    if (ray_blocks * waves > kLoneWaves) {
+        const dim3 g((uint32_t)(waves * (ray_blocks + clear_blocks)));
+        if (camera_inside && !p.occ_is_bytes)
+            hipExtLaunchKernelGGL((k_rays_w<false, false, true>), g, dim3(64), 0, st, ev.start,
+                                  ev.stop, 0, p, c, (int32_t)ray_blocks);
+        else if (camera_inside)
+            hipExtLaunchKernelGGL((k_rays_w<false, true, true>), g, dim3(64), 0, st, ev.start,
+                                  ev.stop, 0, p, c, (int32_t)ray_blocks);
+        else if (!p.occ_is_bytes)
+            hipExtLaunchKernelGGL((k_rays_w<true, false, false>), g, dim3(64), 0, st, ev.start,
+                                  ev.stop, 0, p, c, (int32_t)ray_blocks);
+        else
+            hipExtLaunchKernelGGL((k_rays_w<true, true, false>), g, dim3(64), 0, st, ev.start,
+                                  ev.stop, 0, p, c, (int32_t)ray_blocks);
+        return hipGetLastError();
+    }
     if (camera_inside && !p.occ_is_bytes)
         hipExtLaunchKernelGGL((k_rays<false, false, true>), dim3(blocks), dim3(kBlock), 0, st,
                               ev.start, ev.stop, 0, p, c, (int32_t)ray_blocks);
