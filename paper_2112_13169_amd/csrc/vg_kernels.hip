@@ -1273,19 +1273,16 @@ __global__ __launch_bounds__(kBlock) void k_rays(RayParams p, SlabClear c, int32
 // XCD, as workgroup bb of four wavefronts would (workgroups go to the 8 XCDs
 // in turn), so the positions keep their XCD runs and their walk order.
 // Workgroups from 4 ray_blocks on run the slab clear c, 64 lanes each.
-template <bool kGeneral, bool kBytes, bool kLone>
-__global__ __launch_bounds__(64) void k_rays_w(RayParams p, SlabClear c, int32_t ray_blocks)
+constexpr int32_t kTiles = kBlock / 64;   // tiles per ray block
+
+// Wavefront u (< kTiles * ray_blocks) of a launch with one wavefront per
+// workgroup: tile w of ray block position bb.  Whole rounds of 8 positions x
+// 4 tiles: wavefront u = 32 j + 8 w + x walks tile w of position 8 j + x; the
+// last partial round in order.
+__device__ __forceinline__ void wave_position(int32_t ray_blocks, int32_t u, int32_t &bb,
+                                              int32_t &w)
 {
-    constexpr int32_t kTiles = kBlock / 64;   // tiles per ray block
-    const int32_t units = kTiles * ray_blocks, u = (int32_t)blockIdx.x;
-    if (u >= units) {
-        clear_body(c, (int64_t)(u - units) * 64 + threadIdx.x);
-        return;
-    }
-    // whole rounds of 8 positions x 4 tiles: wavefront u = 32 j + 8 w + x
-    // walks tile w of position 8 j + x; the last partial round in order
     const int32_t full = 8 * kTiles * (ray_blocks / 8);
-    int32_t bb, w;
     if (u < full) {
         const int32_t k = u >> 3, x = u & 7;
         bb = (k / kTiles) * 8 + x;
@@ -1294,6 +1291,18 @@ __global__ __launch_bounds__(64) void k_rays_w(RayParams p, SlabClear c, int32_t
         bb = ray_blocks / 8 * 8 + (u - full) / kTiles;
         w = (u - full) % kTiles;
     }
+}
+
+template <bool kGeneral, bool kBytes, bool kLone>
+__global__ __launch_bounds__(64) void k_rays_w(RayParams p, SlabClear c, int32_t ray_blocks)
+{
+    const int32_t units = kTiles * ray_blocks, u = (int32_t)blockIdx.x;
+    if (u >= units) {
+        clear_body(c, (int64_t)(u - units) * 64 + threadIdx.x);
+        return;
+    }
+    int32_t bb, w;
+    wave_position(ray_blocks, u, bb, w);
     int32_t rb = xcd_runs(bb, ray_blocks);
     if (p.order_in)
         rb = ordered_block(p, ray_blocks, rb);
@@ -1390,12 +1399,15 @@ __global__ __launch_bounds__(kBlock) void kb_dilate_yz_tile(const FrameDesc *__r
     dilate_yz_tile_body<kW, kTZ>(f.sp.pl, local % tiles_y, local / tiles_y, lds);
 }
 
-__global__ __launch_bounds__(kBlock) void kb_rays(const FrameDesc *__restrict__ fd,
-                                                  const int32_t *__restrict__ start, int32_t n)
+// One wavefront per workgroup, as k_rays_w: wavefront u walks tile w of the
+// stage's ray block position bb.
+__global__ __launch_bounds__(64) void kb_rays(const FrameDesc *__restrict__ fd,
+                                              const int32_t *__restrict__ start, int32_t n)
 {
-    int32_t local;
-    const FrameDesc &f = fd[frame_of(start, n, xcd_runs((int32_t)blockIdx.x, start[n]), local)];
-    const int32_t tile = local * (kBlock / 64) + (threadIdx.x >> 6);
+    int32_t bb, w, local;
+    wave_position(start[n], (int32_t)blockIdx.x, bb, w);
+    const FrameDesc &f = fd[frame_of(start, n, xcd_runs(bb, start[n]), local)];
+    const int32_t tile = local * kTiles + w;
     if (f.inside)
         rays_body<false, false, true>(f.rp, tile);
     else
@@ -1655,7 +1667,8 @@ hipError_t launch_batch_stage(int stage, const FrameDesc *fd, const int32_t *sta
         }
         break;
     case kBatchRays:
-        hipExtLaunchKernelGGL(kb_rays, g, b, 0, st, ev.start, ev.stop, 0, fd, start, n);
+        hipExtLaunchKernelGGL(kb_rays, dim3((uint32_t)(kTiles * blocks)), dim3(64), 0, st,
+                              ev.start, ev.stop, 0, fd, start, n);
         break;
     case kBatchResolve:
         if (seq)
