@@ -1309,12 +1309,15 @@ __global__ __launch_bounds__(64) void k_rays_w(RayParams p, SlabClear c, int32_t
     rays_body<kGeneral, kBytes, kLone>(p, rb * kTiles + w);
 }
 
+// One wavefront per workgroup, as the walk of large launches: at 4 wavefronts
+// per SIMD (117 VGPRs on the wide path) a wavefront starts wherever a slot
+// frees (19.2 -> 18.9 us on the 1280x720 frame).
 template <bool kBytes, bool kWide>
-__global__ __launch_bounds__(kBlock) void k_resolve(Planes pl, uint8_t *loc, RowBox rows,
-                                                    int32_t rx, int32_t ry, int32_t rz)
+__global__ __launch_bounds__(64) void k_resolve(Planes pl, uint8_t *loc, RowBox rows, int32_t rx,
+                                                int32_t ry, int32_t rz)
 {
     const int32_t ring[3] = {rx, ry, rz};
-    resolve_body<kBytes, kWide>(pl, loc, rows, ring, (int64_t)blockIdx.x * kBlock + threadIdx.x);
+    resolve_body<kBytes, kWide>(pl, loc, rows, ring, (int64_t)blockIdx.x * 64 + threadIdx.x);
 }
 
 __global__ __launch_bounds__(kBlock) void k_clear(SlabClear c)
@@ -1578,8 +1581,8 @@ hipError_t launch_resolve(const Planes &pl, uint8_t *loc, const RowBox &rows,
     const int64_t n = (int64_t)merge_lanes(pl.n[0], wide) * ny * nz;
     auto kern = pl.occb ? (wide ? k_resolve<true, true> : k_resolve<true, false>)
                         : (wide ? k_resolve<false, true> : k_resolve<false, false>);
-    hipExtLaunchKernelGGL(kern, dim3(blocks_for(n)), dim3(kBlock), 0, st, ev.start, ev.stop, 0, pl,
-                          loc, rows, ring[0], ring[1], ring[2]);
+    hipExtLaunchKernelGGL(kern, dim3((uint32_t)((n + 63) / 64)), dim3(64), 0, st, ev.start,
+                          ev.stop, 0, pl, loc, rows, ring[0], ring[1], ring[2]);
     return hipGetLastError();
 }
 
