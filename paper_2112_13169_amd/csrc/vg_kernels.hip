@@ -1418,24 +1418,26 @@ __global__ __launch_bounds__(64) void kb_rays(const FrameDesc *__restrict__ fd,
 }
 
 template <bool kWide>
-__global__ __launch_bounds__(kBlock) void kb_resolve(const FrameDesc *__restrict__ fd,
-                                                     const int32_t *__restrict__ start, int32_t n)
+// One wavefront per workgroup, as k_resolve: workgroup u is wavefront u % 4
+// of the stage's block u / 4 (start[] counts blocks of kBlock = 256 lanes).
+__global__ __launch_bounds__(64) void kb_resolve(const FrameDesc *__restrict__ fd,
+                                                 const int32_t *__restrict__ start, int32_t n)
 {
     int32_t local;
-    const FrameDesc &f = fd[frame_of(start, n, blockIdx.x, local)];
+    const FrameDesc &f = fd[frame_of(start, n, (int32_t)blockIdx.x >> 2, local)];
     resolve_body<false, kWide>(f.sp.pl, f.loc, f.rows, f.ring,
-                               (int64_t)local * kBlock + threadIdx.x);
+                               (int64_t)local * kBlock + (blockIdx.x & 3u) * 64u + threadIdx.x);
 }
 
 // The merge of a round that holds runs of frames of one grid: a block finds
 // the first frame of its run (the run's other frames have no blocks).
-__global__ __launch_bounds__(kBlock) void kb_resolve_seq(const FrameDesc *__restrict__ fd,
-                                                         const int32_t *__restrict__ start,
-                                                         int32_t n)
+__global__ __launch_bounds__(64) void kb_resolve_seq(const FrameDesc *__restrict__ fd,
+                                                     const int32_t *__restrict__ start,
+                                                     int32_t n)
 {
     int32_t local;
-    const int32_t i = frame_of(start, n, blockIdx.x, local);
-    resolve_seq_body(fd + i, (int64_t)local * kBlock + threadIdx.x);
+    const int32_t i = frame_of(start, n, (int32_t)blockIdx.x >> 2, local);
+    resolve_seq_body(fd + i, (int64_t)local * kBlock + (blockIdx.x & 3u) * 64u + threadIdx.x);
 }
 
 uint32_t blocks_for(int64_t threads) { return (uint32_t)((threads + kBlock - 1) / kBlock); }
@@ -1673,16 +1675,20 @@ hipError_t launch_batch_stage(int stage, const FrameDesc *fd, const int32_t *sta
         hipExtLaunchKernelGGL(kb_rays, dim3((uint32_t)(kTiles * blocks)), dim3(64), 0, st,
                               ev.start, ev.stop, 0, fd, start, n);
         break;
-    case kBatchResolve:
+    case kBatchResolve: {
+        // one wavefront per workgroup, kBlock / 64 per block of the stage's prefix
+        const dim3 g4((uint32_t)(kBlock / 64) * (uint32_t)blocks), b64(64);
         if (seq)
-            hipExtLaunchKernelGGL(kb_resolve_seq, g, b, 0, st, ev.start, ev.stop, 0, fd, start, n);
+            hipExtLaunchKernelGGL(kb_resolve_seq, g4, b64, 0, st, ev.start, ev.stop, 0, fd, start,
+                                  n);
         else if (wide)
-            hipExtLaunchKernelGGL(kb_resolve<true>, g, b, 0, st, ev.start, ev.stop, 0, fd, start,
-                                  n);
+            hipExtLaunchKernelGGL(kb_resolve<true>, g4, b64, 0, st, ev.start, ev.stop, 0, fd,
+                                  start, n);
         else
-            hipExtLaunchKernelGGL(kb_resolve<false>, g, b, 0, st, ev.start, ev.stop, 0, fd, start,
-                                  n);
+            hipExtLaunchKernelGGL(kb_resolve<false>, g4, b64, 0, st, ev.start, ev.stop, 0, fd,
+                                  start, n);
         break;
+    }
     default:
         return hipErrorInvalidValue;
     }
