@@ -712,7 +712,8 @@ def run_pool(workload, frames, K, W, torch, vg, oracle, check=8):
         "voxel_updates_per_frame": round(float(np.mean([s["updates"] for s in stats])), 1),
         "walk_steps_per_frame": round(float(np.mean([s["steps"] for s in stats])), 1),
         "walk_roofline": walk_roofline([s["steps"] for s in stats], walk,
-                                       "k_rays", None, f"first {nc} frames of the pool"),
+                                       "k_rays_w", None,
+                                       f"first {nc} frames of the pool"),
         "bit_exact": same, "oracle_frames": nc,
     }
 

@@ -12,8 +12,8 @@
 //   k_dilate_x    Alg. 1, inflation, separably: seeds -> bits dilated by
 //   k_dilate_yz   vox_inf along x, then along y and z.  The union of the
 //                 (2 vox_inf + 1)^3 cubes is exactly this separable dilation.
-//   k_rays        Alg. 2: one wavefront per tile of 64 fan targets (8 x 8 by
-//                 default), one lane per ray.  Each step stamps its voxel in
+//   k_rays_w      Alg. 2: one wavefront (and workgroup) per tile of 64 fan
+//                 targets (8 x 8 by default), one lane per ray.  Each step stamps its voxel in
 //                 one of two per-frame mark planes: "free" before the ray's
 //                 first occupied voxel, "unknown and traced" from it on.
 //                 Occupancy words are fetched for 8 walk steps at a time so
@@ -1238,41 +1238,16 @@ __global__ __launch_bounds__(kBlock) void k_dilate_yz_tile(Planes pl)
     dilate_yz_tile_body<kW, kTZ>(pl, blockIdx.x, blockIdx.y, lds);
 }
 
-// The walk; workgroups from ray_blocks on run the slab clear c instead (the
-// walk leaves most compute units idle for its longest rays).  kLone: the walk
-// form that overlaps each chunk's loads with the next chunk's steps.
-template <bool kGeneral, bool kBytes, bool kLone>
-__global__ __launch_bounds__(kBlock) void k_rays(RayParams p, SlabClear c, int32_t ray_blocks)
-{
-    int32_t rb = (int32_t)blockIdx.x;
-    if (rb >= ray_blocks) {
-        clear_body(c, (int64_t)(rb - ray_blocks) * kBlock + threadIdx.x);
-        return;
-    }
-    if (kLone && (int64_t)ray_blocks * (kBlock / 64) <= kLoneWaves) {
-        // Workgroups go to the 8 XCDs in turn.  With every ray wavefront
-        // resident at once, each XCD takes a contiguous range of ray blocks,
-        // whose neighbouring tiles share cache lines in its L2.  (With more
-        // wavefronts than SIMDs, contiguous ranges load the XCDs unevenly:
-        // runs of kXcdRun blocks keep the costly tiles spread.)
-        const int32_t q = ray_blocks / 8, rem = ray_blocks % 8, xcd = rb % 8;
-        rb = xcd * q + min(xcd, rem) + rb / 8;
-    } else {
-        rb = xcd_runs(rb, ray_blocks);
-        if (p.order_in)
-            rb = ordered_block(p, ray_blocks, rb);
-    }
-    rays_body<kGeneral, kBytes, kLone>(p, rb * (kBlock / 64) + (threadIdx.x >> 6));
-}
-
-// The walk of a launch of more than kLoneWaves wavefronts, one wavefront per
-// workgroup: a compute unit starts the next wavefront as soon as one of its
-// SIMDs has a free slot, where a workgroup of four waits for a slot on each
-// (the walk took 139 -> 135 us on the 1280x720 frame).  Wavefront u walks
-// tile w of ray block position bb; the four tiles of a position go to one
-// XCD, as workgroup bb of four wavefronts would (workgroups go to the 8 XCDs
-// in turn), so the positions keep their XCD runs and their walk order.
-// Workgroups from 4 ray_blocks on run the slab clear c, 64 lanes each.
+// The walk, one wavefront per workgroup: a compute unit starts the next
+// wavefront as soon as one of its SIMDs has a free slot, where a workgroup of
+// four waits for a slot on each (the walk took 139 -> 135 us on the 1280x720
+// frame), and a small launch spreads over more compute units.  In a launch of
+// more than kLoneWaves wavefronts wavefront u walks tile w of ray block
+// position bb; the four tiles of a position go to one XCD, as workgroup bb of
+// four wavefronts would (workgroups go to the 8 XCDs in turn), so the
+// positions keep their XCD runs and their walk order.  Workgroups from
+// 4 ray_blocks on run the slab clear c, 64 lanes each.  kLone: the walk form
+// that overlaps each chunk's loads with the next chunk's steps.
 constexpr int32_t kTiles = kBlock / 64;   // tiles per ray block
 
 // Wavefront u (< kTiles * ray_blocks) of a launch with one wavefront per
@@ -1299,6 +1274,13 @@ __global__ __launch_bounds__(64) void k_rays_w(RayParams p, SlabClear c, int32_t
     const int32_t units = kTiles * ray_blocks, u = (int32_t)blockIdx.x;
     if (u >= units) {
         clear_body(c, (int64_t)(u - units) * 64 + threadIdx.x);
+        return;
+    }
+    if (kLone && units <= kLoneWaves) {
+        // every wavefront resident at once: each XCD takes a contiguous range
+        // of tiles, whose neighbours share cache lines in its L2
+        const int32_t q = units / 8, rem = units % 8, x = u % 8;
+        rays_body<kGeneral, kBytes, kLone>(p, x * q + min(x, rem) + u / 8);
         return;
     }
     int32_t bb, w;
@@ -1529,47 +1511,31 @@ hipError_t launch_dilate(const Planes &pl, hipStream_t st, const StageEvents &ev
 hipError_t launch_rays(const RayParams &p, bool camera_inside, hipStream_t st,
                        const StageEvents &ev, const SlabClear *clear)
 {
-    const int waves = kBlock / 64;
-    const int64_t ray_blocks = (p.tiles + waves - 1) / waves;
+    const int64_t ray_blocks = (p.tiles + kTiles - 1) / kTiles;
     SlabClear c{};
     int64_t clear_blocks = 0;
     if (clear) {
         c = *clear;
         clear_blocks = blocks_for(clear_lanes(c));
     }
-    const uint32_t blocks = (uint32_t)(ray_blocks + clear_blocks);
-    if (blocks == 0)
+    if (ray_blocks + clear_blocks == 0)
         return record_empty_stage(ev, st);
+    // one wavefront per workgroup, kTiles per block of rays or of the clear;
     // the camera inside the grid: the walk form that keeps its loads in
     // flight; from outside, every step takes the tested path anyway
-    if (ray_blocks * waves > kLoneWaves) {
-        const dim3 g((uint32_t)(waves * (ray_blocks + clear_blocks)));
-        if (camera_inside && !p.occ_is_bytes)
-            hipExtLaunchKernelGGL((k_rays_w<false, false, true>), g, dim3(64), 0, st, ev.start,
-                                  ev.stop, 0, p, c, (int32_t)ray_blocks);
-        else if (camera_inside)
-            hipExtLaunchKernelGGL((k_rays_w<false, true, true>), g, dim3(64), 0, st, ev.start,
-                                  ev.stop, 0, p, c, (int32_t)ray_blocks);
-        else if (!p.occ_is_bytes)
-            hipExtLaunchKernelGGL((k_rays_w<true, false, false>), g, dim3(64), 0, st, ev.start,
-                                  ev.stop, 0, p, c, (int32_t)ray_blocks);
-        else
-            hipExtLaunchKernelGGL((k_rays_w<true, true, false>), g, dim3(64), 0, st, ev.start,
-                                  ev.stop, 0, p, c, (int32_t)ray_blocks);
-        return hipGetLastError();
-    }
+    const dim3 g((uint32_t)(kTiles * (ray_blocks + clear_blocks))), b(64);
     if (camera_inside && !p.occ_is_bytes)
-        hipExtLaunchKernelGGL((k_rays<false, false, true>), dim3(blocks), dim3(kBlock), 0, st,
-                              ev.start, ev.stop, 0, p, c, (int32_t)ray_blocks);
+        hipExtLaunchKernelGGL((k_rays_w<false, false, true>), g, b, 0, st, ev.start, ev.stop, 0,
+                              p, c, (int32_t)ray_blocks);
     else if (camera_inside)
-        hipExtLaunchKernelGGL((k_rays<false, true, true>), dim3(blocks), dim3(kBlock), 0, st,
-                              ev.start, ev.stop, 0, p, c, (int32_t)ray_blocks);
+        hipExtLaunchKernelGGL((k_rays_w<false, true, true>), g, b, 0, st, ev.start, ev.stop, 0, p,
+                              c, (int32_t)ray_blocks);
     else if (!p.occ_is_bytes)
-        hipExtLaunchKernelGGL((k_rays<true, false, false>), dim3(blocks), dim3(kBlock), 0, st,
-                              ev.start, ev.stop, 0, p, c, (int32_t)ray_blocks);
+        hipExtLaunchKernelGGL((k_rays_w<true, false, false>), g, b, 0, st, ev.start, ev.stop, 0,
+                              p, c, (int32_t)ray_blocks);
     else
-        hipExtLaunchKernelGGL((k_rays<true, true, false>), dim3(blocks), dim3(kBlock), 0, st,
-                              ev.start, ev.stop, 0, p, c, (int32_t)ray_blocks);
+        hipExtLaunchKernelGGL((k_rays_w<true, true, false>), g, b, 0, st, ev.start, ev.stop, 0, p,
+                              c, (int32_t)ray_blocks);
     return hipGetLastError();
 }
 

@@ -1,7 +1,7 @@
 // vg_walk.h -- the ray walk of Alg. 2 (Toumieh & Lambert, arXiv 2112.13169,
 // Sec. IV-C): Amanatides & Woo traversal from the camera voxel, termination
 // at the target's length, free / traced marking around the first occupied
-// voxel.  Used by the k_rays kernel; plain C++ without HIP so that the same
+// voxel.  Used by the walk kernels; plain C++ without HIP so that the same
 // code can also be compiled for the host (VG_HD expands accordingly).
 #pragma once
 

@@ -1,4 +1,4 @@
-"""The GPU ray walk (vg_walk.h, shared by the k_rays kernel) compiled for the
+"""The GPU ray walk (vg_walk.h, shared by the walk kernels) compiled for the
 host and compared with the CPU oracle's walk ray by ray: random grids,
 occupancy (bits, or stamp bytes), camera positions inside and outside the
 grid, voxel-centre ties and zero direction components, both walk forms (for
